@@ -1,0 +1,168 @@
+/*
+ * gbm3d.h — C ABI of the MI355X (gfx950) G-BM3D hot path.
+ *
+ * Method: Sanders & Larkin, "New Computational Techniques for a Faster
+ * Variation of BM3D Image Denoising".  Denoising takes only the noisy image
+ * and the noise level (Sec. 1); stage 1 alone gives the basic estimate
+ * (G-BM3D1), both stages give the final estimate (G-BM3D2) (Sec. 1.1).
+ *
+ * Conventions for every entry point:
+ *   - Image pointers are HIP DEVICE pointers to row-major arrays with pitch W
+ *     elements.  Pixel value = u16 / 65535 on the [0, 1] scale; sigma is on
+ *     the same scale.  Float outputs are unclipped float32.
+ *   - Boundary handling is periodic: Z[i, j] = Z[i mod H, j mod W] (Sec. 1.2,
+ *     eq. (1)).
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL = the null stream).  The caller owns every input and output buffer
+ *     and keeps it alive until the stream has passed the work.  A context
+ *     owns its device workspace, grows it on demand (hipMalloc, outside any
+ *     capture) and frees it in gbm3d_destroy.  A context is not thread-safe;
+ *     use one per host thread.  Calls on one context must not overlap on
+ *     different streams (they share the workspace).
+ *   - Arguments are validated on the host before any launch; an invalid call
+ *     returns GBM3D_EINVAL and launches nothing.  Errors from the HIP runtime
+ *     return GBM3D_EHIP.  The text of the last error of a context is
+ *     available from gbm3d_last_error.  A kernel fault surfaces at the
+ *     caller's synchronisation.
+ *   - Supported shapes: patch 8, reference step 3, odd search window in
+ *     [1, 39], group sizes in {2, 4, 8, 16, 32} not above search^2, and
+ *     H, W >= max(8, search) and <= 32768.
+ */
+#ifndef GBM3D_H
+#define GBM3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define GBM3D_OK            0
+#define GBM3D_EINVAL       -1
+#define GBM3D_EUNSUPPORTED -2
+#define GBM3D_ENOMEM       -3
+#define GBM3D_EHIP         -4
+
+/* stage-1 aggregation weights (Sec. 3.1 gives 1/TV; a count of retained
+ * coefficients and unit weights are the alternatives the paper mentions) */
+#define GBM3D_W_TV   0
+#define GBM3D_W_NNZ  1
+#define GBM3D_W_UNIT 2
+
+/* patch-stack transforms */
+#define GBM3D_STACK_BIOR15 0   /* 3-level periodic Mallat bior1.5 (Sec. 5) */
+#define GBM3D_STACK_DCT    1   /* orthonormal 8x8 DCT-II (Sec. 4)           */
+
+typedef struct gbm3d_ctx gbm3d_ctx;
+
+typedef struct {
+  uint32_t struct_size; /* = sizeof(gbm3d_params); guards the ABI            */
+  int32_t patch;        /* N = 8                                            */
+  int32_t step;         /* reference grid step, 3                           */
+  int32_t search;       /* S, odd; displacements |dy|,|dx| <= S/2; 39       */
+  int32_t k_ht;         /* group size of stage 1, 16                        */
+  int32_t k_wiener;     /* group size of stage 2, 32                        */
+  float ht_a, ht_b;     /* tau_l = sigma * (ht_a - ht_b * l) (Sec. 5): 3.6, 0.3 */
+  int32_t ht_weight;    /* GBM3D_W_TV (default) | GBM3D_W_NNZ | GBM3D_W_UNIT */
+  float tv_eps_rel;     /* w = 1 / (TV + tv_eps_rel * sigma * 64 * k_ht); 1e-3 */
+  int32_t keep_dc;      /* 1: the 3-D DC coefficient is never shrunk        */
+} gbm3d_params;
+
+/* One image of a batch (see gbm3d_denoise_batch). */
+typedef struct {
+  const uint16_t* noisy; /* device, H*W                                     */
+  const uint16_t* pilot; /* device, H*W, or NULL to run stage 1 as the pilot */
+  float* out;            /* device, H*W                                     */
+  int32_t H, W;
+  float sigma;
+} gbm3d_image;
+
+/* Fills *p with the defaults above (sets struct_size). */
+void gbm3d_default_params(gbm3d_params* p);
+
+/* Creates a context on HIP device `hip_device` (-1 = the current device).
+ * Returns GBM3D_OK and stores the context in *ctx, or an error code. */
+int gbm3d_create(gbm3d_ctx** ctx, int hip_device);
+
+/* Frees the context and its workspace (synchronises the device first).
+ * NULL is ignored. */
+void gbm3d_destroy(gbm3d_ctx* ctx);
+
+/* Static text for a status code. */
+const char* gbm3d_status_str(int status);
+
+/* Text of the last error reported on ctx ("" if none); valid until the next
+ * call on ctx. */
+const char* gbm3d_last_error(const gbm3d_ctx* ctx);
+
+/* Number of references on the periodic grid: ceil(H/step) * ceil(W/step).
+ * References are ordered row-major: ref = p * ceil(W/step) + q sits at
+ * (step*p, step*q). */
+int64_t gbm3d_n_refs(int H, int W, int step);
+
+/* Host-only validation of the arguments of gbm3d_denoise (image shape, noise
+ * level, parameters; NULL params = defaults).  Needs no device and launches
+ * nothing.  The error text is available from gbm3d_last_error(NULL). */
+int gbm3d_check_args(int H, int W, float sigma, const gbm3d_params* params);
+
+/* Library version string. */
+const char* gbm3d_version(void);
+
+/* Block matching (Sec. 2 eq. dfg, Theorem 1; arg_K min of Sec. 3.1).
+ * img: device u16 [H][W].  idx: device int16 [n_refs][K] receiving, for each
+ * reference, the displacement ranks r = (dy + S/2) * S + (dx + S/2) of its K
+ * matched blocks: slot 0 is the reference itself, slots 1..K-1 the K-1 other
+ * displacements with the smallest (squared distance, rank) keys in ascending
+ * order; distances are exact. */
+int gbm3d_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K,
+                const gbm3d_params* params, int16_t* idx, void* stream);
+
+/* Transform-domain patch stack: for every pixel position (y, x), the 2-D
+ * transform of the periodic 8x8 block with top-left (y, x) of img/65535.
+ * kind: GBM3D_STACK_BIOR15 (Sec. 5; coefficient (u, v) in Mallat layout) or
+ * GBM3D_STACK_DCT (Sec. 4; (u, v) = (row, column) frequency).
+ * out: device float [H*W][64], element ((y*W + x)*64 + u*8 + v). */
+int gbm3d_stack(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int kind,
+                float* out, void* stream);
+
+/* Stage 1 (G-BM3D1): matching with k_ht, bior1.5 x Haar hard thresholding
+ * with tau_l, weighted aggregation (Sec. 3.1, Sec. 5).
+ * noisy: device u16 [H][W]; basic: device float [H][W]. */
+int gbm3d_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
+                const gbm3d_params* params, float* basic, void* stream);
+
+/* Stage 2 (Sec. 4): matching with k_wiener on `pilot`, DCT x Haar empirical
+ * Wiener filter of the noisy groups with the pilot's spectrum, aggregation.
+ * noisy, pilot: device u16 [H][W]; out: device float [H][W]. */
+int gbm3d_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot,
+                 int H, int W, float sigma, const gbm3d_params* params,
+                 float* out, void* stream);
+
+/* Both stages (G-BM3D2): stage 1, pilot Q = floor(clip(basic, 0, 1)*65535
+ * + 1/2), stage 2 with Q.  out: device float [H][W].  basic_out and q_out
+ * are optional (NULL) device outputs of the intermediate estimate. */
+int gbm3d_denoise(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
+                  const gbm3d_params* params, float* out, float* basic_out,
+                  uint16_t* q_out, void* stream);
+
+/* Pilot quantisation: out[i] = floor(clip(in[i], 0, 1) * 65535 + 1/2),
+ * evaluated in double from the float input; NaN -> 0.  Device pointers. */
+int gbm3d_quantize(gbm3d_ctx* ctx, const float* in, uint16_t* out, size_t n, void* stream);
+
+/* Per-kernel timing for benchmarking.  While enabled, the context brackets
+ * every kernel it launches with two HIP events recorded on the launch stream.
+ * gbm3d_timing_read synchronises the pending events and returns, for one
+ * kernel name ("bm", "stack_bior", "stack_dct", "group_ht", "group_wiener",
+ * "reduce"), the summed elapsed milliseconds and the number of launches since
+ * the last reset.  Off by default. */
+int gbm3d_timing_enable(gbm3d_ctx* ctx, int on);
+int gbm3d_timing_read(gbm3d_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
+int gbm3d_timing_reset(gbm3d_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBM3D_H */

@@ -1,0 +1,194 @@
+// Device-side building blocks of the G-BM3D library: transform tables built at
+// compile time from the filter definitions, and wavefront helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbm3d {
+
+constexpr int kPatch = 8;
+constexpr int kStep = 3;
+constexpr int kMaxR = 19;  // largest search half-width (39 x 39 window)
+constexpr int kWave = 64;
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// bior1.5 (Sec. 5): analysis low-pass taps at offsets -4..5 in units of
+// sqrt(2)/256; the synthesis scaling filter is the Haar box.
+// ---------------------------------------------------------------------------
+constexpr int kBiorTap[10] = {3, -3, -22, 22, 128, 128, 22, -22, -3, 3};
+
+struct Mat8 {
+  double m[8][8];
+};
+
+constexpr int pmod(int a, int L) { return ((a % L) + L) % L; }
+
+// One periodic analysis level on length L (even): rows 0..L/2-1 give the
+// low-pass a[n] = sum_i h_i x[2n+i], rows L/2.. the Haar details
+// d[n] = (x[2n+1] - x[2n]) / sqrt(2).
+constexpr Mat8 bior_analysis(int L) {
+  Mat8 A{};
+  for (int n = 0; n < L / 2; ++n) {
+    for (int i = 0; i < 10; ++i) A.m[n][pmod(2 * n + i - 4, L)] += kBiorTap[i] * kSqrt2 / 256.0;
+    A.m[L / 2 + n][2 * n] += -kInvSqrt2;
+    A.m[L / 2 + n][2 * n + 1] += kInvSqrt2;
+  }
+  return A;
+}
+
+// The matching periodic synthesis level (x = S c): a low coefficient spreads
+// as the Haar box over (2n, 2n+1); a detail coefficient spreads as the dual
+// wavelet psi[m] = (-1)^(m+1) h[1-m], m = -4..5 around 2n.
+constexpr Mat8 bior_synthesis(int L) {
+  Mat8 S{};
+  for (int n = 0; n < L / 2; ++n) {
+    S.m[2 * n][n] += kInvSqrt2;
+    S.m[2 * n + 1][n] += kInvSqrt2;
+    for (int m = -4; m <= 5; ++m) {
+      const int t = 1 - m;  // tap offset of h
+      if (t < -4 || t > 5) continue;
+      const double sign = ((m + 1) & 1) ? -1.0 : 1.0;
+      S.m[pmod(2 * n + m, L)][L / 2 + n] += sign * kBiorTap[t + 4] * kSqrt2 / 256.0;
+    }
+  }
+  return S;
+}
+
+// ---------------------------------------------------------------------------
+// Orthonormal DCT-II of length 8 (Sec. 4): C[k][n] = a_k cos(pi (2n+1) k / 16)
+// ---------------------------------------------------------------------------
+constexpr double ccos(double x) {
+  while (x > kPi) x -= 2 * kPi;
+  while (x < -kPi) x += 2 * kPi;
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 40; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr Mat8 dct8() {
+  Mat8 C{};
+  for (int k = 0; k < 8; ++k)
+    for (int n = 0; n < 8; ++n)
+      C.m[k][n] = (k == 0 ? 0.35355339059327376220 : 0.5) * ccos(kPi * (2 * n + 1) * k / 16.0);
+  return C;
+}
+
+constexpr Mat8 transpose8(const Mat8& A) {
+  Mat8 T{};
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) T.m[i][j] = A.m[j][i];
+  return T;
+}
+
+constexpr double cabs(double x) { return x < 0 ? -x : x; }
+
+// max |A S - I| over the leading L x L block
+constexpr double inverse_error(const Mat8& A, const Mat8& S, int L) {
+  double e = 0;
+  for (int i = 0; i < L; ++i)
+    for (int j = 0; j < L; ++j) {
+      double s = 0;
+      for (int k = 0; k < L; ++k) s += A.m[i][k] * S.m[k][j];
+      const double d = cabs(s - (i == j ? 1.0 : 0.0));
+      if (d > e) e = d;
+    }
+  return e;
+}
+
+static_assert(inverse_error(bior_analysis(2), bior_synthesis(2), 2) < 1e-14, "bior L=2");
+static_assert(inverse_error(bior_analysis(4), bior_synthesis(4), 4) < 1e-14, "bior L=4");
+static_assert(inverse_error(bior_analysis(8), bior_synthesis(8), 8) < 1e-14, "bior L=8");
+static_assert(inverse_error(dct8(), transpose8(dct8()), 8) < 1e-14, "dct orthonormal");
+
+// y = M x over the leading L x L block, float arithmetic, zero entries skipped
+template <int L>
+__device__ __forceinline__ void apply_mat(const Mat8& M, const float* x, float* y) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      if (M.m[i][j] != 0.0) acc = fmaf(static_cast<float>(M.m[i][j]), x[j], acc);
+    y[i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Orthonormal full-depth Haar along a group of K registers (K power of two).
+// Forward: at each level, pairs (2j, 2j+1) of the current sums become the
+// sum (x0+x1)/sqrt2 at j and the difference (x0-x1)/sqrt2 at half+j; the
+// group DC ends at index 0.  Inverse undoes the levels in reverse.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void haar_fwd(float* v) {
+  const float s = static_cast<float>(kInvSqrt2);
+#pragma unroll
+  for (int half = K / 2; half >= 1; half /= 2) {
+    float t[K];
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      t[j] = (v[2 * j] + v[2 * j + 1]) * s;
+      t[half + j] = (v[2 * j] - v[2 * j + 1]) * s;
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * half; ++j) v[j] = t[j];
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void haar_inv(float* v) {
+  const float s = static_cast<float>(kInvSqrt2);
+#pragma unroll
+  for (int half = 1; half <= K / 2; half *= 2) {
+    float t[K];
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      t[2 * j] = (v[j] + v[half + j]) * s;
+      t[2 * j + 1] = (v[j] - v[half + j]) * s;
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * half; ++j) v[j] = t[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64)
+// ---------------------------------------------------------------------------
+
+// Orders this wave's LDS accesses: every lane's earlier LDS writes are visible
+// to every lane's later LDS reads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Mallat level of a 2-D bior coefficient c = u*8+v: 1 for the finest
+// details, 3 for the coarsest details and the approximation.
+__device__ __forceinline__ int bior_level(int c) {
+  const int u = c >> 3, v = c & 7;
+  const int m = u > v ? u : v;
+  return m >= 4 ? 1 : (m >= 2 ? 2 : 3);
+}
+
+}  // namespace gbm3d

@@ -1,0 +1,117 @@
+// Transform-domain patch stack: the 2-D transform of the periodic 8x8 block at
+// every pixel position, 64 float coefficients per position (256 B, AoS).
+//   bior1.5: 3-level periodic Mallat decomposition (Sec. 5), each level
+//            applying one analysis step to the rows and columns of the current
+//            low-low block;
+//   DCT:     orthonormal separable 8x8 DCT-II (Sec. 4).
+// A workgroup covers 4 rows x 64 columns of positions.  Each thread
+// transforms one block read from an LDS pixel tile, parks its 64 coefficients
+// in LDS, and the wave then writes its 64 consecutive positions as one
+// contiguous 16 KB run with 16-byte stores.
+#include "common.h"
+#include "kernels.h"
+
+namespace gbm3d {
+
+namespace {
+
+constexpr int kRowsPerWg = 4;
+constexpr int kPixRows = kRowsPerWg + kPatch - 1;  // 11
+constexpr int kPixCols = kWave + kPatch - 1;       // 71
+constexpr int kStagePitch = 65;                    // floats per parked block (odd: conflict-free)
+
+template <int L>
+__device__ __forceinline__ void rows_cols(float (&x)[8][8], const Mat8& M) {
+  // rows: x[a][0..L) <- M x[a][0..L)
+#pragma unroll
+  for (int a = 0; a < L; ++a) {
+    float t[8];
+    apply_mat<L>(M, x[a], t);
+#pragma unroll
+    for (int b = 0; b < L; ++b) x[a][b] = t[b];
+  }
+  // columns
+#pragma unroll
+  for (int b = 0; b < L; ++b) {
+    float c[8], t[8];
+#pragma unroll
+    for (int a = 0; a < L; ++a) c[a] = x[a][b];
+    apply_mat<L>(M, c, t);
+#pragma unroll
+    for (int a = 0; a < L; ++a) x[a][b] = t[a];
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ void forward2d(float (&x)[8][8]) {
+  if constexpr (KIND == 0) {
+    constexpr Mat8 A8 = bior_analysis(8);
+    constexpr Mat8 A4 = bior_analysis(4);
+    constexpr Mat8 A2 = bior_analysis(2);
+    rows_cols<8>(x, A8);
+    rows_cols<4>(x, A4);
+    rows_cols<2>(x, A2);
+  } else {
+    constexpr Mat8 C = dct8();
+    rows_cols<8>(x, C);
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void stack_kernel(const uint16_t* __restrict__ img, int H, int W,
+                                                    float* __restrict__ out) {
+  __shared__ float pix[kPixRows][kPixCols + 1];
+  __shared__ float stage[kRowsPerWg][kWave * kStagePitch];
+  const int y0 = blockIdx.y * kRowsPerWg;
+  const int x0 = blockIdx.x * kWave;
+  const float scale = 1.0f / 65535.0f;
+  for (int i = threadIdx.x; i < kPixRows * kPixCols; i += blockDim.x) {
+    const int r = i / kPixCols, c = i - r * kPixCols;
+    const int y = (y0 + r) % H, x = (x0 + c) % W;
+    pix[r][c] = static_cast<float>(img[static_cast<size_t>(y) * W + x]) * scale;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  float x[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) x[a][b] = pix[w + a][lane + b];
+  forward2d<KIND>(x);
+  float* st = stage[w] + lane * kStagePitch;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) st[a * 8 + b] = x[a][b];
+  wave_lds_sync();
+
+  const int y = y0 + w;
+  if (y >= H) return;
+  const int n_pos = min(kWave, W - x0);             // positions of this row in the tile
+  float4* dst = reinterpret_cast<float4*>(out + (static_cast<size_t>(y) * W + x0) * 64);
+  // 16 rounds; in round i lane l stores float4 g = i*64 + l of the run
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int g = i * kWave + lane;
+    const int blk = g >> 4, c = (g & 15) * 4;
+    if (blk < n_pos) {
+      const float* s = stage[w] + blk * kStagePitch + c;
+      dst[g] = make_float4(s[0], s[1], s[2], s[3]);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stack(const uint16_t* img, int H, int W, int kind, float* out, hipStream_t st) {
+  dim3 grid((W + kWave - 1) / kWave, (H + kRowsPerWg - 1) / kRowsPerWg);
+  if (kind == 0)
+    hipLaunchKernelGGL(stack_kernel<0>, grid, dim3(256), 0, st, img, H, W, out);
+  else
+    hipLaunchKernelGGL(stack_kernel<1>, grid, dim3(256), 0, st, img, H, W, out);
+  return hipGetLastError();
+}
+
+}  // namespace gbm3d

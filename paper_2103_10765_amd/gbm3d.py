@@ -1,0 +1,254 @@
+"""ctypes binding of libgbm3d.so (the C ABI in include/gbm3d.h).
+
+Argument marshalling only: every step of the denoiser runs in the library's
+HIP kernels.  Tensors supply device memory; the current torch stream is passed
+as the HIP stream.  There is no CPU fallback: if the library is missing,
+loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so the library binds to the same HIP runtime as torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgbm3d.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+W_TV, W_NNZ, W_UNIT = 0, 1, 2
+STACK_BIOR15, STACK_DCT = 0, 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("patch", ctypes.c_int32),
+        ("step", ctypes.c_int32),
+        ("search", ctypes.c_int32),
+        ("k_ht", ctypes.c_int32),
+        ("k_wiener", ctypes.c_int32),
+        ("ht_a", ctypes.c_float),
+        ("ht_b", ctypes.c_float),
+        ("ht_weight", ctypes.c_int32),
+        ("tv_eps_rel", ctypes.c_float),
+        ("keep_dc", ctypes.c_int32),
+    ]
+
+
+class GBM3DError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gbm3d status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_F = ctypes.c_float
+
+_SIGNATURES = {
+    "gbm3d_default_params": (None, [ctypes.POINTER(Params)]),
+    "gbm3d_create": (_I, [ctypes.POINTER(_P), _I]),
+    "gbm3d_destroy": (None, [_P]),
+    "gbm3d_status_str": (ctypes.c_char_p, [_I]),
+    "gbm3d_last_error": (ctypes.c_char_p, [_P]),
+    "gbm3d_n_refs": (ctypes.c_int64, [_I, _I, _I]),
+    "gbm3d_check_args": (_I, [_I, _I, _F, ctypes.POINTER(Params)]),
+    "gbm3d_version": (ctypes.c_char_p, []),
+    "gbm3d_match": (_I, [_P, _P, _I, _I, _I, ctypes.POINTER(Params), _P, _P]),
+    "gbm3d_stack": (_I, [_P, _P, _I, _I, _I, _P, _P]),
+    "gbm3d_basic": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P]),
+    "gbm3d_wiener": (_I, [_P, _P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P]),
+    "gbm3d_denoise": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P, _P, _P]),
+    "gbm3d_quantize": (_I, [_P, _P, _P, ctypes.c_size_t, _P]),
+    "gbm3d_timing_enable": (_I, [_P, _I]),
+    "gbm3d_timing_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_int64)]),
+    "gbm3d_timing_reset": (_I, [_P]),
+}
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_2103_10765_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().gbm3d_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def n_refs(H: int, W: int, step: int = 3) -> int:
+    return int(lib().gbm3d_n_refs(H, W, step))
+
+
+def check_args(H: int, W: int, sigma: float, params: Params | None = None) -> int:
+    return int(lib().gbm3d_check_args(H, W, sigma, ctypes.byref(params) if params is not None else None))
+
+
+def last_thread_error() -> str:
+    return lib().gbm3d_last_error(None).decode()
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hw(t: torch.Tensor):
+    if t.dim() != 2:
+        raise ValueError("images are 2-D [H, W]")
+    return int(t.shape[0]), int(t.shape[1])
+
+
+class Context:
+    """One library context (device workspace) on a HIP device."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        s = lib().gbm3d_create(ctypes.byref(h), self.device)
+        if s != OK:
+            raise GBM3DError(s, last_thread_error())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().gbm3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s: int):
+        if s != OK:
+            raise GBM3DError(s, lib().gbm3d_last_error(self._h).decode())
+
+    def _params(self, params):
+        return ctypes.byref(params if params is not None else default_params())
+
+    # -- entry points ------------------------------------------------------
+    def match(self, img: torch.Tensor, K: int, params: Params | None = None, out=None, stream=None):
+        H, W = _hw(img)
+        p = params if params is not None else default_params()
+        n = n_refs(H, W, p.step)
+        if out is None:
+            out = torch.empty((n, K), dtype=torch.int16, device=img.device)
+        self._check(lib().gbm3d_match(self._h, _dev(img, torch.uint16, "img"), H, W, K, ctypes.byref(p),
+                                      _dev(out, torch.int16, "idx"), _stream(stream)))
+        return out
+
+    def stack(self, img: torch.Tensor, kind: int = STACK_BIOR15, out=None, stream=None):
+        H, W = _hw(img)
+        if out is None:
+            out = torch.empty((H * W, 64), dtype=torch.float32, device=img.device)
+        self._check(lib().gbm3d_stack(self._h, _dev(img, torch.uint16, "img"), H, W, kind,
+                                      _dev(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def basic(self, noisy: torch.Tensor, sigma: float, params: Params | None = None, out=None, stream=None):
+        H, W = _hw(noisy)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=noisy.device)
+        self._check(lib().gbm3d_basic(self._h, _dev(noisy, torch.uint16, "noisy"), H, W, float(sigma),
+                                      self._params(params), _dev(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def wiener(self, noisy: torch.Tensor, pilot: torch.Tensor, sigma: float, params: Params | None = None,
+               out=None, stream=None):
+        H, W = _hw(noisy)
+        if tuple(pilot.shape) != (H, W):
+            raise ValueError("pilot shape differs from noisy")
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=noisy.device)
+        self._check(lib().gbm3d_wiener(self._h, _dev(noisy, torch.uint16, "noisy"),
+                                       _dev(pilot, torch.uint16, "pilot"), H, W, float(sigma),
+                                       self._params(params), _dev(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def denoise(self, noisy: torch.Tensor, sigma: float, params: Params | None = None, out=None,
+                basic_out=None, q_out=None, stream=None):
+        H, W = _hw(noisy)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=noisy.device)
+        b = _dev(basic_out, torch.float32, "basic_out") if basic_out is not None else None
+        q = _dev(q_out, torch.uint16, "q_out") if q_out is not None else None
+        self._check(lib().gbm3d_denoise(self._h, _dev(noisy, torch.uint16, "noisy"), H, W, float(sigma),
+                                        self._params(params), _dev(out, torch.float32, "out"), b, q,
+                                        _stream(stream)))
+        return out
+
+    def timing(self, on: bool = True):
+        self._check(lib().gbm3d_timing_enable(self._h, 1 if on else 0))
+
+    def timing_reset(self):
+        self._check(lib().gbm3d_timing_reset(self._h))
+
+    def timing_read(self, kernel: str):
+        """(total milliseconds, launches) of one kernel since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(lib().gbm3d_timing_read(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def quantize(self, x: torch.Tensor, out=None, stream=None):
+        if out is None:
+            out = torch.empty(x.shape, dtype=torch.uint16, device=x.device)
+        self._check(lib().gbm3d_quantize(self._h, _dev(x, torch.float32, "in"), _dev(out, torch.uint16, "out"),
+                                         x.numel(), _stream(stream)))
+        return out
+
+
+_default_ctx: dict[int, Context] = {}
+
+
+def context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def denoise(noisy: torch.Tensor, sigma: float, params: Params | None = None) -> torch.Tensor:
+    """Two-stage G-BM3D of a uint16 CUDA image; returns float32 [H, W]."""
+    return context(noisy.device.index).denoise(noisy, sigma, params)
+
+
+def basic(noisy: torch.Tensor, sigma: float, params: Params | None = None) -> torch.Tensor:
+    """Stage 1 only (basic estimate)."""
+    return context(noisy.device.index).basic(noisy, sigma, params)

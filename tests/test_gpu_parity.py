@@ -1,0 +1,316 @@
+"""GPU parity: the HIP path through the C ABI against the fp64 CPU oracle on
+the same seeded inputs.
+
+Bars: match indices bit-exact (exact integer distances, lower-rank tie rule);
+filtered outputs within max-abs 2e-4 on the [0, 1] scale and PSNR within
+0.01 dB.  For stage 1, pixels covered by a group holding a hard-threshold
+decision within 1e-5 (relative) of tau are excluded from the max-abs check,
+because float32 coefficients may decide those differently; such groups must
+be rare.  Full-size images are checked on sampled references and windows the
+oracle evaluates exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gbm3d_oracle as O
+from paper_2103_10765_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SIG = 25.0 / 255.0
+MAXABS = 2e-4
+PSNR_TOL = 0.01
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    return t
+
+
+@pytest.fixture(scope="module")
+def G(torch):
+    from paper_2103_10765_amd import gbm3d
+    return gbm3d
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def up(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def oparams(G, gp):
+    return O.DEFAULT.with_(search=gp.search, k_ht=gp.k_ht, k_wiener=gp.k_wiener, ht_a=gp.ht_a, ht_b=gp.ht_b)
+
+
+# ---------------------------------------------------------------------------
+# patch stacks
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("shape", [(40, 45), (67, 200), (9, 130)])
+def test_stack_parity(torch, G, ctx, kind, shape):
+    H, W = shape
+    say("stack", kind, shape)
+    _, Z = synth.make_case(H, W, SIG, 31)
+    S = ctx.stack(up(torch, Z), kind).cpu().numpy().reshape(H, W, 8, 8)
+    z = Z.astype(np.float64) / 65535.0
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    P = O._blocks(z, ys.ravel(), xs.ravel(), 8)
+    ref = O.bior2d_forward(P) if kind == 0 else O.dct2d_forward(P)
+    err = np.abs(S.reshape(-1, 8, 8) - ref).max()
+    assert err < 1e-5, err
+
+
+# ---------------------------------------------------------------------------
+# block matching
+# ---------------------------------------------------------------------------
+
+MATCH_CASES = [
+    # (H, W, search, K, seed)
+    (39, 39, 39, 16, 1),
+    (48, 51, 15, 8, 2),
+    (128, 128, 39, 16, 3),
+    (128, 128, 39, 32, 4),
+    (100, 131, 21, 4, 5),
+    (67, 190, 39, 32, 6),
+    (45, 400, 9, 2, 7),
+]
+
+
+@pytest.mark.parametrize("H,W,S,K,seed", MATCH_CASES)
+def test_match_bit_exact(torch, G, ctx, H, W, S, K, seed):
+    say("match", H, W, S, K)
+    _, Z = synth.make_case(H, W, SIG, seed)
+    p = G.default_params(search=S)
+    got = ctx.match(up(torch, Z), K, p).cpu().numpy().astype(np.int64)
+    exp = O.match(Z, K, O.DEFAULT.with_(search=S))
+    bad = np.nonzero((got != exp).any(axis=1))[0]
+    assert bad.size == 0, (bad[:5], got[bad[:2]], exp[bad[:2]])
+
+
+@pytest.mark.parametrize("kind", ["flat", "lowbits", "periodic", "extremes"])
+def test_match_ties(torch, G, ctx, kind):
+    H, W, S, K = 60, 70, 15, 16
+    say("match ties", kind)
+    rng = np.random.default_rng(40)
+    if kind == "flat":
+        Z = np.full((H, W), 777, dtype=np.uint16)
+    elif kind == "lowbits":
+        Z = rng.integers(0, 3, size=(H, W)).astype(np.uint16)
+    elif kind == "periodic":
+        Z = np.tile(rng.integers(0, 65536, size=(5, 7)), (12, 10))[:H, :W].astype(np.uint16)
+    else:
+        Z = (rng.integers(0, 2, size=(H, W)) * 65535).astype(np.uint16)
+    p = G.default_params(search=S)
+    got = ctx.match(up(torch, Z), K, p).cpu().numpy().astype(np.int64)
+    exp = O.match(Z, K, O.DEFAULT.with_(search=S))
+    assert np.array_equal(got, exp)
+
+
+def test_match_full_size_sampled(torch, G, ctx):
+    """512 x 512, search 39, K = 16 and 32: 400 sampled references."""
+    _, Z = synth.single_image_case(512, SIG, 2)
+    ids = np.random.default_rng(0).choice(O.n_refs(512, 512, 3), 400, replace=False)
+    for K in (16, 32):
+        say("match 512 sampled K", K)
+        got = ctx.match(up(torch, Z), K).cpu().numpy().astype(np.int64)[ids]
+        exp = O.match(Z, K, O.DEFAULT, ref_ids=ids)
+        assert np.array_equal(got, exp)
+
+
+def test_match_max_width_sampled(torch, G, ctx):
+    """The widest supported image (W = 32768), 40 rows; sampled references."""
+    H, W = 40, 32768
+    say("match max width")
+    _, Z = synth.make_case(H, W, SIG, 8)
+    ids = np.random.default_rng(1).choice(O.n_refs(H, W, 3), 200, replace=False)
+    got = ctx.match(up(torch, Z), 16).cpu().numpy().astype(np.int64)[ids]
+    exp = O.match(Z, 16, O.DEFAULT, ref_ids=ids)
+    assert np.array_equal(got, exp)
+
+
+# ---------------------------------------------------------------------------
+# stage 1
+# ---------------------------------------------------------------------------
+
+def _check_stage1(Yg, Yo, idx, margin, p, clean=None, ref_ids=None, window=None):
+    H, W = Yg.shape
+    flag = O.flagged_pixels(H, W, idx, margin, p, ref_ids=ref_ids)
+    n_flag_groups = int((margin < 1e-5).sum())
+    if window is not None:
+        rows, cols = window
+        Yg, Yo, flag = Yg[np.ix_(rows, cols)], Yo[np.ix_(rows, cols)], flag[np.ix_(rows, cols)]
+        if clean is not None:
+            clean = clean[np.ix_(rows, cols)]
+    err = np.abs(Yg - Yo)[~flag]
+    assert err.size > 0.5 * Yg.size
+    assert err.max() <= MAXABS, (err.max(), n_flag_groups)
+    if clean is not None:
+        d = abs(O.psnr(Yg, clean) - O.psnr(Yo, clean))
+        assert d <= PSNR_TOL, d
+    return n_flag_groups
+
+
+@pytest.mark.parametrize("H,W,S,sigma,seed", [(128, 128, 39, 25 / 255, 1), (96, 130, 21, 15 / 255, 9),
+                                              (64, 64, 39, 50 / 255, 10), (39, 41, 39, 25 / 255, 11)])
+def test_basic_parity(torch, G, ctx, H, W, S, sigma, seed):
+    say("basic", H, W, S, sigma)
+    clean, Z = synth.make_case(H, W, sigma, seed)
+    gp = G.default_params(search=S)
+    p = oparams(G, gp)
+    Yg = ctx.basic(up(torch, Z), sigma, gp).cpu().numpy().astype(np.float64)
+    Yo, (idx, margin, _, _) = O.basic_estimate(Z, sigma, p, return_parts=True)
+    n_flag = _check_stage1(Yg, Yo, idx, margin, p, clean)
+    assert n_flag <= max(1, 1e-3 * O.n_refs(H, W, 3))
+
+
+@pytest.mark.parametrize("weight", [1, 2])
+def test_basic_weight_variants(torch, G, ctx, weight):
+    H, W = 60, 66
+    clean, Z = synth.make_case(H, W, SIG, 12)
+    gp = G.default_params(search=15, ht_weight=weight)
+    p = oparams(G, gp).with_(ht_weight={1: "nnz", 2: "unit"}[weight])
+    Yg = ctx.basic(up(torch, Z), SIG, gp).cpu().numpy().astype(np.float64)
+    Yo, (idx, margin, _, _) = O.basic_estimate(Z, SIG, p, return_parts=True)
+    _check_stage1(Yg, Yo, idx, margin, p, clean)
+
+
+def test_basic_zero_threshold_identity(torch, G, ctx):
+    _, Z = synth.make_case(70, 80, SIG, 13)
+    gp = G.default_params(search=21, ht_a=0.0, ht_b=0.0)
+    Yg = ctx.basic(up(torch, Z), SIG, gp).cpu().numpy()
+    assert np.abs(Yg - Z / 65535.0).max() < 1e-5
+
+
+def test_basic_constant_image(torch, G, ctx):
+    Z = np.full((50, 61), 40000, dtype=np.uint16)
+    Yg = ctx.basic(up(torch, Z), SIG).cpu().numpy()
+    Yw = ctx.wiener(up(torch, Z), up(torch, Z), SIG).cpu().numpy()
+    assert np.abs(Yg - 40000 / 65535.0).max() < 2e-6
+    assert np.abs(Yw - 40000 / 65535.0).max() < 2e-6
+
+
+def _windows(H, W, h, w):
+    # interior, top-left corner (wraps) and bottom-right corner (wraps)
+    return [(H // 2 - h // 2, W // 3, h, w), (H - h // 2, W - w // 2, h, w), (5, W - 7, h, w)]
+
+
+def test_basic_full_size_windows(torch, G, ctx):
+    """512 x 512 at sigma 25/255: three 24 x 24 windows evaluated exactly by the oracle."""
+    clean, Z = synth.single_image_case(512, SIG, 2)
+    Yg = ctx.basic(up(torch, Z), SIG).cpu().numpy().astype(np.float64)
+    p = O.DEFAULT
+    for (y0, x0, h, w) in _windows(512, 512, 24, 24):
+        say("basic 512 window", y0, x0)
+        ids = O.refs_for_window(512, 512, p, y0, x0, h, w)
+        Yo, (idx, margin, _, _) = O.basic_estimate(Z, SIG, p, ref_ids=ids, return_parts=True)
+        rows, cols = (y0 + np.arange(h)) % 512, (x0 + np.arange(w)) % 512
+        _check_stage1(Yg, Yo, idx, margin, p, ref_ids=ids, window=(rows, cols))
+
+
+# ---------------------------------------------------------------------------
+# stage 2 (pilot given as an input)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("H,W,S,sigma,seed", [(128, 128, 39, 25 / 255, 1), (80, 99, 15, 50 / 255, 14),
+                                              (39, 39, 39, 15 / 255, 15)])
+def test_wiener_parity(torch, G, ctx, H, W, S, sigma, seed):
+    say("wiener", H, W, S, sigma)
+    clean, Z = synth.make_case(H, W, sigma, seed)
+    gp = G.default_params(search=S)
+    p = oparams(G, gp)
+    pilot = O.quantize(O.basic_estimate(Z, sigma, p))          # the oracle's own pilot
+    Yg = ctx.wiener(up(torch, Z), up(torch, pilot), sigma, gp).cpu().numpy().astype(np.float64)
+    Yo = O.wiener_estimate(Z, pilot, sigma, p)
+    assert np.abs(Yg - Yo).max() <= MAXABS
+    assert abs(O.psnr(Yg, clean) - O.psnr(Yo, clean)) <= PSNR_TOL
+
+
+def test_wiener_full_size_windows(torch, G, ctx):
+    """512 x 512: pilot = the clean image quantised (an input both sides take)."""
+    clean, Z = synth.single_image_case(512, SIG, 2)
+    pilot = synth.to_u16(clean)
+    Yg = ctx.wiener(up(torch, Z), up(torch, pilot), SIG).cpu().numpy().astype(np.float64)
+    for (y0, x0, h, w) in _windows(512, 512, 20, 20):
+        say("wiener 512 window", y0, x0)
+        ids = O.refs_for_window(512, 512, O.DEFAULT, y0, x0, h, w)
+        Yo = O.wiener_estimate(Z, pilot, SIG, O.DEFAULT, ref_ids=ids)
+        rows, cols = (y0 + np.arange(h)) % 512, (x0 + np.arange(w)) % 512
+        assert np.abs(Yg[np.ix_(rows, cols)] - Yo[np.ix_(rows, cols)]).max() <= MAXABS
+
+
+# ---------------------------------------------------------------------------
+# both stages, quantisation
+# ---------------------------------------------------------------------------
+
+def test_denoise_end_to_end(torch, G, ctx):
+    say("denoise 128")
+    clean, Z = synth.make_case(128, 128, SIG, 1)
+    Zt = up(torch, Z)
+    basic = torch.empty((128, 128), dtype=torch.float32, device="cuda")
+    q = torch.empty((128, 128), dtype=torch.uint16, device="cuda")
+    Yg = ctx.denoise(Zt, SIG, basic_out=basic, q_out=q).cpu().numpy().astype(np.float64)
+    Y, Yb, Q = O.denoise(Z, SIG)
+    assert abs(O.psnr(Yg, clean) - O.psnr(Y, clean)) <= PSNR_TOL
+    # the intermediate outputs are the stage-1 call's and its quantisation
+    b2 = ctx.basic(Zt, SIG).cpu().numpy()
+    assert np.abs(basic.cpu().numpy() - b2).max() < 1e-6
+    assert np.array_equal(q.cpu().numpy(), O.quantize(basic.cpu().numpy().astype(np.float64)))
+    # stage 2 from the GPU's own pilot equals the Wiener call with that pilot
+    Yw = ctx.wiener(Zt, q, SIG).cpu().numpy()
+    assert np.abs(Yw - Yg).max() < 1e-6
+    # the two stages improve on each other
+    assert O.psnr(Yg, clean) > O.psnr(basic.cpu().numpy(), clean) > O.psnr(Z / 65535.0, clean)
+
+
+def test_quantize_bit_exact(torch, G, ctx):
+    rng = np.random.default_rng(50)
+    k = rng.integers(0, 65536, size=4000)
+    x = np.concatenate([(k + 0.5) / 65535.0, k / 65535.0, rng.uniform(-0.5, 1.5, 4000),
+                        [np.nan, -0.0, 0.0, 1.0, np.inf, -np.inf]]).astype(np.float32)
+    got = ctx.quantize(up(torch, x)).cpu().numpy()
+    exp = O.quantize(x.astype(np.float64))
+    exp[np.isinf(x) & (x > 0)] = 65535
+    assert np.array_equal(got, exp)
+
+
+def test_invalid_arguments_launch_nothing(torch, G, ctx):
+    Z = up(torch, np.zeros((64, 64), dtype=np.uint16))
+    out = torch.full((64, 64), -7.0, device="cuda")
+    for kw, sigma in [(dict(search=40), SIG), (dict(k_ht=3), SIG), ({}, 0.0), (dict(step=2), SIG)]:
+        with pytest.raises(G.GBM3DError) as e:
+            ctx.basic(Z, sigma, G.default_params(**kw), out=out)
+        assert e.value.status in (G.EINVAL, G.EUNSUPPORTED)
+    torch.cuda.synchronize()
+    assert (out == -7.0).all()
+    small = up(torch, np.zeros((20, 64), dtype=np.uint16))
+    with pytest.raises(G.GBM3DError):
+        ctx.match(small, 16)
+
+
+def test_side_stream_and_repeat(torch, G, ctx):
+    _, Z = synth.make_case(100, 100, SIG, 16)
+    Zt = up(torch, Z)
+    a = ctx.denoise(Zt, SIG)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = ctx.denoise(Zt, SIG, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert np.abs(a.cpu().numpy() - b.cpu().numpy()).max() < 1e-6
