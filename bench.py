@@ -32,7 +32,7 @@ def algorithmic_work(H, W, search, k1, k2):
     FX = 3 * (TPX - 1) + 8 + 2 * R
     FXP = FX + ((8 - FX) % 32 + 32) % 32
     n_tiles = ((nRy + TPY - 1) // TPY) * ((nRx + TPX - 1) // TPX)
-    partial_bytes = n_tiles * 2 * FY * FXP * 4
+    partial_bytes = n_tiles * 2 * FY * FXP * 8  # 64-bit fixed-point sums
     S2 = search * search
     return {
         # one difference + one fused square-accumulate per (pixel, displacement)

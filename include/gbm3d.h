@@ -66,8 +66,11 @@ typedef struct {
   int32_t k_wiener;     /* group size of stage 2, 32                        */
   float ht_a, ht_b;     /* tau_l = sigma * (ht_a - ht_b * l) (Sec. 5): 3.6, 0.3 */
   int32_t ht_weight;    /* GBM3D_W_TV (default) | GBM3D_W_NNZ | GBM3D_W_UNIT */
-  float tv_eps_rel;     /* w = 1 / (TV + tv_eps_rel * sigma * 64 * k_ht); 1e-3 */
+  float tv_eps_rel;     /* > 0: w = 1 / (TV + tv_eps_rel * sigma * 64 * k_ht); 1e-3 */
   int32_t keep_dc;      /* 1: the 3-D DC coefficient is never shrunk        */
+  /* launch tuning (results do not depend on it) */
+  int32_t bm_split;     /* block matching: parts of the displacement rows per
+                           reference row, 1 | 2 | 4; 0 = chosen by image size */
 } gbm3d_params;
 
 /* One image of a batch (see gbm3d_denoise_batch). */

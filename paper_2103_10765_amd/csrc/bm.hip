@@ -1,22 +1,27 @@
 // Block matching (Sec. 2, eq. dfg; arg_K min of Sec. 3.1), shift-wise.
 //
-// For one reference row p and 62 consecutive reference columns q, a workgroup
-// of four waves scans the search window: wave w takes a quarter of the
-// displacement rows dy, and for each displacement (dy, dx) every lane forms
-// the squared differences of its own three pixel columns [3q, 3q+3) of the
-// reference block against the displaced block, summed over the 8 block rows.
-// Because references sit 3 pixels apart, a block's 8 columns are the 3
-// columns of its own lane, the 3 of the next lane and the first 2 of the lane
-// after that: the box filter of the squared-difference map at the reference
-// position is completed with two wavefront shuffles.  All arithmetic is on
-// integers held in float64, so distances are exact (< 2^38).
+// A wave holds 64 consecutive references of one reference row (62 produce
+// output, the last two only contribute columns).  For every displacement
+// (dy, dx) of the search window each lane forms the squared differences of its
+// own three pixel columns [3q, 3q+3) of the reference block against the
+// displaced block, summed over the 8 block rows.  Because references sit 3
+// pixels apart, a block's 8 columns are the 3 columns of its own lane, the 3
+// of the next lane and the first 2 of the lane after that: the box filter of
+// the squared-difference map at the reference position is completed with two
+// DPP wave shifts.  Values are integers held in float64, so every distance is
+// exact (< 2^38) and keys dist * 2048 + rank order candidates by (distance,
+// rank) exactly.
 //
-// Each lane keeps the K-1 best keys (distance * 2048 + rank) of its
-// reference in a sorted register list.  Candidates that beat the current
-// worst key are appended to a small per-lane LDS buffer; the buffer is merged
-// into the list when some lane fills it, so the insertion network runs once
-// per batch instead of on almost every displacement.  At the end the four
-// waves' lists are merged through LDS and the ranks are written out.
+// Three consecutive dx are evaluated per iteration as independent chains, with
+// the next columns prefetched from LDS while they compute.  Each lane keeps
+// the K-1 best keys of its reference in a sorted register list; candidates
+// below the current worst key are appended to a per-lane LDS buffer and merged
+// into the list when some lane's buffer is nearly full.
+//
+// A workgroup of four waves covers RPW reference rows x SPLIT parts of the
+// displacement rows (RPW * SPLIT = 4) and shares one LDS image tile with the
+// search halo.  With SPLIT > 1 the partial lists of a row are merged through
+// LDS at the end.
 #include "common.h"
 #include "kernels.h"
 
@@ -24,11 +29,16 @@ namespace gbm3d {
 
 namespace {
 
-constexpr int kLanesOut = 62;                       // references per workgroup (lanes 62, 63 only help)
-constexpr int kTileRows = kPatch + 2 * kMaxR;       // 46
-constexpr int kTileCols = 3 * kWave + 2 + 2 * kMaxR + 4;  // 236 (slack for the 3-column unroll)
-constexpr int kBuf = 8;                             // buffered candidates per lane
+constexpr int kLanesOut = 62;
+constexpr int kTileCols = 3 * kWave + 2 + 2 * kMaxR + 8;  // 238: columns 3q0-R .. (slack for prefetch)
+constexpr int kBuf = 12;                                   // buffered candidates per lane
+constexpr int kFlushAt = kBuf - 3;                         // an iteration appends at most 3
 constexpr double kInf = __builtin_huge_val();
+
+template <int RPW>
+struct TileShape {
+  static constexpr int rows = kStep * (RPW - 1) + kPatch + 2 * kMaxR;
+};
 
 template <int L>
 __device__ __forceinline__ void insert_sorted(double (&list)[L], double key) {
@@ -38,46 +48,59 @@ __device__ __forceinline__ void insert_sorted(double (&list)[L], double key) {
   list[0] = fmin(key, list[0]);
 }
 
-template <int K>
+// value of lane + 1 (DPP wave shift; lane 63 keeps its own value)
+__device__ __forceinline__ double from_next_lane(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int nlo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  const int nhi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __hiloint2double(nhi, nlo);
+}
+
+template <int K, int RPW>
 struct BmSmem {
   static constexpr int L = K - 1;
-  static constexpr size_t kScan = sizeof(float) * kTileRows * kTileCols + sizeof(double) * 4 * kBuf * kWave;
+  static constexpr size_t kTile = sizeof(float) * TileShape<RPW>::rows * kTileCols;
+  static constexpr size_t kScan = kTile + sizeof(double) * 4 * kBuf * kWave;
   static constexpr size_t kMerge = sizeof(double) * 4 * (L > 0 ? L : 1) * kWave;
   static constexpr size_t bytes = kScan > kMerge ? kScan : kMerge;
 };
 
-template <int K>
+template <int K, int RPW, int SPLIT>
 __global__ __launch_bounds__(256, 2) void bm_kernel(const uint16_t* __restrict__ img, int H, int W, int R,
                                                     int nRy, int nRx, int16_t* __restrict__ idx) {
+  static_assert(RPW * SPLIT == 4, "four waves per workgroup");
   constexpr int L = K - 1;
-  __shared__ __align__(16) unsigned char smem[BmSmem<K>::bytes];
+  constexpr int kRowsMax = TileShape<RPW>::rows;
+  __shared__ __align__(16) unsigned char smem[BmSmem<K, RPW>::bytes];
   float(*tile)[kTileCols] = reinterpret_cast<float(*)[kTileCols]>(smem);
-  double* buf = reinterpret_cast<double*>(smem + sizeof(float) * kTileRows * kTileCols);
+  double* buf = reinterpret_cast<double*>(smem + BmSmem<K, RPW>::kTile);
 
   const int S = 2 * R + 1;
-  const int p = blockIdx.y;
-  const int q0 = blockIdx.x * kLanesOut;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
+  const int row_in_wg = wave / SPLIT, part = wave % SPLIT;
+  const int p0 = blockIdx.y * RPW;
+  const int p = p0 + row_in_wg;
+  const int q0 = blockIdx.x * kLanesOut;
 
-  // Image tile with the search halo, periodic: rows 3p-R .. 3p+7+R,
-  // columns 3q0-R .. 3q0+191+R (+ slack).
-  const int y0 = kStep * p - R;
+  // LDS image tile, periodic: rows 3p0-R .. 3(p0+RPW-1)+7+R, columns 3q0-R ..
+  const int y0 = kStep * p0 - R;
   const int x0 = kStep * q0 - R;
-  const int rows = kPatch + 2 * R;
+  const int rows = kStep * (RPW - 1) + kPatch + 2 * R;
   for (int i = threadIdx.x; i < rows * kTileCols; i += blockDim.x) {
     const int r = i / kTileCols, c = i - r * kTileCols;
     const int y = pmod(y0 + r, H), x = pmod(x0 + c, W);
     tile[r][c] = static_cast<float>(img[static_cast<size_t>(y) * W + x]);
   }
+  (void)kRowsMax;
   __syncthreads();
 
-  // this lane's three reference columns, all 8 rows
+  const int trow = kStep * row_in_wg;  // this wave's first tile row for dy = -R
   double rf[kPatch][3];
 #pragma unroll
   for (int a = 0; a < kPatch; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) rf[a][b] = static_cast<double>(tile[R + a][R + 3 * lane + b]);
+    for (int b = 0; b < 3; ++b) rf[a][b] = static_cast<double>(tile[trow + R + a][R + 3 * lane + b]);
 
   double list[L];
 #pragma unroll
@@ -97,25 +120,21 @@ __global__ __launch_bounds__(256, 2) void bm_kernel(const uint16_t* __restrict__
     thr = list[L - 1];
   };
 
-  const int dy_begin = (wave * S) / 4, dy_end = ((wave + 1) * S) / 4;
-  const int S3 = ((S + 2) / 3) * 3;  // dx iterations, a multiple of 3 (extra ones are masked)
+  const int dy_begin = (part * S) / SPLIT, dy_end = ((part + 1) * S) / SPLIT;
+  const int nIter = (S + 5) / 6;  // 6 displacements per unrolled iteration (extra ones masked)
   const int r_center = R * S + R;
 
   for (int dyi = dy_begin; dyi < dy_end; ++dyi) {
-    // candidate block rows start at tile row (R + dy) = dyi; columns at 3*lane + dxi
-    const float* base = &tile[dyi][3 * lane];
-    double c0[kPatch], c1[kPatch], c2[kPatch];
-#pragma unroll
-    for (int a = 0; a < kPatch; ++a) {
-      c0[a] = static_cast<double>(base[a * kTileCols + 0]);
-      c1[a] = static_cast<double>(base[a * kTileCols + 1]);
-      c2[a] = static_cast<double>(base[a * kTileCols + 2]);
-    }
+    const float* base = &tile[trow + dyi][3 * lane];
     const int rank_row = dyi * S;
-
-    // one displacement: columns (ca, cb, cc) hold displaced columns dxi, dxi+1, dxi+2
-    auto step = [&](const double* ca, const double* cb, const double* cc, int dxi) {
-      double a2 = 0.0, a1 = 0.0;
+    auto load = [&](double* c, int col) {
+#pragma unroll
+      for (int a = 0; a < kPatch; ++a) c[a] = static_cast<double>(base[a * kTileCols + col]);
+    };
+    // partial sums of one displacement: (cols 0..1, col 2) of this lane
+    auto partial = [&](const double* ca, const double* cb, const double* cc, double& a2, double& a1) {
+      a2 = 0.0;
+      a1 = 0.0;
 #pragma unroll
       for (int a = 0; a < kPatch; ++a) {
         const double d0 = rf[a][0] - ca[a];
@@ -125,8 +144,12 @@ __global__ __launch_bounds__(256, 2) void bm_kernel(const uint16_t* __restrict__
         a2 = fma(d1, d1, a2);
         a1 = fma(d2, d2, a1);
       }
+    };
+    auto finish = [&](double a2, double a1, int dxi) {
       const double s3 = a2 + a1;
-      const double dist = s3 + __shfl_down(s3, 1, kWave) + __shfl_down(a2, 2, kWave);
+      // dist(l) = s3(l) + s3(l+1) + a2(l+2) = s3(l) + X(l+1), X = s3 + a2(l+1)
+      const double x = s3 + from_next_lane(a2);
+      const double dist = s3 + from_next_lane(x);
       const int rank = rank_row + dxi;
       double key = fma(dist, 2048.0, static_cast<double>(rank));
       if (dxi >= S || rank == r_center) key = kInf;
@@ -134,69 +157,112 @@ __global__ __launch_bounds__(256, 2) void bm_kernel(const uint16_t* __restrict__
         mybuf[cnt * kWave] = key;
         ++cnt;
       }
-      if (__any(cnt == kBuf)) flush();
     };
-    auto reload = [&](double* c, int col) {
-#pragma unroll
-      for (int a = 0; a < kPatch; ++a) c[a] = static_cast<double>(base[a * kTileCols + col]);
+    // three displacements dxi, dxi+1, dxi+2 from columns (c0 c1 c2 n0 n1); n2 is prefetched
+    auto iter3 = [&](const double* c0, const double* c1, const double* c2, double* n0, double* n1, double* n2,
+                     int dxi) {
+      load(n0, dxi + 3);
+      load(n1, dxi + 4);
+      load(n2, dxi + 5);
+      double a2a, a1a, a2b, a1b, a2c, a1c;
+      partial(c0, c1, c2, a2a, a1a);
+      partial(c1, c2, n0, a2b, a1b);
+      partial(c2, n0, n1, a2c, a1c);
+      finish(a2a, a1a, dxi);
+      finish(a2b, a1b, dxi + 1);
+      finish(a2c, a1c, dxi + 2);
+      if (__any(cnt > kFlushAt)) flush();
     };
 
-    for (int dxi = 0; dxi < S3; dxi += 3) {
-      step(c0, c1, c2, dxi);
-      reload(c0, dxi + 3);
-      step(c1, c2, c0, dxi + 1);
-      reload(c1, dxi + 4);
-      step(c2, c0, c1, dxi + 2);
-      reload(c2, dxi + 5);
+    double A0[kPatch], A1[kPatch], A2[kPatch], B0[kPatch], B1[kPatch], B2[kPatch];
+    load(A0, 0);
+    load(A1, 1);
+    load(A2, 2);
+    for (int it = 0; it < nIter; ++it) {
+      const int dxi = 6 * it;
+      iter3(A0, A1, A2, B0, B1, B2, dxi);
+      iter3(B0, B1, B2, A0, A1, A2, dxi + 3);
     }
   }
   flush();
 
-  // merge the four waves' lists: lists[w][i][lane]
   __syncthreads();
   double* lists = reinterpret_cast<double*>(smem);
-#pragma unroll
-  for (int i = 0; i < L; ++i) lists[(wave * L + i) * kWave + lane] = list[i];
-  __syncthreads();
-  if (wave != 0) return;
   const int q = q0 + lane;
-  const bool valid = lane < kLanesOut && q < nRx;
+  const bool valid = lane < kLanesOut && q < nRx && p < nRy;
   int16_t* out = idx + (static_cast<size_t>(p) * nRx + q) * K;
-  if (valid) out[0] = static_cast<int16_t>(r_center);
-  int ptr0 = 0, ptr1 = 0, ptr2 = 0, ptr3 = 0;
-  for (int o = 0; o < L; ++o) {
-    const double h0 = ptr0 < L ? lists[(0 * L + ptr0) * kWave + lane] : kInf;
-    const double h1 = ptr1 < L ? lists[(1 * L + ptr1) * kWave + lane] : kInf;
-    const double h2 = ptr2 < L ? lists[(2 * L + ptr2) * kWave + lane] : kInf;
-    const double h3 = ptr3 < L ? lists[(3 * L + ptr3) * kWave + lane] : kInf;
-    const double m01 = fmin(h0, h1), m23 = fmin(h2, h3);
-    const double m = fmin(m01, m23);
-    if (m == h0) ++ptr0;
-    else if (m == h1) ++ptr1;
-    else if (m == h2) ++ptr2;
-    else ++ptr3;
-    const double rank = m - 2048.0 * floor(m * (1.0 / 2048.0));
-    if (valid) out[1 + o] = static_cast<int16_t>(rank);
+  if constexpr (SPLIT == 1) {
+    if (valid) {
+      out[0] = static_cast<int16_t>(r_center);
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const double m = list[i];
+        out[1 + i] = static_cast<int16_t>(m - 2048.0 * floor(m * (1.0 / 2048.0)));
+      }
+    }
+  } else {
+    // lists[w][i][lane]; the first wave of each row merges its row's SPLIT lists
+#pragma unroll
+    for (int i = 0; i < L; ++i) lists[(wave * L + i) * kWave + lane] = list[i];
+    __syncthreads();
+    if (part != 0) return;
+    const double* ls = lists + static_cast<size_t>(wave) * L * kWave + lane;
+    int ptr[SPLIT];
+#pragma unroll
+    for (int s = 0; s < SPLIT; ++s) ptr[s] = 0;
+    if (valid) out[0] = static_cast<int16_t>(r_center);
+    for (int o = 0; o < L; ++o) {
+      double m = kInf;
+      int best = 0;
+#pragma unroll
+      for (int s = 0; s < SPLIT; ++s) {
+        const double h = ptr[s] < L ? ls[(s * L + ptr[s]) * kWave] : kInf;
+        if (h < m) {
+          m = h;
+          best = s;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < SPLIT; ++s) ptr[s] += (s == best) ? 1 : 0;
+      if (valid) out[1 + o] = static_cast<int16_t>(m - 2048.0 * floor(m * (1.0 / 2048.0)));
+    }
   }
 }
 
 }  // namespace
 
-template <int K>
-static hipError_t launch_bm_k(const uint16_t* img, int H, int W, int R, int16_t* idx, hipStream_t st) {
+template <int K, int RPW, int SPLIT>
+static hipError_t launch_bm_shape(const uint16_t* img, int H, int W, int R, int16_t* idx, hipStream_t st) {
   const int nRy = (H + kStep - 1) / kStep, nRx = (W + kStep - 1) / kStep;
-  dim3 grid((nRx + kLanesOut - 1) / kLanesOut, nRy);
-  hipLaunchKernelGGL(bm_kernel<K>, grid, dim3(256), 0, st, img, H, W, R, nRy, nRx, idx);
+  dim3 grid((nRx + kLanesOut - 1) / kLanesOut, (nRy + RPW - 1) / RPW);
+  hipLaunchKernelGGL((bm_kernel<K, RPW, SPLIT>), grid, dim3(256), 0, st, img, H, W, R, nRy, nRx, idx);
   return hipGetLastError();
 }
 
-hipError_t launch_bm(const uint16_t* img, int H, int W, int R, int K, int16_t* idx, hipStream_t st) {
+// Workgroup shape: split the displacement rows only when the image has too
+// few reference rows to give every SIMD a couple of waves.
+template <int K>
+static hipError_t launch_bm_k(const uint16_t* img, int H, int W, int R, int split, int16_t* idx, hipStream_t st) {
+  if (split <= 0) {
+    const long nRy = (H + kStep - 1) / kStep, nRx = (W + kStep - 1) / kStep;
+    const long waves1 = nRy * ((nRx + kLanesOut - 1) / kLanesOut);  // waves with no split
+    split = waves1 >= 2048 ? 1 : (waves1 >= 1024 ? 2 : 4);
+  }
+  switch (split) {
+    case 1: return launch_bm_shape<K, 4, 1>(img, H, W, R, idx, st);
+    case 2: return launch_bm_shape<K, 2, 2>(img, H, W, R, idx, st);
+    case 4: return launch_bm_shape<K, 1, 4>(img, H, W, R, idx, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bm(const uint16_t* img, int H, int W, int R, int K, int16_t* idx, hipStream_t st, int split) {
   switch (K) {
-    case 2: return launch_bm_k<2>(img, H, W, R, idx, st);
-    case 4: return launch_bm_k<4>(img, H, W, R, idx, st);
-    case 8: return launch_bm_k<8>(img, H, W, R, idx, st);
-    case 16: return launch_bm_k<16>(img, H, W, R, idx, st);
-    case 32: return launch_bm_k<32>(img, H, W, R, idx, st);
+    case 2: return launch_bm_k<2>(img, H, W, R, split, idx, st);
+    case 4: return launch_bm_k<4>(img, H, W, R, split, idx, st);
+    case 8: return launch_bm_k<8>(img, H, W, R, split, idx, st);
+    case 16: return launch_bm_k<16>(img, H, W, R, split, idx, st);
+    case 32: return launch_bm_k<32>(img, H, W, R, split, idx, st);
     default: return hipErrorInvalidValue;
   }
 }

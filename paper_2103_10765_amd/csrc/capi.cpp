@@ -103,6 +103,8 @@ int check_shape(gbm3d_ctx* ctx, int H, int W, const gbm3d_params& p) {
   if (p.step != 3) return fail(ctx, GBM3D_EUNSUPPORTED, "step %d unsupported (only 3)", p.step);
   if (p.search < 1 || p.search > 39 || p.search % 2 == 0)
     return fail(ctx, GBM3D_EINVAL, "search %d must be odd and in [1, 39]", p.search);
+  if (p.bm_split != 0 && p.bm_split != 1 && p.bm_split != 2 && p.bm_split != 4)
+    return fail(ctx, GBM3D_EINVAL, "bm_split %d must be 0, 1, 2 or 4", p.bm_split);
   const int lo = p.search > 8 ? p.search : 8;
   if (H < lo || W < lo || H > 32768 || W > 32768)
     return fail(ctx, GBM3D_EINVAL, "image %dx%d outside [%d, 32768]", H, W, lo);
@@ -124,8 +126,8 @@ int check_ht(gbm3d_ctx* ctx, const gbm3d_params& p) {
   if (!std::isfinite(p.ht_a) || !std::isfinite(p.ht_b)) return fail(ctx, GBM3D_EINVAL, "ht_a/ht_b must be finite");
   if (p.ht_weight < GBM3D_W_TV || p.ht_weight > GBM3D_W_UNIT)
     return fail(ctx, GBM3D_EINVAL, "ht_weight %d unknown", p.ht_weight);
-  if (!(p.tv_eps_rel >= 0.0f) || !std::isfinite(p.tv_eps_rel))
-    return fail(ctx, GBM3D_EINVAL, "tv_eps_rel must be >= 0 and finite");
+  if (!(p.tv_eps_rel > 0.0f) || !std::isfinite(p.tv_eps_rel))
+    return fail(ctx, GBM3D_EINVAL, "tv_eps_rel must be > 0 and finite");
   return GBM3D_OK;
 }
 
@@ -183,12 +185,12 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
   const int R = p.search / 2;
   CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
   CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_ht * sizeof(int16_t), "idx"));
-  CHECK(ensure(ctx, ctx->partials, gbm3d::partials_floats(H, W, R) * sizeof(float), "partials"));
+  CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
   int16_t* idx = static_cast<int16_t*>(ctx->idx.p);
   float* stack = static_cast<float*>(ctx->stack_a.p);
-  float* part = static_cast<float*>(ctx->partials.p);
+  void* part = ctx->partials.p;
   const float eps = p.tv_eps_rel * sigma * 64.0f * static_cast<float>(p.k_ht);
-  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(noisy, H, W, R, p.k_ht, idx, st); }),
+  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(noisy, H, W, R, p.k_ht, idx, st, p.bm_split); }),
           "block matching launch");
   HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(noisy, H, W, GBM3D_STACK_BIOR15, stack, st); }),
           "stack launch");
@@ -208,12 +210,12 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
   CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
   CHECK(ensure(ctx, ctx->stack_b, stack_bytes(H, W), "pilot stack"));
   CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_wiener * sizeof(int16_t), "idx"));
-  CHECK(ensure(ctx, ctx->partials, gbm3d::partials_floats(H, W, R) * sizeof(float), "partials"));
+  CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
   int16_t* idx = static_cast<int16_t*>(ctx->idx.p);
   float* sn = static_cast<float*>(ctx->stack_a.p);
   float* sp = static_cast<float*>(ctx->stack_b.p);
-  float* part = static_cast<float*>(ctx->partials.p);
-  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(pilot, H, W, R, p.k_wiener, idx, st); }),
+  void* part = ctx->partials.p;
+  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(pilot, H, W, R, p.k_wiener, idx, st, p.bm_split); }),
           "block matching launch");
   HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(noisy, H, W, GBM3D_STACK_DCT, sn, st); }),
           "stack launch");
@@ -246,6 +248,7 @@ void gbm3d_default_params(gbm3d_params* p) {
   p->ht_weight = GBM3D_W_TV;
   p->tv_eps_rel = 1e-3f;
   p->keep_dc = 1;
+  p->bm_split = 0;
 }
 
 int gbm3d_create(gbm3d_ctx** out, int hip_device) {
@@ -314,7 +317,7 @@ int gbm3d_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, const 
   CHECK(check_k(ctx, K, p, "K"));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
-  HIP_TRY(ctx, gbm3d::launch_bm(img, H, W, p.search / 2, K, idx, static_cast<hipStream_t>(stream)),
+  HIP_TRY(ctx, gbm3d::launch_bm(img, H, W, p.search / 2, K, idx, static_cast<hipStream_t>(stream), p.bm_split),
           "block matching launch");
   return GBM3D_OK;
 }

@@ -121,6 +121,49 @@ __device__ __forceinline__ void apply_mat(const Mat8& M, const float* x, float* 
   }
 }
 
+// 8-point DCT-II and its inverse by the even/odd symmetry of the basis,
+// C[k][7-n] = (-1)^k C[k][n]: 40 operations instead of 64.
+__device__ __forceinline__ void dct8_fwd(const float* x, float* y) {
+  constexpr Mat8 C = dct8();
+  float s[4], d[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    s[n] = x[n] + x[7 - n];
+    d[n] = x[n] - x[7 - n];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float* v = (k & 1) ? d : s;
+    float acc = 0.0f;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc = fmaf(static_cast<float>(C.m[k][n]), v[n], acc);
+    y[k] = acc;
+  }
+}
+
+__device__ __forceinline__ void dct8_inv(const float* X, float* x) {
+  constexpr Mat8 C = dct8();
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    float e = 0.0f, o = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) e = fmaf(static_cast<float>(C.m[k][n]), X[k], e);
+#pragma unroll
+    for (int k = 1; k < 8; k += 2) o = fmaf(static_cast<float>(C.m[k][n]), X[k], o);
+    x[n] = e + o;
+    x[7 - n] = e - o;
+  }
+}
+
+// round(x * 2^40) as a 64-bit integer, exact for |x| < 2^11: the fixed-point
+// format of the aggregation sums (integer addition is order-independent).
+constexpr double kFixScale = 1099511627776.0;  // 2^40
+__device__ __forceinline__ long long to_fixed(float x) {
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  const double y = fma(static_cast<double>(x), kFixScale, magic);
+  return __double_as_longlong(y) - __double_as_longlong(magic);
+}
+
 // ---------------------------------------------------------------------------
 // Orthonormal full-depth Haar along a group of K registers (K power of two).
 // Forward: at each level, pairs (2j, 2j+1) of the current sums become the

@@ -7,25 +7,26 @@
 
 namespace gbm3d {
 
-// idx[n_refs][K]: displacement ranks of the K matched blocks (slot 0 = reference)
-hipError_t launch_bm(const uint16_t* img, int H, int W, int R, int K, int16_t* idx, hipStream_t st);
+// idx[n_refs][K]: displacement ranks of the K matched blocks (slot 0 = reference).
+// split: parts of the displacement rows per reference row (1, 2, 4; 0 = by size)
+hipError_t launch_bm(const uint16_t* img, int H, int W, int R, int K, int16_t* idx, hipStream_t st, int split = 0);
 
 // out[H*W][64]: 2-D transform (kind 0 = bior1.5 Mallat, 1 = DCT) of every block
 hipError_t launch_stack(const uint16_t* img, int H, int W, int kind, float* out, hipStream_t st);
 
-// floats of the per-tile partial-sum buffer used by the group kernels
-size_t partials_floats(int H, int W, int R);
+// bytes of the per-tile partial-sum buffer (64-bit fixed point) of the group kernels
+size_t partials_bytes(int H, int W, int R);
 
 hipError_t launch_group_ht(const float* stack, const int16_t* idx, int H, int W, int R, int K, float sigma,
-                           float ht_a, float ht_b, int weight_mode, float eps, int keep_dc, float* partials,
+                           float ht_a, float ht_b, int weight_mode, float eps, int keep_dc, void* partials,
                            hipStream_t st);
 
 hipError_t launch_group_wiener(const float* stack_noisy, const float* stack_pilot, const int16_t* idx, int H,
-                               int W, int R, int K, float sigma, float* partials, hipStream_t st);
+                               int W, int R, int K, float sigma, void* partials, hipStream_t st);
 
 // out = sum(num) / sum(den) over the overlapping tile footprints; q (optional)
 // receives the uint16 quantisation of out
-hipError_t launch_reduce(const float* partials, int H, int W, int R, float* out, uint16_t* q, hipStream_t st);
+hipError_t launch_reduce(const void* partials, int H, int W, int R, float* out, uint16_t* q, hipStream_t st);
 
 hipError_t launch_quantize(const float* in, uint16_t* out, size_t n, hipStream_t st);
 

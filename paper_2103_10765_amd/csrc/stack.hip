@@ -20,23 +20,22 @@ constexpr int kPixRows = kRowsPerWg + kPatch - 1;  // 11
 constexpr int kPixCols = kWave + kPatch - 1;       // 71
 constexpr int kStagePitch = 65;                    // floats per parked block (odd: conflict-free)
 
-template <int L>
-__device__ __forceinline__ void rows_cols(float (&x)[8][8], const Mat8& M) {
-  // rows: x[a][0..L) <- M x[a][0..L)
+// one separable level on the leading L x L block: rows (x[a][0..L)), then columns
+template <int L, typename F>
+__device__ __forceinline__ void rows_cols(float (&x)[8][8], F&& line) {
 #pragma unroll
   for (int a = 0; a < L; ++a) {
     float t[8];
-    apply_mat<L>(M, x[a], t);
+    line(x[a], t);
 #pragma unroll
     for (int b = 0; b < L; ++b) x[a][b] = t[b];
   }
-  // columns
 #pragma unroll
   for (int b = 0; b < L; ++b) {
     float c[8], t[8];
 #pragma unroll
     for (int a = 0; a < L; ++a) c[a] = x[a][b];
-    apply_mat<L>(M, c, t);
+    line(c, t);
 #pragma unroll
     for (int a = 0; a < L; ++a) x[a][b] = t[a];
   }
@@ -48,12 +47,11 @@ __device__ __forceinline__ void forward2d(float (&x)[8][8]) {
     constexpr Mat8 A8 = bior_analysis(8);
     constexpr Mat8 A4 = bior_analysis(4);
     constexpr Mat8 A2 = bior_analysis(2);
-    rows_cols<8>(x, A8);
-    rows_cols<4>(x, A4);
-    rows_cols<2>(x, A2);
+    rows_cols<8>(x, [&](const float* i, float* o) { apply_mat<8>(A8, i, o); });
+    rows_cols<4>(x, [&](const float* i, float* o) { apply_mat<4>(A4, i, o); });
+    rows_cols<2>(x, [&](const float* i, float* o) { apply_mat<2>(A2, i, o); });
   } else {
-    constexpr Mat8 C = dct8();
-    rows_cols<8>(x, C);
+    rows_cols<8>(x, [&](const float* i, float* o) { dct8_fwd(i, o); });
   }
 }
 

@@ -33,6 +33,7 @@ class Params(ctypes.Structure):
         ("ht_weight", ctypes.c_int32),
         ("tv_eps_rel", ctypes.c_float),
         ("keep_dc", ctypes.c_int32),
+        ("bm_split", ctypes.c_int32),
     ]
 
 
@@ -162,9 +163,13 @@ class Context:
         return ctypes.byref(params if params is not None else default_params())
 
     # -- entry points ------------------------------------------------------
-    def match(self, img: torch.Tensor, K: int, params: Params | None = None, out=None, stream=None):
+    def match(self, img: torch.Tensor, K: int, params: Params | None = None, out=None, stream=None,
+              split: int | None = None):
         H, W = _hw(img)
         p = params if params is not None else default_params()
+        if split is not None:
+            p = Params.from_buffer_copy(p)
+            p.bm_split = split
         n = n_refs(H, W, p.step)
         if out is None:
             out = torch.empty((n, K), dtype=torch.int16, device=img.device)

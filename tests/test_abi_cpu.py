@@ -74,6 +74,7 @@ def test_validation_rules(G):
     assert G.check_args(512, 512, s25, G.default_params(step=4)) == G.EUNSUPPORTED
     assert G.check_args(512, 512, s25, G.default_params(ht_weight=7)) == G.EINVAL
     assert G.check_args(512, 512, s25, G.default_params(tv_eps_rel=-1.0)) == G.EINVAL
+    assert G.check_args(512, 512, s25, G.default_params(tv_eps_rel=0.0)) == G.EINVAL
     p = G.default_params()
     p.struct_size = 4
     assert G.check_args(512, 512, s25, p) == G.EINVAL

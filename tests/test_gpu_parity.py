@@ -149,18 +149,27 @@ def test_match_max_width_sampled(torch, G, ctx):
 # stage 1
 # ---------------------------------------------------------------------------
 
+FLAG_MAXABS = 5e-3   # bound on pixels near a flipped hard-threshold decision
+
+
 def _check_stage1(Yg, Yo, idx, margin, p, clean=None, ref_ids=None, window=None):
+    """max-abs <= 2e-4 off the pixels of near-threshold groups; those pixels
+    within 5e-3 (one flipped coefficient of size ~tau spread over ~100
+    overlapping blocks); near-threshold groups rare; PSNR within 0.01 dB."""
     H, W = Yg.shape
     flag = O.flagged_pixels(H, W, idx, margin, p, ref_ids=ref_ids)
     n_flag_groups = int((margin < 1e-5).sum())
+    assert n_flag_groups <= max(4, 0.005 * len(margin)), n_flag_groups
     if window is not None:
         rows, cols = window
         Yg, Yo, flag = Yg[np.ix_(rows, cols)], Yo[np.ix_(rows, cols)], flag[np.ix_(rows, cols)]
         if clean is not None:
             clean = clean[np.ix_(rows, cols)]
-    err = np.abs(Yg - Yo)[~flag]
-    assert err.size > 0.5 * Yg.size
-    assert err.max() <= MAXABS, (err.max(), n_flag_groups)
+    err = np.abs(Yg - Yo)
+    assert (~flag).sum() > 0.5 * Yg.size
+    assert err[~flag].max() <= MAXABS, (err[~flag].max(), n_flag_groups)
+    if flag.any():
+        assert err[flag].max() <= FLAG_MAXABS, err[flag].max()
     if clean is not None:
         d = abs(O.psnr(Yg, clean) - O.psnr(Yo, clean))
         assert d <= PSNR_TOL, d
@@ -176,8 +185,7 @@ def test_basic_parity(torch, G, ctx, H, W, S, sigma, seed):
     p = oparams(G, gp)
     Yg = ctx.basic(up(torch, Z), sigma, gp).cpu().numpy().astype(np.float64)
     Yo, (idx, margin, _, _) = O.basic_estimate(Z, sigma, p, return_parts=True)
-    n_flag = _check_stage1(Yg, Yo, idx, margin, p, clean)
-    assert n_flag <= max(1, 1e-3 * O.n_refs(H, W, 3))
+    _check_stage1(Yg, Yo, idx, margin, p, clean)
 
 
 @pytest.mark.parametrize("weight", [1, 2])
@@ -270,11 +278,11 @@ def test_denoise_end_to_end(torch, G, ctx):
     assert abs(O.psnr(Yg, clean) - O.psnr(Y, clean)) <= PSNR_TOL
     # the intermediate outputs are the stage-1 call's and its quantisation
     b2 = ctx.basic(Zt, SIG).cpu().numpy()
-    assert np.abs(basic.cpu().numpy() - b2).max() < 1e-6
+    assert np.array_equal(basic.cpu().numpy(), b2)
     assert np.array_equal(q.cpu().numpy(), O.quantize(basic.cpu().numpy().astype(np.float64)))
-    # stage 2 from the GPU's own pilot equals the Wiener call with that pilot
+    # stage 2 from the GPU's own pilot is the Wiener call with that pilot, bit for bit
     Yw = ctx.wiener(Zt, q, SIG).cpu().numpy()
-    assert np.abs(Yw - Yg).max() < 1e-6
+    assert np.array_equal(Yw, Yg.astype(np.float32))
     # the two stages improve on each other
     assert O.psnr(Yg, clean) > O.psnr(basic.cpu().numpy(), clean) > O.psnr(Z / 65535.0, clean)
 
@@ -305,12 +313,25 @@ def test_invalid_arguments_launch_nothing(torch, G, ctx):
 
 
 def test_side_stream_and_repeat(torch, G, ctx):
+    """Aggregation sums are 64-bit fixed point, so repeated runs (any stream,
+    any wave interleaving) are bit-identical."""
     _, Z = synth.make_case(100, 100, SIG, 16)
     Zt = up(torch, Z)
-    a = ctx.denoise(Zt, SIG)
+    a = ctx.denoise(Zt, SIG).cpu().numpy()
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         b = ctx.denoise(Zt, SIG, stream=s)
     s.synchronize()
     torch.cuda.synchronize()
-    assert np.abs(a.cpu().numpy() - b.cpu().numpy()).max() < 1e-6
+    assert np.array_equal(a, b.cpu().numpy())
+    for _ in range(3):
+        assert np.array_equal(a, ctx.denoise(Zt, SIG).cpu().numpy())
+
+
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_match_workgroup_shapes_agree(torch, G, ctx, split):
+    """Every workgroup shape of the matching kernel gives the oracle's indices."""
+    _, Z = synth.make_case(90, 200, SIG, 17)
+    exp = O.match(Z, 16, O.DEFAULT.with_(search=21))
+    got = ctx.match(up(torch, Z), 16, G.default_params(search=21), split=split).cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, exp)
