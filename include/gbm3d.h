@@ -51,6 +51,11 @@ extern "C" {
 #define GBM3D_W_NNZ  1
 #define GBM3D_W_UNIT 2
 
+/* gbm3d_denoise_batch flags */
+#define GBM3D_BATCH_GRAPH      1  /* capture the launches into a hipGraph, replayed
+                                     while the batch shape is unchanged            */
+#define GBM3D_BATCH_BASIC_ONLY 2  /* stage 1 only: out receives the basic estimate */
+
 /* patch-stack transforms */
 #define GBM3D_STACK_BIOR15 0   /* 3-level periodic Mallat bior1.5 (Sec. 5) */
 #define GBM3D_STACK_DCT    1   /* orthonormal 8x8 DCT-II (Sec. 4)           */
@@ -149,6 +154,20 @@ int gbm3d_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot,
 int gbm3d_denoise(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
                   const gbm3d_params* params, float* out, float* basic_out,
                   uint16_t* q_out, void* stream);
+
+/* A batch of images of any sizes (the plug-and-play use case of Sec. 1: one
+ * denoiser call per iteration, many images).  imgs: HOST array of n
+ * descriptors (device pointers inside).  For each image: if pilot == NULL,
+ * stage 1, Q and stage 2 as in gbm3d_denoise; otherwise stage 2 with the given
+ * pilot.  With GBM3D_BATCH_BASIC_ONLY, stage 1 only (pilot must be NULL) and
+ * out receives the basic estimate.  All images run in one sequence of ~9
+ * persistent kernel launches that walk per-image work lists; with
+ * GBM3D_BATCH_GRAPH the sequence is captured once into a hipGraph and replayed
+ * while image count, sizes, parameters and flags are unchanged (pointers may
+ * change between calls).  Results equal the single-image calls bit for bit.
+ * The image array is copied before the call returns. */
+int gbm3d_denoise_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n,
+                        const gbm3d_params* params, int flags, void* stream);
 
 /* Pilot quantisation: out[i] = floor(clip(in[i], 0, 1) * 65535 + 1/2),
  * evaluated in double from the float input; NaN -> 0.  Device pointers. */

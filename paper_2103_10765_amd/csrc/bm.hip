@@ -65,23 +65,31 @@ struct BmSmem {
   static constexpr size_t bytes = kScan > kMerge ? kScan : kMerge;
 };
 
+__host__ __device__ constexpr int bm_segments(int W) { return ((W + kStep - 1) / kStep + kLanesOut - 1) / kLanesOut; }
+
+template <int RPW>
+__host__ __device__ constexpr int bm_items(int H, int W) {
+  return (((H + kStep - 1) / kStep) + RPW - 1) / RPW * bm_segments(W);
+}
+
+// One work item: reference rows [RPW*pb, RPW*pb + RPW) x 62 reference columns.
 template <int K, int RPW, int SPLIT>
-__global__ __launch_bounds__(256, 2) void bm_kernel(const uint16_t* __restrict__ img, int H, int W, int R,
-                                                    int nRy, int nRx, int16_t* __restrict__ idx) {
+__device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __restrict__ img,
+                                        int16_t* __restrict__ idx, int H, int W, int R, int item) {
   static_assert(RPW * SPLIT == 4, "four waves per workgroup");
   constexpr int L = K - 1;
-  constexpr int kRowsMax = TileShape<RPW>::rows;
-  __shared__ __align__(16) unsigned char smem[BmSmem<K, RPW>::bytes];
   float(*tile)[kTileCols] = reinterpret_cast<float(*)[kTileCols]>(smem);
   double* buf = reinterpret_cast<double*>(smem + BmSmem<K, RPW>::kTile);
 
+  const int nRy = (H + kStep - 1) / kStep, nRx = (W + kStep - 1) / kStep;
+  const int segs = bm_segments(W);
   const int S = 2 * R + 1;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int row_in_wg = wave / SPLIT, part = wave % SPLIT;
-  const int p0 = blockIdx.y * RPW;
+  const int p0 = (item / segs) * RPW;
   const int p = p0 + row_in_wg;
-  const int q0 = blockIdx.x * kLanesOut;
+  const int q0 = (item % segs) * kLanesOut;
 
   // LDS image tile, periodic: rows 3p0-R .. 3(p0+RPW-1)+7+R, columns 3q0-R ..
   const int y0 = kStep * p0 - R;
@@ -92,7 +100,6 @@ __global__ __launch_bounds__(256, 2) void bm_kernel(const uint16_t* __restrict__
     const int y = pmod(y0 + r, H), x = pmod(x0 + c, W);
     tile[r][c] = static_cast<float>(img[static_cast<size_t>(y) * W + x]);
   }
-  (void)kRowsMax;
   __syncthreads();
 
   const int trow = kStep * row_in_wg;  // this wave's first tile row for dy = -R
@@ -229,40 +236,67 @@ __global__ __launch_bounds__(256, 2) void bm_kernel(const uint16_t* __restrict__
   }
 }
 
+template <int K, int RPW, int SPLIT, bool BATCH>
+__global__ __launch_bounds__(256, 2) void bm_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
+  __shared__ __align__(16) unsigned char smem[BmSmem<K, RPW>::bytes];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
+    bm_body<K, RPW, SPLIT>(smem, use_pilot ? r.pilot : r.noisy, r.idx, r.H, r.W, R, item);
+  });
+}
+
 }  // namespace
 
 template <int K, int RPW, int SPLIT>
-static hipError_t launch_bm_shape(const uint16_t* img, int H, int W, int R, int16_t* idx, hipStream_t st) {
-  const int nRy = (H + kStep - 1) / kStep, nRx = (W + kStep - 1) / kStep;
-  dim3 grid((nRx + kLanesOut - 1) / kLanesOut, (nRy + RPW - 1) / RPW);
-  hipLaunchKernelGGL((bm_kernel<K, RPW, SPLIT>), grid, dim3(256), 0, st, img, H, W, R, nRy, nRx, idx);
+static hipError_t launch_bm_shape(const ImgRec& one, const WorkList* wl, int R, int use_pilot, int grid_cap,
+                                  hipStream_t st) {
+  if (!wl) {
+    const int items = bm_items<RPW>(one.H, one.W);
+    hipLaunchKernelGGL((bm_kernel<K, RPW, SPLIT, false>), dim3(items), dim3(256), 0, st, one, WorkList{}, R,
+                       use_pilot);
+  } else {
+    if (wl->total <= 0) return hipSuccess;
+    const int grid = std::min(wl->total, grid_cap);
+    hipLaunchKernelGGL((bm_kernel<K, RPW, SPLIT, true>), dim3(grid), dim3(256), 0, st, one, *wl, R, use_pilot);
+  }
   return hipGetLastError();
 }
 
-// Workgroup shape: split the displacement rows only when the image has too
-// few reference rows to give every SIMD a couple of waves.
-template <int K>
-static hipError_t launch_bm_k(const uint16_t* img, int H, int W, int R, int split, int16_t* idx, hipStream_t st) {
-  if (split <= 0) {
-    const long nRy = (H + kStep - 1) / kStep, nRx = (W + kStep - 1) / kStep;
-    const long waves1 = nRy * ((nRx + kLanesOut - 1) / kLanesOut);  // waves with no split
-    split = waves1 >= 2048 ? 1 : (waves1 >= 1024 ? 2 : 4);
-  }
+int bm_auto_split(long total_waves_unsplit) {
+  return total_waves_unsplit >= 2048 ? 1 : (total_waves_unsplit >= 1024 ? 2 : 4);
+}
+
+int bm_items_for(int H, int W, int split) {
   switch (split) {
-    case 1: return launch_bm_shape<K, 4, 1>(img, H, W, R, idx, st);
-    case 2: return launch_bm_shape<K, 2, 2>(img, H, W, R, idx, st);
-    case 4: return launch_bm_shape<K, 1, 4>(img, H, W, R, idx, st);
+    case 1: return bm_items<4>(H, W);
+    case 2: return bm_items<2>(H, W);
+    default: return bm_items<1>(H, W);
+  }
+}
+
+long bm_waves_unsplit(int H, int W) {
+  return static_cast<long>((H + kStep - 1) / kStep) * bm_segments(W);
+}
+
+template <int K>
+static hipError_t launch_bm_k(const ImgRec& one, const WorkList* wl, int R, int split, int use_pilot, int grid_cap,
+                              hipStream_t st) {
+  switch (split) {
+    case 1: return launch_bm_shape<K, 4, 1>(one, wl, R, use_pilot, grid_cap, st);
+    case 2: return launch_bm_shape<K, 2, 2>(one, wl, R, use_pilot, grid_cap, st);
+    case 4: return launch_bm_shape<K, 1, 4>(one, wl, R, use_pilot, grid_cap, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_bm(const uint16_t* img, int H, int W, int R, int K, int16_t* idx, hipStream_t st, int split) {
+hipError_t launch_bm(const ImgRec& one, const WorkList* wl, int R, int K, int split, int use_pilot, int grid_cap,
+                     hipStream_t st) {
+  if (split <= 0) split = bm_auto_split(bm_waves_unsplit(one.H, one.W));
   switch (K) {
-    case 2: return launch_bm_k<2>(img, H, W, R, split, idx, st);
-    case 4: return launch_bm_k<4>(img, H, W, R, split, idx, st);
-    case 8: return launch_bm_k<8>(img, H, W, R, split, idx, st);
-    case 16: return launch_bm_k<16>(img, H, W, R, split, idx, st);
-    case 32: return launch_bm_k<32>(img, H, W, R, split, idx, st);
+    case 2: return launch_bm_k<2>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 4: return launch_bm_k<4>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 8: return launch_bm_k<8>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 16: return launch_bm_k<16>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 32: return launch_bm_k<32>(one, wl, R, split, use_pilot, grid_cap, st);
     default: return hipErrorInvalidValue;
   }
 }

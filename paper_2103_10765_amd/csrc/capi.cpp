@@ -1,7 +1,10 @@
-// C ABI of the G-BM3D library: argument validation, device workspace and the
-// stage pipelines.  Every compute step runs in the library's HIP kernels.
+// C ABI of the G-BM3D library: argument validation, device workspace, the
+// stage pipelines for one image and for batches (work lists, persistent
+// launches, hipGraph capture).  Every compute step runs in the library's HIP
+// kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +17,9 @@
 #include "../../include/gbm3d.h"
 #include "kernels.h"
 
+using gbm3d::ImgRec;
+using gbm3d::WorkList;
+
 namespace {
 
 struct Buffer {
@@ -21,19 +27,43 @@ struct Buffer {
   size_t bytes = 0;
 };
 
-thread_local std::string g_thread_error;
-
-}  // namespace
-
 struct TimingRecord {
   const char* name;
   hipEvent_t start, stop;
 };
 
+thread_local std::string g_thread_error;
+
+// Work lists of the batch phases: per-image prefix offsets of the items.
+enum Phase { kBm1, kStack1, kGroup1, kReduce1, kBm2, kStack2, kGroup2, kReduce2, kPhases };
+
+struct BatchPlan {
+  std::vector<ImgRec> recs;
+  std::vector<int> begin[kPhases];  // n + 1 each
+  int bm_split1 = 1, bm_split2 = 1;
+  bool any_stage1 = false, any_stage2 = false;
+};
+
+struct GraphEntry {
+  std::string key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
 struct gbm3d_ctx {
   int device = 0;
+  int n_cu = 256;
   std::string err;
   Buffer stack_a, stack_b, idx, partials, basic, q;
+  // batches
+  Buffer batch_ws, batch_table;
+  void* host_stage = nullptr;  // pinned staging of the batch table
+  size_t host_stage_bytes = 0;
+  hipEvent_t table_copied = nullptr;
+  hipStream_t capture_stream = nullptr;
+  GraphEntry graph;
   // per-kernel timing (off by default)
   bool timing = false;
   std::vector<TimingRecord> pending;
@@ -60,10 +90,16 @@ int hip_fail(gbm3d_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, e == hipErrorOutOfMemory ? GBM3D_ENOMEM : GBM3D_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(ctx, expr, what)                 \
-  do {                                           \
-    hipError_t e_ = (expr);                      \
+#define HIP_TRY(ctx, expr, what)                          \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
     if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+#define CHECK(expr)                \
+  do {                             \
+    int s_ = (expr);               \
+    if (s_ != GBM3D_OK) return s_; \
   } while (0)
 
 hipEvent_t take_event(gbm3d_ctx* ctx) {
@@ -96,7 +132,7 @@ hipError_t timed(gbm3d_ctx* ctx, const char* name, hipStream_t st, F&& launch) {
 bool is_pow2_group(int k) { return k == 2 || k == 4 || k == 8 || k == 16 || k == 32; }
 
 // Host-side validation; no side effects beyond the error text.
-int check_shape(gbm3d_ctx* ctx, int H, int W, const gbm3d_params& p) {
+int check_params(gbm3d_ctx* ctx, const gbm3d_params& p) {
   if (p.struct_size != sizeof(gbm3d_params))
     return fail(ctx, GBM3D_EINVAL, "params.struct_size %u != %zu", p.struct_size, sizeof(gbm3d_params));
   if (p.patch != 8) return fail(ctx, GBM3D_EUNSUPPORTED, "patch %d unsupported (only 8)", p.patch);
@@ -105,6 +141,11 @@ int check_shape(gbm3d_ctx* ctx, int H, int W, const gbm3d_params& p) {
     return fail(ctx, GBM3D_EINVAL, "search %d must be odd and in [1, 39]", p.search);
   if (p.bm_split != 0 && p.bm_split != 1 && p.bm_split != 2 && p.bm_split != 4)
     return fail(ctx, GBM3D_EINVAL, "bm_split %d must be 0, 1, 2 or 4", p.bm_split);
+  return GBM3D_OK;
+}
+
+int check_shape(gbm3d_ctx* ctx, int H, int W, const gbm3d_params& p) {
+  CHECK(check_params(ctx, p));
   const int lo = p.search > 8 ? p.search : 8;
   if (H < lo || W < lo || H > 32768 || W > 32768)
     return fail(ctx, GBM3D_EINVAL, "image %dx%d outside [%d, 32768]", H, W, lo);
@@ -118,7 +159,8 @@ int check_k(gbm3d_ctx* ctx, int K, const gbm3d_params& p, const char* name) {
 }
 
 int check_sigma(gbm3d_ctx* ctx, float sigma) {
-  if (!(sigma > 0.0f) || !std::isfinite(sigma)) return fail(ctx, GBM3D_EINVAL, "sigma %g must be > 0 and finite", sigma);
+  if (!(sigma > 0.0f) || !std::isfinite(sigma))
+    return fail(ctx, GBM3D_EINVAL, "sigma %g must be > 0 and finite", sigma);
   return GBM3D_OK;
 }
 
@@ -136,12 +178,6 @@ gbm3d_params resolve(const gbm3d_params* p) {
   gbm3d_default_params(&d);
   return p ? *p : d;
 }
-
-#define CHECK(expr)               \
-  do {                            \
-    int s_ = (expr);              \
-    if (s_ != GBM3D_OK) return s_; \
-  } while (0)
 
 int ensure(gbm3d_ctx* ctx, Buffer& b, size_t bytes, const char* name) {
   if (bytes <= b.bytes) return GBM3D_OK;
@@ -176,30 +212,45 @@ struct DeviceGuard {
   }
 };
 
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 size_t stack_bytes(int H, int W) { return static_cast<size_t>(H) * W * 64 * sizeof(float); }
 size_t n_refs(int H, int W) { return static_cast<size_t>((H + 2) / 3) * ((W + 2) / 3); }
 
-// Stage 1 into `basic` (and optionally its quantisation into q).
+ImgRec blank_rec(int H, int W, float sigma) {
+  ImgRec r;
+  std::memset(&r, 0, sizeof(r));
+  r.H = H;
+  r.W = W;
+  r.sigma = sigma;
+  return r;
+}
+
+float tv_eps(const gbm3d_params& p, float sigma) { return p.tv_eps_rel * sigma * 64.0f * static_cast<float>(p.k_ht); }
+
+// Stage 1 of one image into `basic` (and optionally its quantisation into q).
 int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, const gbm3d_params& p,
               float* basic, uint16_t* q, hipStream_t st) {
   const int R = p.search / 2;
   CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
   CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_ht * sizeof(int16_t), "idx"));
   CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
-  int16_t* idx = static_cast<int16_t*>(ctx->idx.p);
-  float* stack = static_cast<float*>(ctx->stack_a.p);
-  void* part = ctx->partials.p;
-  const float eps = p.tv_eps_rel * sigma * 64.0f * static_cast<float>(p.k_ht);
-  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(noisy, H, W, R, p.k_ht, idx, st, p.bm_split); }),
+  ImgRec r = blank_rec(H, W, sigma);
+  r.noisy = noisy;
+  r.basic = basic;
+  r.q = q;
+  r.stack_a = static_cast<float*>(ctx->stack_a.p);
+  r.idx = static_cast<int16_t*>(ctx->idx.p);
+  r.partials = static_cast<unsigned long long*>(ctx->partials.p);
+  r.eps = tv_eps(p, sigma);
+  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(r, nullptr, R, p.k_ht, p.bm_split, 0, 0, st); }),
           "block matching launch");
-  HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(noisy, H, W, GBM3D_STACK_BIOR15, stack, st); }),
+  HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(r, nullptr, 0, 0, 0, 0, st); }),
           "stack launch");
   HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
-            return gbm3d::launch_group_ht(stack, idx, H, W, R, p.k_ht, sigma, p.ht_a, p.ht_b, p.ht_weight, eps,
-                                          p.keep_dc, part, st);
+            return gbm3d::launch_group_ht(r, nullptr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0, st);
           }),
           "hard-threshold group launch");
-  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(part, H, W, R, basic, q, st); }),
+  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, R, 0, 0, st); }),
           "aggregation launch");
   return GBM3D_OK;
 }
@@ -211,23 +262,215 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
   CHECK(ensure(ctx, ctx->stack_b, stack_bytes(H, W), "pilot stack"));
   CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_wiener * sizeof(int16_t), "idx"));
   CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
-  int16_t* idx = static_cast<int16_t*>(ctx->idx.p);
-  float* sn = static_cast<float*>(ctx->stack_a.p);
-  float* sp = static_cast<float*>(ctx->stack_b.p);
-  void* part = ctx->partials.p;
-  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(pilot, H, W, R, p.k_wiener, idx, st, p.bm_split); }),
+  ImgRec r = blank_rec(H, W, sigma);
+  r.noisy = noisy;
+  r.pilot = pilot;
+  r.out = out;
+  r.stack_a = static_cast<float*>(ctx->stack_a.p);
+  r.stack_b = static_cast<float*>(ctx->stack_b.p);
+  r.idx = static_cast<int16_t*>(ctx->idx.p);
+  r.partials = static_cast<unsigned long long*>(ctx->partials.p);
+  HIP_TRY(ctx,
+          timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(r, nullptr, R, p.k_wiener, p.bm_split, 1, 0, st); }),
           "block matching launch");
-  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(noisy, H, W, GBM3D_STACK_DCT, sn, st); }),
+  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 0, 0, 0, st); }),
           "stack launch");
-  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(pilot, H, W, GBM3D_STACK_DCT, sp, st); }),
+  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 1, 1, 0, st); }),
           "pilot stack launch");
   HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
-            return gbm3d::launch_group_wiener(sn, sp, idx, H, W, R, p.k_wiener, sigma, part, st);
+            return gbm3d::launch_group_wiener(r, nullptr, R, p.k_wiener, 0, st);
           }),
           "Wiener group launch");
-  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(part, H, W, R, out, nullptr, st); }),
+  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, R, 1, 0, st); }),
           "aggregation launch");
   return GBM3D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+// Device table layout: recs[n], then kPhases prefix arrays of n + 1 ints.
+size_t table_bytes(int n) { return align256(sizeof(ImgRec) * n) + sizeof(int) * kPhases * (n + 1); }
+
+int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_params& p, int flags, BatchPlan& plan) {
+  const int R = p.search / 2;
+  const bool basic_only = (flags & GBM3D_BATCH_BASIC_ONLY) != 0;
+  const int kmax = std::max(p.k_ht, p.k_wiener);
+  // workspace slices
+  size_t total = 0;
+  std::vector<size_t> off(n);
+  for (int i = 0; i < n; ++i) {
+    const int H = imgs[i].H, W = imgs[i].W;
+    const bool s1 = imgs[i].pilot == nullptr;
+    off[i] = total;
+    total += align256(stack_bytes(H, W));                                   // stack_a
+    if (!basic_only) total += align256(stack_bytes(H, W));                  // stack_b
+    total += align256(n_refs(H, W) * kmax * sizeof(int16_t));               // idx
+    total += align256(gbm3d::partials_bytes(H, W, R));                      // partials
+    if (s1 && !basic_only) total += align256(static_cast<size_t>(H) * W * (sizeof(float) + sizeof(uint16_t)));
+  }
+  CHECK(ensure(ctx, ctx->batch_ws, total, "batch workspace"));
+  char* base = static_cast<char*>(ctx->batch_ws.p);
+  plan.recs.resize(n);
+  long waves1 = 0, waves2 = 0;
+  for (int i = 0; i < n; ++i) {
+    const gbm3d_image& im = imgs[i];
+    const int H = im.H, W = im.W;
+    const bool s1 = im.pilot == nullptr;
+    ImgRec r = blank_rec(H, W, im.sigma);
+    char* c = base + off[i];
+    r.stack_a = reinterpret_cast<float*>(c);
+    c += align256(stack_bytes(H, W));
+    if (!basic_only) {
+      r.stack_b = reinterpret_cast<float*>(c);
+      c += align256(stack_bytes(H, W));
+    }
+    r.idx = reinterpret_cast<int16_t*>(c);
+    c += align256(n_refs(H, W) * kmax * sizeof(int16_t));
+    r.partials = reinterpret_cast<unsigned long long*>(c);
+    c += align256(gbm3d::partials_bytes(H, W, R));
+    r.noisy = im.noisy;
+    r.eps = tv_eps(p, im.sigma);
+    if (basic_only) {
+      r.basic = im.out;
+    } else if (s1) {
+      r.basic = reinterpret_cast<float*>(c);
+      c += static_cast<size_t>(H) * W * sizeof(float);
+      r.q = reinterpret_cast<uint16_t*>(c);
+      r.pilot = r.q;
+      r.out = im.out;
+    } else {
+      r.pilot = im.pilot;
+      r.out = im.out;
+    }
+    plan.recs[i] = r;
+    if (s1) waves1 += gbm3d::bm_waves_unsplit(H, W);
+    if (!basic_only) waves2 += gbm3d::bm_waves_unsplit(H, W);
+    plan.any_stage1 = plan.any_stage1 || s1;
+  }
+  plan.any_stage2 = !basic_only;
+  plan.bm_split1 = p.bm_split > 0 ? p.bm_split : gbm3d::bm_auto_split(waves1);
+  plan.bm_split2 = p.bm_split > 0 ? p.bm_split : gbm3d::bm_auto_split(waves2);
+  for (int ph = 0; ph < kPhases; ++ph) plan.begin[ph].assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int H = imgs[i].H, W = imgs[i].W;
+    const bool s1 = imgs[i].pilot == nullptr;
+    const bool s2 = !basic_only;
+    const int items[kPhases] = {
+        s1 ? gbm3d::bm_items_for(H, W, plan.bm_split1) : 0,
+        s1 ? gbm3d::stack_items_for(H, W) : 0,
+        s1 ? gbm3d::group_items_for(H, W, R) : 0,
+        s1 ? gbm3d::reduce_items_for(H, W) : 0,
+        s2 ? gbm3d::bm_items_for(H, W, plan.bm_split2) : 0,
+        s2 ? gbm3d::stack_items_for(H, W) : 0,
+        s2 ? gbm3d::group_items_for(H, W, R) : 0,
+        s2 ? gbm3d::reduce_items_for(H, W) : 0,
+    };
+    for (int ph = 0; ph < kPhases; ++ph) plan.begin[ph][i + 1] = plan.begin[ph][i] + items[ph];
+  }
+  return GBM3D_OK;
+}
+
+WorkList worklist(const gbm3d_ctx* ctx, const BatchPlan& plan, int n, int phase) {
+  const char* t = static_cast<const char*>(ctx->batch_table.p);
+  WorkList w;
+  w.recs = reinterpret_cast<const ImgRec*>(t);
+  w.begin = reinterpret_cast<const int*>(t + align256(sizeof(ImgRec) * n)) + phase * (n + 1);
+  w.n = n;
+  w.total = plan.begin[phase][n];
+  return w;
+}
+
+// The batch launch sequence (also what a graph captures).  Persistent grids:
+// two matching / stack workgroups, one group workgroup and eight reduction
+// workgroups per compute unit.
+int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_params& p, hipStream_t st) {
+  const int R = p.search / 2;
+  const ImgRec none = blank_rec(0, 0, 0.0f);
+  const int cu = ctx->n_cu;
+  if (plan.any_stage1) {
+    const WorkList bm = worklist(ctx, plan, n, kBm1), sk = worklist(ctx, plan, n, kStack1);
+    const WorkList gr = worklist(ctx, plan, n, kGroup1), rd = worklist(ctx, plan, n, kReduce1);
+    HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
+              return gbm3d::launch_bm(none, &bm, R, p.k_ht, plan.bm_split1, 0, 2 * cu, st);
+            }),
+            "batch block matching");
+    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, 2 * cu, st); }),
+            "batch stack");
+    HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
+              return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, cu, st);
+            }),
+            "batch hard-threshold groups");
+    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 0, 8 * cu, st); }),
+            "batch aggregation");
+  }
+  if (plan.any_stage2) {
+    const WorkList bm = worklist(ctx, plan, n, kBm2), sk = worklist(ctx, plan, n, kStack2);
+    const WorkList gr = worklist(ctx, plan, n, kGroup2), rd = worklist(ctx, plan, n, kReduce2);
+    HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
+              return gbm3d::launch_bm(none, &bm, R, p.k_wiener, plan.bm_split2, 1, 2 * cu, st);
+            }),
+            "batch block matching");
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, 2 * cu, st); }),
+            "batch stack");
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, 2 * cu, st); }),
+            "batch pilot stack");
+    HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
+              return gbm3d::launch_group_wiener(none, &gr, R, p.k_wiener, cu, st);
+            }),
+            "batch Wiener groups");
+    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 1, 8 * cu, st); }),
+            "batch aggregation");
+  }
+  return GBM3D_OK;
+}
+
+// Copies the plan's table to the device (stream-ordered, from pinned memory).
+int upload_table(gbm3d_ctx* ctx, const BatchPlan& plan, int n, hipStream_t st) {
+  const size_t bytes = table_bytes(n);
+  CHECK(ensure(ctx, ctx->batch_table, bytes, "batch table"));
+  if (ctx->host_stage_bytes < bytes) {
+    if (ctx->host_stage) {
+      HIP_TRY(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
+      HIP_TRY(ctx, hipHostFree(ctx->host_stage), "hipHostFree");
+      ctx->host_stage = nullptr;
+      ctx->host_stage_bytes = 0;
+    }
+    HIP_TRY(ctx, hipHostMalloc(&ctx->host_stage, bytes, hipHostMallocDefault), "hipHostMalloc");
+    ctx->host_stage_bytes = bytes;
+  }
+  if (!ctx->table_copied) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->table_copied, hipEventDisableTiming), "event");
+  // the previous copy out of the staging buffer must have finished
+  HIP_TRY(ctx, hipEventSynchronize(ctx->table_copied), "hipEventSynchronize");
+  char* h = static_cast<char*>(ctx->host_stage);
+  std::memcpy(h, plan.recs.data(), sizeof(ImgRec) * n);
+  int* b = reinterpret_cast<int*>(h + align256(sizeof(ImgRec) * n));
+  for (int ph = 0; ph < kPhases; ++ph) std::memcpy(b + ph * (n + 1), plan.begin[ph].data(), sizeof(int) * (n + 1));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->batch_table.p, h, bytes, hipMemcpyHostToDevice, st), "table copy");
+  HIP_TRY(ctx, hipEventRecord(ctx->table_copied, st), "hipEventRecord");
+  return GBM3D_OK;
+}
+
+void drop_graph(gbm3d_ctx* ctx) {
+  if (ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
+  if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
+  ctx->graph = GraphEntry{};
+}
+
+// Everything that fixes the launch sequence: grids, work lists and kernel
+// arguments other than the table contents.
+std::string graph_key(const BatchPlan& plan, int n, const gbm3d_params& p, int flags, const gbm3d_ctx* ctx) {
+  std::string k;
+  auto add = [&](const void* d, size_t s) { k.append(static_cast<const char*>(d), s); };
+  add(&n, sizeof(n));
+  add(&p, sizeof(p));
+  add(&flags, sizeof(flags));
+  add(&ctx->batch_table.p, sizeof(void*));
+  add(&plan.bm_split1, sizeof(int));
+  add(&plan.bm_split2, sizeof(int));
+  for (int ph = 0; ph < kPhases; ++ph) add(plan.begin[ph].data(), sizeof(int) * (n + 1));
+  return k;
 }
 
 }  // namespace
@@ -268,6 +511,7 @@ int gbm3d_create(gbm3d_ctx** out, int hip_device) {
                 prop.gcnArchName);
   gbm3d_ctx* ctx = new gbm3d_ctx();
   ctx->device = dev;
+  ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   *out = ctx;
   return GBM3D_OK;
 }
@@ -277,8 +521,13 @@ void gbm3d_destroy(gbm3d_ctx* ctx) {
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
-    for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q})
+    drop_graph(ctx);
+    for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->batch_ws,
+                      &ctx->batch_table})
       if (b->p) (void)hipFree(b->p);
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+    if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto& r : ctx->pending) {
       (void)hipEventDestroy(r.start);
       (void)hipEventDestroy(r.stop);
@@ -306,7 +555,7 @@ int64_t gbm3d_n_refs(int H, int W, int step) {
   return static_cast<int64_t>((H + step - 1) / step) * ((W + step - 1) / step);
 }
 
-const char* gbm3d_version(void) { return "gbm3d-mi355x 0.1 (gfx950)"; }
+const char* gbm3d_version(void) { return "gbm3d-mi355x 0.2 (gfx950)"; }
 
 int gbm3d_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, const gbm3d_params* params, int16_t* idx,
                 void* stream) {
@@ -317,7 +566,12 @@ int gbm3d_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, const 
   CHECK(check_k(ctx, K, p, "K"));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
-  HIP_TRY(ctx, gbm3d::launch_bm(img, H, W, p.search / 2, K, idx, static_cast<hipStream_t>(stream), p.bm_split),
+  ImgRec r = blank_rec(H, W, 1.0f);
+  r.noisy = img;
+  r.idx = idx;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx,
+          timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(r, nullptr, p.search / 2, K, p.bm_split, 0, 0, st); }),
           "block matching launch");
   return GBM3D_OK;
 }
@@ -332,7 +586,10 @@ int gbm3d_stack(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int kind, flo
   CHECK(check_shape(ctx, H, W, p));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
-  HIP_TRY(ctx, gbm3d::launch_stack(img, H, W, kind, out, static_cast<hipStream_t>(stream)), "stack launch");
+  ImgRec r = blank_rec(H, W, 1.0f);
+  r.noisy = img;
+  r.stack_a = out;
+  HIP_TRY(ctx, gbm3d::launch_stack(r, nullptr, kind, 0, 0, 0, static_cast<hipStream_t>(stream)), "stack launch");
   return GBM3D_OK;
 }
 
@@ -390,6 +647,61 @@ int gbm3d_denoise(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sig
   return run_wiener(ctx, noisy, q, H, W, sigma, p, out, st);
 }
 
+int gbm3d_denoise_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_params* params, int flags,
+                        void* stream) {
+  const gbm3d_params p = resolve(params);
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (n < 0 || (n > 0 && !imgs)) return fail(ctx, GBM3D_EINVAL, "bad image array");
+  if (flags & ~(GBM3D_BATCH_GRAPH | GBM3D_BATCH_BASIC_ONLY)) return fail(ctx, GBM3D_EINVAL, "unknown flags %d", flags);
+  if (n == 0) return GBM3D_OK;
+  CHECK(check_params(ctx, p));
+  CHECK(check_k(ctx, p.k_ht, p, "k_ht"));
+  CHECK(check_k(ctx, p.k_wiener, p, "k_wiener"));
+  CHECK(check_ht(ctx, p));
+  const bool basic_only = (flags & GBM3D_BATCH_BASIC_ONLY) != 0;
+  for (int i = 0; i < n; ++i) {
+    const gbm3d_image& im = imgs[i];
+    if (!im.noisy || !im.out) return fail(ctx, GBM3D_EINVAL, "image %d: NULL noisy or out pointer", i);
+    if (basic_only && im.pilot) return fail(ctx, GBM3D_EINVAL, "image %d: stage 1 only takes no pilot", i);
+    CHECK(check_shape(ctx, im.H, im.W, p));
+    CHECK(check_sigma(ctx, im.sigma));
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  BatchPlan plan;
+  CHECK(plan_batch(ctx, imgs, n, p, flags, plan));
+  CHECK(upload_table(ctx, plan, n, st));
+  if (!(flags & GBM3D_BATCH_GRAPH) || ctx->timing) return launch_batch(ctx, plan, n, p, st);
+
+  const std::string key = graph_key(plan, n, p, flags, ctx);
+  if (!ctx->graph.exec || ctx->graph.key != key) {
+    drop_graph(ctx);
+    if (!ctx->capture_stream)
+      HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "stream");
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    const int s = launch_batch(ctx, plan, n, p, ctx->capture_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (s != GBM3D_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    HIP_TRY(ctx, e, "end capture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(ctx, ei, "graph instantiate");
+    }
+    ctx->graph.key = key;
+    ctx->graph.graph = graph;
+    ctx->graph.exec = exec;
+  }
+  HIP_TRY(ctx, hipGraphLaunch(ctx->graph.exec, st), "graph launch");
+  return GBM3D_OK;
+}
+
 int gbm3d_quantize(gbm3d_ctx* ctx, const float* in, uint16_t* out, size_t n, void* stream) {
   if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
   if (n == 0) return GBM3D_OK;
@@ -430,7 +742,7 @@ int gbm3d_timing_reset(gbm3d_ctx* ctx) {
   if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
   double ms;
   int64_t n;
-  (void)gbm3d_timing_read(ctx, "", &ms, &n);
+  CHECK(gbm3d_timing_read(ctx, "", &ms, &n));
   ctx->totals.clear();
   return GBM3D_OK;
 }

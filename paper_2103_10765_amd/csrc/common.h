@@ -203,6 +203,58 @@ __device__ __forceinline__ void haar_inv(float* v) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-image descriptor and work lists.  Every kernel is a per-work-item body;
+// for one image the grid enumerates its items, for a batch a persistent grid
+// walks a work list whose per-image prefix offsets are in `begin`.
+// ---------------------------------------------------------------------------
+struct ImgRec {
+  const uint16_t* noisy;           // u16 [H][W]
+  const uint16_t* pilot;           // stage-2 matching input, u16 [H][W]
+  float* out;                      // stage-2 output, f32 [H][W]
+  float* basic;                    // stage-1 output, f32 [H][W]
+  uint16_t* q;                     // optional quantised stage-1 output, u16 [H][W]
+  float* stack_a;                  // f32 [H*W][64]
+  float* stack_b;                  // f32 [H*W][64]
+  int16_t* idx;                    // i16 [n_ref][K]
+  unsigned long long* partials;    // 64-bit fixed-point tile sums
+  int H, W;
+  float sigma, eps;
+};
+
+struct WorkList {
+  const ImgRec* recs;  // device array [n]
+  const int* begin;    // device array [n + 1]: first item of each image
+  int n;
+  int total;           // begin[n]
+};
+
+// image owning work item `item` (begin is non-decreasing, begin[0] = 0)
+__device__ __forceinline__ int find_image(const int* __restrict__ begin, int n, int item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Runs body(rec, local_item) for this workgroup's items: the single image's
+// item blockIdx.x, or every batch item blockIdx.x + k * gridDim.x.
+template <bool BATCH, typename F>
+__device__ __forceinline__ void for_each_item(const ImgRec& one, const WorkList& wl, F&& body) {
+  if constexpr (!BATCH) {
+    body(one, static_cast<int>(blockIdx.x));
+  } else {
+    for (int item = blockIdx.x; item < wl.total; item += gridDim.x) {
+      const int i = find_image(wl.begin, wl.n, item);
+      const ImgRec r = wl.recs[i];
+      body(r, item - wl.begin[i]);
+      __syncthreads();  // LDS is reused by the next item
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Wavefront helpers (wave64)
 // ---------------------------------------------------------------------------
 

@@ -36,6 +36,7 @@ constexpr int kThreads = kWaves * kWave;
 constexpr int kScratchPitch = 9;                  // LDS row pitch of a parked 8x8 block
 constexpr int kBlockFloats = 8 * kScratchPitch;   // 72
 constexpr int kTPY = 8, kTPX = 8;                 // references per tile
+constexpr int kReduceThreads = 256;
 
 using acc_t = unsigned long long;
 
@@ -47,8 +48,31 @@ struct Foot {
 };
 
 struct GroupArgs {
-  int H, W, R, S, nRy, nRx, nTx;
-  int FY, FXP;
+  int H, W, R, S, nRy, nRx, nTx, nTy;
+  int FY, FX, FXP;
+};
+
+__host__ __device__ inline GroupArgs make_args(int H, int W, int R) {
+  GroupArgs g;
+  g.H = H;
+  g.W = W;
+  g.R = R;
+  g.S = 2 * R + 1;
+  g.nRy = (H + kStep - 1) / kStep;
+  g.nRx = (W + kStep - 1) / kStep;
+  g.nTx = (g.nRx + kTPX - 1) / kTPX;
+  g.nTy = (g.nRy + kTPY - 1) / kTPY;
+  g.FY = kStep * (kTPY - 1) + kPatch + 2 * R;
+  g.FX = kStep * (kTPX - 1) + kPatch + 2 * R;
+  g.FXP = g.FX + ((8 - g.FX) % 32 + 32) % 32;
+  return g;
+}
+
+__host__ __device__ inline int reduce_items(int H, int W) { return H * ((W + kReduceThreads - 1) / kReduceThreads); }
+
+struct HtParams {
+  float ht_a, ht_b;
+  int weight_mode, keep_dc;
 };
 
 // Inverse of one separable level on the leading L x L block of each of the K
@@ -125,35 +149,35 @@ __device__ __forceinline__ void zero_acc(acc_t* acc, int n) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __restrict__ partials, int nTx) {
+__device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __restrict__ dst) {
   __syncthreads();
-  acc_t* dst = partials + (static_cast<size_t>(blockIdx.y) * nTx + blockIdx.x) * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = acc[i];
+  __syncthreads();  // the accumulator is reused by the next item
 }
 
+// One work item = one tile of references: stage-1 groups.
 template <int K>
-__global__ __launch_bounds__(kThreads) void group_ht_kernel(const float* __restrict__ stack,
-                                                            const int16_t* __restrict__ idx, GroupArgs g,
-                                                            float sigma, float ht_a, float ht_b, int weight_mode,
-                                                            float eps, int keep_dc, acc_t* __restrict__ partials) {
-  __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[kWaves][K * kBlockFloats];
+__device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * kBlockFloats], const ImgRec& r, int R,
+                                              const HtParams& hp, int item) {
+  const GroupArgs g = make_args(r.H, r.W, R);
+  const float* __restrict__ stack = r.stack_a;
+  const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int n_acc = 2 * g.FY * g.FXP;
   zero_acc(acc, n_acc);
-  const int fy0 = kStep * static_cast<int>(blockIdx.y) * kTPY - g.R;
-  const int fx0 = kStep * static_cast<int>(blockIdx.x) * kTPX - g.R;
+  const int fy0 = kStep * tyi * kTPY - g.R;
+  const int fx0 = kStep * txi * kTPX - g.R;
   float* xw = scratch[wave];
   const int a = lane >> 3, b = lane & 7;
-  const float tau = sigma * (ht_a - ht_b * static_cast<float>(bior_level(lane)));
-  const bool dc_lane = keep_dc && lane == 0;
+  const float tau = r.sigma * (hp.ht_a - hp.ht_b * static_cast<float>(bior_level(lane)));
+  const bool dc_lane = hp.keep_dc && lane == 0;
 
   for (int t = wave; t < kTPY * kTPX; t += kWaves) {
-    const int p = blockIdx.y * kTPY + t / kTPX, q = blockIdx.x * kTPX + t % kTPX;
+    const int p = tyi * kTPY + t / kTPX, q = txi * kTPX + t % kTPX;
     if (p >= g.nRy || q >= g.nRx) continue;
     int pos_v, lyx_v;
-    decode_slots<K>(g, idx, p, q, fy0, fx0, lane, pos_v, lyx_v);
+    decode_slots<K>(g, r.idx, p, q, fy0, fx0, lane, pos_v, lyx_v);
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -185,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void group_ht_kernel(const float* __restr
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = xw[k * kBlockFloats + a * kScratchPitch + b];
     float w;
-    if (weight_mode == 0) {
+    if (hp.weight_mode == 0) {
       float tv = 0.0f;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -193,39 +217,40 @@ __global__ __launch_bounds__(kThreads) void group_ht_kernel(const float* __restr
         if (b < 7) tv += fabsf(xw[k * kBlockFloats + a * kScratchPitch + b + 1] - u[k]);
         if (a < 7) tv += fabsf(xw[k * kBlockFloats + (a + 1) * kScratchPitch + b] - u[k]);
       }
-      w = eps / (wave_sum(tv) + eps);
-    } else if (weight_mode == 1) {
+      w = r.eps / (wave_sum(tv) + r.eps);
+    } else if (hp.weight_mode == 1) {
       w = 1.0f / static_cast<float>(max(wave_sum_int(nnz), 1));
     } else {
       w = 1.0f;
     }
     accumulate<K>(acc, g, lyx_v, u, w, lane);
   }
-  flush_acc(acc, n_acc, partials, g.nTx);
+  flush_acc(acc, n_acc, r.partials + static_cast<size_t>(item) * n_acc);
 }
 
+// One work item = one tile of references: stage-2 groups.
 template <int K>
-__global__ __launch_bounds__(kThreads) void group_wiener_kernel(const float* __restrict__ stack_n,
-                                                                const float* __restrict__ stack_p,
-                                                                const int16_t* __restrict__ idx, GroupArgs g,
-                                                                float sigma, acc_t* __restrict__ partials) {
-  __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[kWaves][K * kBlockFloats];
+__device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K * kBlockFloats], const ImgRec& r,
+                                                  int R, int item) {
+  const GroupArgs g = make_args(r.H, r.W, R);
+  const float* __restrict__ stack_n = r.stack_a;
+  const float* __restrict__ stack_p = r.stack_b;
+  const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int n_acc = 2 * g.FY * g.FXP;
   zero_acc(acc, n_acc);
-  const int fy0 = kStep * static_cast<int>(blockIdx.y) * kTPY - g.R;
-  const int fx0 = kStep * static_cast<int>(blockIdx.x) * kTPX - g.R;
+  const int fy0 = kStep * tyi * kTPY - g.R;
+  const int fx0 = kStep * txi * kTPX - g.R;
   float* xw = scratch[wave];
   const int a = lane >> 3, b = lane & 7;
-  const float s2 = sigma * sigma;
+  const float s2 = r.sigma * r.sigma;
 
   for (int t = wave; t < kTPY * kTPX; t += kWaves) {
-    const int p = blockIdx.y * kTPY + t / kTPX, q = blockIdx.x * kTPX + t % kTPX;
+    const int p = tyi * kTPY + t / kTPX, q = txi * kTPX + t % kTPX;
     if (p >= g.nRy || q >= g.nRx) continue;
     int pos_v, lyx_v;
-    decode_slots<K>(g, idx, p, q, fy0, fx0, lane, pos_v, lyx_v);
+    decode_slots<K>(g, r.idx, p, q, fy0, fx0, lane, pos_v, lyx_v);
     float vn[K], vp[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -256,27 +281,45 @@ __global__ __launch_bounds__(kThreads) void group_wiener_kernel(const float* __r
     for (int k = 0; k < K; ++k) u[k] = xw[k * kBlockFloats + a * kScratchPitch + b];
     accumulate<K>(acc, g, lyx_v, u, w, lane);
   }
-  flush_acc(acc, n_acc, partials, g.nTx);
+  flush_acc(acc, n_acc, r.partials + static_cast<size_t>(item) * n_acc);
+}
+
+template <int K, bool BATCH>
+__global__ __launch_bounds__(kThreads) void group_ht_kernel(ImgRec one, WorkList wl, int R, HtParams hp) {
+  __shared__ acc_t acc[Foot::entries];
+  __shared__ float scratch[kWaves][K * kBlockFloats];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_ht_body<K>(acc, scratch, r, R, hp, item); });
+}
+
+template <int K, bool BATCH>
+__global__ __launch_bounds__(kThreads) void group_wiener_kernel(ImgRec one, WorkList wl, int R) {
+  __shared__ acc_t acc[Foot::entries];
+  __shared__ float scratch[kWaves][K * kBlockFloats];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_wiener_body<K>(acc, scratch, r, R, item); });
 }
 
 // floor(a / b) for b > 0
 __device__ __forceinline__ int fdiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
-// Sum of the partial footprints covering pixel (y, x), then normalise.
-__global__ __launch_bounds__(256) void reduce_kernel(const acc_t* __restrict__ partials, GroupArgs g, int TY,
-                                                     int TX, int nTy, int FX, float* __restrict__ out,
-                                                     uint16_t* __restrict__ q) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
+// One work item = 256 pixels of one row: sum of the partial footprints
+// covering each pixel (periodic), then normalise.
+__device__ __forceinline__ void reduce_body(const ImgRec& r, int R, int final_stage, int item) {
+  const GroupArgs g = make_args(r.H, r.W, R);
+  const acc_t* __restrict__ partials = r.partials;
+  float* __restrict__ out = final_stage ? r.out : r.basic;
+  uint16_t* __restrict__ q = final_stage ? nullptr : r.q;
+  const int TY = kStep * kTPY, TX = kStep * kTPX;
+  const int xb = (g.W + kReduceThreads - 1) / kReduceThreads;
+  const int y = item / xb;
+  const int x = (item % xb) * kReduceThreads + static_cast<int>(threadIdx.x);
   if (x >= g.W) return;
-  const int R = g.R;
   // candidate (tile row, local row) pairs for y; the footprint of tile row t
   // covers unwrapped rows [t*TY - R, t*TY - R + FY)
   int cty[16], cly[16], ny = 0;
   {
-    const int lo = -R, hi = (nTy - 1) * TY - R + g.FY;
+    const int lo = -R, hi = (g.nTy - 1) * TY - R + g.FY;
     for (int yy = y + fdiv(lo - y + g.H - 1, g.H) * g.H; yy < hi; yy += g.H) {
-      const int t0 = max(0, fdiv(yy + R - g.FY, TY) + 1), t1 = min(nTy - 1, fdiv(yy + R, TY));
+      const int t0 = max(0, fdiv(yy + R - g.FY, TY) + 1), t1 = min(g.nTy - 1, fdiv(yy + R, TY));
       for (int t = t0; t <= t1 && ny < 16; ++t) {
         cty[ny] = t;
         cly[ny] = yy - (t * TY - R);
@@ -286,9 +329,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const acc_t* __restrict__ p
   }
   int ctx[16], clx[16], nx = 0;
   {
-    const int lo = -R, hi = (g.nTx - 1) * TX - R + FX;
+    const int lo = -R, hi = (g.nTx - 1) * TX - R + g.FX;
     for (int xx = x + fdiv(lo - x + g.W - 1, g.W) * g.W; xx < hi; xx += g.W) {
-      const int t0 = max(0, fdiv(xx + R - FX, TX) + 1), t1 = min(g.nTx - 1, fdiv(xx + R, TX));
+      const int t0 = max(0, fdiv(xx + R - g.FX, TX) + 1), t1 = min(g.nTx - 1, fdiv(xx + R, TX));
       for (int t = t0; t <= t1 && nx < 16; ++t) {
         ctx[nx] = t;
         clx[nx] = xx - (t * TX - R);
@@ -315,6 +358,11 @@ __global__ __launch_bounds__(256) void reduce_kernel(const acc_t* __restrict__ p
   }
 }
 
+template <bool BATCH>
+__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ImgRec one, WorkList wl, int R, int final_stage) {
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { reduce_body(r, R, final_stage, item); });
+}
+
 __global__ void quantize_kernel(const float* __restrict__ in, uint16_t* __restrict__ out, size_t n) {
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
@@ -323,82 +371,81 @@ __global__ void quantize_kernel(const float* __restrict__ in, uint16_t* __restri
   }
 }
 
-GroupArgs make_args(int H, int W, int R) {
-  GroupArgs g;
-  g.H = H;
-  g.W = W;
-  g.R = R;
-  g.S = 2 * R + 1;
-  g.nRy = (H + kStep - 1) / kStep;
-  g.nRx = (W + kStep - 1) / kStep;
-  g.nTx = (g.nRx + kTPX - 1) / kTPX;
-  g.FY = kStep * (kTPY - 1) + kPatch + 2 * R;
-  const int FX = kStep * (kTPX - 1) + kPatch + 2 * R;
-  g.FXP = FX + ((8 - FX) % 32 + 32) % 32;
-  return g;
-}
-
 }  // namespace
 
 size_t partials_bytes(int H, int W, int R) {
   const GroupArgs g = make_args(H, W, R);
-  const int nTy = (g.nRy + kTPY - 1) / kTPY;
-  return static_cast<size_t>(nTy) * g.nTx * 2 * g.FY * g.FXP * sizeof(acc_t);
+  return static_cast<size_t>(g.nTy) * g.nTx * 2 * g.FY * g.FXP * sizeof(acc_t);
 }
 
+int group_items_for(int H, int W, int R) {
+  const GroupArgs g = make_args(H, W, R);
+  return g.nTy * g.nTx;
+}
+
+int reduce_items_for(int H, int W) { return reduce_items(H, W); }
+
 template <int K>
-static hipError_t launch_ht_k(const float* stack, const int16_t* idx, int H, int W, int R, float sigma,
-                              float ht_a, float ht_b, int weight_mode, float eps, int keep_dc, void* partials,
+static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int grid_cap,
                               hipStream_t st) {
-  const GroupArgs g = make_args(H, W, R);
-  dim3 grid(g.nTx, (g.nRy + kTPY - 1) / kTPY);
-  hipLaunchKernelGGL((group_ht_kernel<K>), grid, dim3(kThreads), 0, st, stack, idx, g, sigma, ht_a, ht_b,
-                     weight_mode, eps, keep_dc, static_cast<acc_t*>(partials));
+  if (!wl) {
+    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(kThreads), 0, st,
+                       one, WorkList{}, R, hp);
+  } else {
+    if (wl->total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(kThreads), 0, st, one,
+                       *wl, R, hp);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_group_ht(const float* stack, const int16_t* idx, int H, int W, int R, int K, float sigma,
-                           float ht_a, float ht_b, int weight_mode, float eps, int keep_dc, void* partials,
-                           hipStream_t st) {
+hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, float ht_a, float ht_b,
+                           int weight_mode, int keep_dc, int grid_cap, hipStream_t st) {
+  const HtParams hp{ht_a, ht_b, weight_mode, keep_dc};
   switch (K) {
-    case 2: return launch_ht_k<2>(stack, idx, H, W, R, sigma, ht_a, ht_b, weight_mode, eps, keep_dc, partials, st);
-    case 4: return launch_ht_k<4>(stack, idx, H, W, R, sigma, ht_a, ht_b, weight_mode, eps, keep_dc, partials, st);
-    case 8: return launch_ht_k<8>(stack, idx, H, W, R, sigma, ht_a, ht_b, weight_mode, eps, keep_dc, partials, st);
-    case 16: return launch_ht_k<16>(stack, idx, H, W, R, sigma, ht_a, ht_b, weight_mode, eps, keep_dc, partials, st);
-    case 32: return launch_ht_k<32>(stack, idx, H, W, R, sigma, ht_a, ht_b, weight_mode, eps, keep_dc, partials, st);
+    case 2: return launch_ht_k<2>(one, wl, R, hp, grid_cap, st);
+    case 4: return launch_ht_k<4>(one, wl, R, hp, grid_cap, st);
+    case 8: return launch_ht_k<8>(one, wl, R, hp, grid_cap, st);
+    case 16: return launch_ht_k<16>(one, wl, R, hp, grid_cap, st);
+    case 32: return launch_ht_k<32>(one, wl, R, hp, grid_cap, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int K>
-static hipError_t launch_wiener_k(const float* sn, const float* sp, const int16_t* idx, int H, int W, int R,
-                                  float sigma, void* partials, hipStream_t st) {
-  const GroupArgs g = make_args(H, W, R);
-  dim3 grid(g.nTx, (g.nRy + kTPY - 1) / kTPY);
-  hipLaunchKernelGGL((group_wiener_kernel<K>), grid, dim3(kThreads), 0, st, sn, sp, idx, g, sigma,
-                     static_cast<acc_t*>(partials));
+static hipError_t launch_wiener_k(const ImgRec& one, const WorkList* wl, int R, int grid_cap, hipStream_t st) {
+  if (!wl) {
+    hipLaunchKernelGGL((group_wiener_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(kThreads), 0,
+                       st, one, WorkList{}, R);
+  } else {
+    if (wl->total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((group_wiener_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(kThreads), 0, st,
+                       one, *wl, R);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_group_wiener(const float* sn, const float* sp, const int16_t* idx, int H, int W, int R, int K,
-                               float sigma, void* partials, hipStream_t st) {
+hipError_t launch_group_wiener(const ImgRec& one, const WorkList* wl, int R, int K, int grid_cap, hipStream_t st) {
   switch (K) {
-    case 2: return launch_wiener_k<2>(sn, sp, idx, H, W, R, sigma, partials, st);
-    case 4: return launch_wiener_k<4>(sn, sp, idx, H, W, R, sigma, partials, st);
-    case 8: return launch_wiener_k<8>(sn, sp, idx, H, W, R, sigma, partials, st);
-    case 16: return launch_wiener_k<16>(sn, sp, idx, H, W, R, sigma, partials, st);
-    case 32: return launch_wiener_k<32>(sn, sp, idx, H, W, R, sigma, partials, st);
+    case 2: return launch_wiener_k<2>(one, wl, R, grid_cap, st);
+    case 4: return launch_wiener_k<4>(one, wl, R, grid_cap, st);
+    case 8: return launch_wiener_k<8>(one, wl, R, grid_cap, st);
+    case 16: return launch_wiener_k<16>(one, wl, R, grid_cap, st);
+    case 32: return launch_wiener_k<32>(one, wl, R, grid_cap, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_reduce(const void* partials, int H, int W, int R, float* out, uint16_t* q, hipStream_t st) {
-  const GroupArgs g = make_args(H, W, R);
-  const int nTy = (g.nRy + kTPY - 1) / kTPY;
-  const int FX = kStep * (kTPX - 1) + kPatch + 2 * R;
-  dim3 grid((W + 255) / 256, H);
-  hipLaunchKernelGGL(reduce_kernel, grid, dim3(256), 0, st, static_cast<const acc_t*>(partials), g, kStep * kTPY,
-                     kStep * kTPX, nTy, FX, out, q);
+hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int R, int final_stage, int grid_cap,
+                         hipStream_t st) {
+  if (!wl) {
+    hipLaunchKernelGGL((reduce_kernel<false>), dim3(reduce_items(one.H, one.W)), dim3(kReduceThreads), 0, st, one,
+                       WorkList{}, R, final_stage);
+  } else {
+    if (wl->total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((reduce_kernel<true>), dim3(std::min(wl->total, grid_cap)), dim3(kReduceThreads), 0, st,
+                       one, *wl, R, final_stage);
+  }
   return hipGetLastError();
 }
 

@@ -1,32 +1,51 @@
 // Host-side launchers of the library's kernels (all asynchronous on `st`).
+//
+// Each launcher runs either one image (`wl` == nullptr: the grid enumerates
+// the image's work items, the descriptor `one` is passed by value) or a batch
+// (`wl` != nullptr: a persistent grid of at most `grid_cap` workgroups walks
+// the work list).  The *_items_for functions give an image's item count for
+// each kernel, used to build work lists.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include "common.h"
+
 namespace gbm3d {
 
-// idx[n_refs][K]: displacement ranks of the K matched blocks (slot 0 = reference).
-// split: parts of the displacement rows per reference row (1, 2, 4; 0 = by size)
-hipError_t launch_bm(const uint16_t* img, int H, int W, int R, int K, int16_t* idx, hipStream_t st, int split = 0);
+// Block matching of one image's noisy (use_pilot = 0) or pilot (1) image into
+// rec.idx[n_refs][K] (slot 0 = reference).  split: parts of the displacement
+// rows per reference row (1, 2, 4; 0 = by image size).
+hipError_t launch_bm(const ImgRec& one, const WorkList* wl, int R, int K, int split, int use_pilot, int grid_cap,
+                     hipStream_t st);
+int bm_auto_split(long total_waves_unsplit);
+long bm_waves_unsplit(int H, int W);
+int bm_items_for(int H, int W, int split);
 
-// out[H*W][64]: 2-D transform (kind 0 = bior1.5 Mallat, 1 = DCT) of every block
-hipError_t launch_stack(const uint16_t* img, int H, int W, int kind, float* out, hipStream_t st);
+// 2-D transform (kind 0 = bior1.5 Mallat, 1 = DCT) of every block of noisy
+// (src_sel 0) or pilot (1) into stack_a (dst_sel 0) or stack_b (1), [H*W][64].
+hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src_sel, int dst_sel, int grid_cap,
+                        hipStream_t st);
+int stack_items_for(int H, int W);
 
 // bytes of the per-tile partial-sum buffer (64-bit fixed point) of the group kernels
 size_t partials_bytes(int H, int W, int R);
+int group_items_for(int H, int W, int R);
 
-hipError_t launch_group_ht(const float* stack, const int16_t* idx, int H, int W, int R, int K, float sigma,
-                           float ht_a, float ht_b, int weight_mode, float eps, int keep_dc, void* partials,
-                           hipStream_t st);
+// stage-1 groups: stack_a (bior) + idx -> partials (weights scaled by rec.eps)
+hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, float ht_a, float ht_b,
+                           int weight_mode, int keep_dc, int grid_cap, hipStream_t st);
 
-hipError_t launch_group_wiener(const float* stack_noisy, const float* stack_pilot, const int16_t* idx, int H,
-                               int W, int R, int K, float sigma, void* partials, hipStream_t st);
+// stage-2 groups: stack_a (noisy DCT) + stack_b (pilot DCT) + idx -> partials
+hipError_t launch_group_wiener(const ImgRec& one, const WorkList* wl, int R, int K, int grid_cap, hipStream_t st);
 
-// out = sum(num) / sum(den) over the overlapping tile footprints; q (optional)
-// receives the uint16 quantisation of out
-hipError_t launch_reduce(const void* partials, int H, int W, int R, float* out, uint16_t* q, hipStream_t st);
+// sum(num) / sum(den) over the overlapping tile footprints into rec.basic
+// (+ its quantisation into rec.q when set) or, with final_stage, rec.out
+hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int R, int final_stage, int grid_cap,
+                         hipStream_t st);
+int reduce_items_for(int H, int W);
 
 hipError_t launch_quantize(const float* in, uint16_t* out, size_t n, hipStream_t st);
 

@@ -55,13 +55,17 @@ __device__ __forceinline__ void forward2d(float (&x)[8][8]) {
   }
 }
 
+__host__ __device__ constexpr int stack_items(int H, int W) {
+  return ((H + kRowsPerWg - 1) / kRowsPerWg) * ((W + kWave - 1) / kWave);
+}
+
 template <int KIND>
-__global__ __launch_bounds__(256) void stack_kernel(const uint16_t* __restrict__ img, int H, int W,
-                                                    float* __restrict__ out) {
-  __shared__ float pix[kPixRows][kPixCols + 1];
-  __shared__ float stage[kRowsPerWg][kWave * kStagePitch];
-  const int y0 = blockIdx.y * kRowsPerWg;
-  const int x0 = blockIdx.x * kWave;
+__device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*stage)[kWave * kStagePitch],
+                                           const uint16_t* __restrict__ img, float* __restrict__ out, int H, int W,
+                                           int item) {
+  const int xt = (W + kWave - 1) / kWave;
+  const int y0 = (item / xt) * kRowsPerWg;
+  const int x0 = (item % xt) * kWave;
   const float scale = 1.0f / 65535.0f;
   for (int i = threadIdx.x; i < kPixRows * kPixCols; i += blockDim.x) {
     const int r = i / kPixCols, c = i - r * kPixCols;
@@ -86,29 +90,53 @@ __global__ __launch_bounds__(256) void stack_kernel(const uint16_t* __restrict__
   wave_lds_sync();
 
   const int y = y0 + w;
-  if (y >= H) return;
-  const int n_pos = min(kWave, W - x0);             // positions of this row in the tile
-  float4* dst = reinterpret_cast<float4*>(out + (static_cast<size_t>(y) * W + x0) * 64);
-  // 16 rounds; in round i lane l stores float4 g = i*64 + l of the run
+  if (y < H) {
+    const int n_pos = min(kWave, W - x0);  // positions of this row in the tile
+    float4* dst = reinterpret_cast<float4*>(out + (static_cast<size_t>(y) * W + x0) * 64);
+    // 16 rounds; in round i lane l stores float4 g = i*64 + l of the run
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int g = i * kWave + lane;
-    const int blk = g >> 4, c = (g & 15) * 4;
-    if (blk < n_pos) {
-      const float* s = stage[w] + blk * kStagePitch + c;
-      dst[g] = make_float4(s[0], s[1], s[2], s[3]);
+    for (int i = 0; i < 16; ++i) {
+      const int g = i * kWave + lane;
+      const int blk = g >> 4, c = (g & 15) * 4;
+      if (blk < n_pos) {
+        const float* s = stage[w] + blk * kStagePitch + c;
+        dst[g] = make_float4(s[0], s[1], s[2], s[3]);
+      }
     }
   }
+  __syncthreads();  // the pixel tile and the staging area are reused
+}
+
+// src_sel: 0 = noisy, 1 = pilot; dst_sel: 0 = stack_a, 1 = stack_b
+template <int KIND, bool BATCH>
+__global__ __launch_bounds__(256) void stack_kernel(ImgRec one, WorkList wl, int src_sel, int dst_sel) {
+  __shared__ float pix[kPixRows][kPixCols + 1];
+  __shared__ float stage[kRowsPerWg][kWave * kStagePitch];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
+    stack_body<KIND>(pix, stage, src_sel ? r.pilot : r.noisy, dst_sel ? r.stack_b : r.stack_a, r.H, r.W, item);
+  });
 }
 
 }  // namespace
 
-hipError_t launch_stack(const uint16_t* img, int H, int W, int kind, float* out, hipStream_t st) {
-  dim3 grid((W + kWave - 1) / kWave, (H + kRowsPerWg - 1) / kRowsPerWg);
-  if (kind == 0)
-    hipLaunchKernelGGL(stack_kernel<0>, grid, dim3(256), 0, st, img, H, W, out);
-  else
-    hipLaunchKernelGGL(stack_kernel<1>, grid, dim3(256), 0, st, img, H, W, out);
+int stack_items_for(int H, int W) { return stack_items(H, W); }
+
+hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src_sel, int dst_sel, int grid_cap,
+                        hipStream_t st) {
+  if (!wl) {
+    const int items = stack_items(one.H, one.W);
+    if (kind == 0)
+      hipLaunchKernelGGL((stack_kernel<0, false>), dim3(items), dim3(256), 0, st, one, WorkList{}, src_sel, dst_sel);
+    else
+      hipLaunchKernelGGL((stack_kernel<1, false>), dim3(items), dim3(256), 0, st, one, WorkList{}, src_sel, dst_sel);
+  } else {
+    if (wl->total <= 0) return hipSuccess;
+    const int grid = std::min(wl->total, grid_cap);
+    if (kind == 0)
+      hipLaunchKernelGGL((stack_kernel<0, true>), dim3(grid), dim3(256), 0, st, one, *wl, src_sel, dst_sel);
+    else
+      hipLaunchKernelGGL((stack_kernel<1, true>), dim3(grid), dim3(256), 0, st, one, *wl, src_sel, dst_sel);
+  }
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgbm3d.so")
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+BATCH_GRAPH, BATCH_BASIC_ONLY = 1, 2
 W_TV, W_NNZ, W_UNIT = 0, 1, 2
 STACK_BIOR15, STACK_DCT = 0, 1
 
@@ -34,6 +35,17 @@ class Params(ctypes.Structure):
         ("tv_eps_rel", ctypes.c_float),
         ("keep_dc", ctypes.c_int32),
         ("bm_split", ctypes.c_int32),
+    ]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [
+        ("noisy", ctypes.c_void_p),
+        ("pilot", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("H", ctypes.c_int32),
+        ("W", ctypes.c_int32),
+        ("sigma", ctypes.c_float),
     ]
 
 
@@ -64,6 +76,7 @@ _SIGNATURES = {
     "gbm3d_wiener": (_I, [_P, _P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P]),
     "gbm3d_denoise": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P, _P, _P]),
     "gbm3d_quantize": (_I, [_P, _P, _P, ctypes.c_size_t, _P]),
+    "gbm3d_denoise_batch": (_I, [_P, ctypes.POINTER(Image), _I, ctypes.POINTER(Params), _I, _P]),
     "gbm3d_timing_enable": (_I, [_P, _I]),
     "gbm3d_timing_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)]),
@@ -216,6 +229,33 @@ class Context:
                                         self._params(params), _dev(out, torch.float32, "out"), b, q,
                                         _stream(stream)))
         return out
+
+    def denoise_batch(self, noisy, sigmas, pilots=None, outs=None, params: Params | None = None,
+                      graph: bool = False, basic_only: bool = False, stream=None):
+        """Denoise a list of uint16 CUDA images of any sizes in one batch.
+
+        pilots: optional list (entries may be None) of uint16 pilots for stage 2;
+        basic_only: stage 1 only.  Returns the list of float32 outputs."""
+        n = len(noisy)
+        if len(sigmas) != n:
+            raise ValueError("one sigma per image")
+        pilots = pilots if pilots is not None else [None] * n
+        if outs is None:
+            outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in noisy]
+        arr = (Image * max(n, 1))()
+        for i, (x, s, pl, o) in enumerate(zip(noisy, sigmas, pilots, outs)):
+            H, W = _hw(x)
+            arr[i].noisy = _dev(x, torch.uint16, "noisy").value
+            arr[i].pilot = _dev(pl, torch.uint16, "pilot").value if pl is not None else None
+            if pl is not None and tuple(pl.shape) != (H, W):
+                raise ValueError("pilot shape differs from noisy")
+            if tuple(o.shape) != (H, W):
+                raise ValueError("output shape differs from noisy")
+            arr[i].out = _dev(o, torch.float32, "out").value
+            arr[i].H, arr[i].W, arr[i].sigma = H, W, float(s)
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_BASIC_ONLY if basic_only else 0)
+        self._check(lib().gbm3d_denoise_batch(self._h, arr, n, self._params(params), flags, _stream(stream)))
+        return outs
 
     def timing(self, on: bool = True):
         self._check(lib().gbm3d_timing_enable(self._h, 1 if on else 0))

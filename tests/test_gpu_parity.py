@@ -335,3 +335,75 @@ def test_match_workgroup_shapes_agree(torch, G, ctx, split):
     exp = O.match(Z, 16, O.DEFAULT.with_(search=21))
     got = ctx.match(up(torch, Z), 16, G.default_params(search=21), split=split).cpu().numpy().astype(np.int64)
     assert np.array_equal(got, exp)
+
+
+# ---------------------------------------------------------------------------
+# batches (persistent launches over per-image work lists, hipGraph replay)
+# ---------------------------------------------------------------------------
+
+def _batch_inputs(torch, n, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    imgs, sig = [], []
+    for i in range(n):
+        H, W = int(rng.integers(lo, hi + 1)), int(rng.integers(lo, hi + 1))
+        s = float(rng.uniform(10, 50) / 255)
+        _, Z = synth.make_case(H, W, s, seed + 1 + i)
+        imgs.append(up(torch, Z))
+        sig.append(s)
+    return imgs, sig
+
+
+def test_batch_equals_single_calls(torch, G, ctx):
+    """Uneven sizes (incl. ragged and minimum), mixed pilots: every batch output
+    equals the single-image call bit for bit."""
+    say("batch vs single")
+    imgs, sig = _batch_inputs(torch, 7, 39, 150, 700)
+    pil = [None, None, up(torch, synth.to_u16(np.random.default_rng(1).random(tuple(imgs[2].shape)))), None,
+           None, None, None]
+    outs = ctx.denoise_batch(imgs, sig, pilots=pil)
+    torch.cuda.synchronize()
+    for i, (x, s, pl) in enumerate(zip(imgs, sig, pil)):
+        ref = ctx.denoise(x, s) if pl is None else ctx.wiener(x, pl, s)
+        assert np.array_equal(outs[i].cpu().numpy(), ref.cpu().numpy()), i
+    basic = ctx.denoise_batch(imgs[:3], sig[:3], basic_only=True)
+    for i in range(3):
+        assert np.array_equal(basic[i].cpu().numpy(), ctx.basic(imgs[i], sig[i]).cpu().numpy())
+
+
+def test_batch_graph_replays_match_eager(torch, G, ctx):
+    """Captured once, replayed several times with eager work and syncs in
+    between; every replay equals the eager batch."""
+    say("batch graph")
+    imgs, sig = _batch_inputs(torch, 5, 40, 120, 800)
+    eager = [o.cpu().numpy() for o in ctx.denoise_batch(imgs, sig)]
+    outs = [torch.full(tuple(x.shape), -1.0, device="cuda") for x in imgs]
+    for rep in range(4):
+        for o in outs:
+            o.fill_(-1.0)
+        ctx.denoise_batch(imgs, sig, outs=outs, graph=True)
+        torch.cuda.synchronize()
+        _ = ctx.denoise(imgs[0], sig[0])          # eager work between replays
+        torch.cuda.synchronize()
+        for i in range(len(imgs)):
+            assert np.array_equal(outs[i].cpu().numpy(), eager[i]), (rep, i)
+    # new output buffers, same shapes: the graph is reused with the new pointers
+    outs2 = [torch.empty(tuple(x.shape), device="cuda") for x in imgs]
+    ctx.denoise_batch(imgs, sig, outs=outs2, graph=True)
+    torch.cuda.synchronize()
+    for i in range(len(imgs)):
+        assert np.array_equal(outs2[i].cpu().numpy(), eager[i])
+
+
+def test_batch_oracle_psnr(torch, G, ctx):
+    """Batch outputs against the oracle's own two-stage run (PSNR within 0.01 dB)."""
+    rng = np.random.default_rng(900)
+    cases = [synth.make_case(int(h), int(w), s, 901 + i)
+             for i, (h, w, s) in enumerate(zip(rng.integers(48, 90, 3), rng.integers(48, 90, 3),
+                                               rng.uniform(10, 50, 3) / 255))]
+    sig = [float(s) for s in rng.uniform(10, 50, 3) / 255]
+    cases = [synth.make_case(c[1].shape[0], c[1].shape[1], s, 911 + i) for i, (c, s) in enumerate(zip(cases, sig))]
+    p = G.default_params(search=21)
+    outs = ctx.denoise_batch([up(torch, Z) for _, Z in cases], sig, params=p)
+    for (clean, Z), s, o in zip(cases, sig, outs):
+        Y, _, _ = O.denoise(Z, s, O.DEFAULT.with_(search=21))
+        assert abs(O.psnr(o.cpu().numpy().astype(np.float64), clean) - O.psnr(Y, clean)) <= PSNR_TOL
