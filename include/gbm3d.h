@@ -173,6 +173,40 @@ int gbm3d_denoise_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n,
  * evaluated in double from the float input; NaN -> 0.  Device pointers. */
 int gbm3d_quantize(gbm3d_ctx* ctx, const float* in, uint16_t* out, size_t n, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned pilot: a six-layer 3x3 convolutional network (2 -> 32 -> 32 -> 32 ->
+ * 32 -> 32 -> 1 channels, ReLU after the first five, zero "same" padding,
+ * input (z, sigma plane), output pilot = z - f) that can stand in for stage 1
+ * as the first estimate the Wiener stage needs (Sec. 4).  bf16 weights and
+ * activations, fp32 accumulation on the matrix cores.  Parameters live in a
+ * float32 master vector of gbm3d_pilot_param_count() entries: per layer
+ * W[ky][kx][ci][co] (row-major) followed by bias[co].
+ * ------------------------------------------------------------------------- */
+int gbm3d_pilot_param_count(void);
+
+/* Packs the master vector (device float [P]) into the context's bf16 weights. */
+int gbm3d_pilot_load(gbm3d_ctx* ctx, const float* master, void* stream);
+
+/* Pilot of B images noisy [B][H][W] (device u16) with noise levels sigma
+ * (device float [B]).  pilot_u16 (device u16 [B][H][W], the quantised pilot
+ * floor(clip(p,0,1)*65535 + 1/2)) and/or pilot_f32 (device float) may be NULL.
+ * Needs gbm3d_pilot_load first. */
+int gbm3d_pilot_infer(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W,
+                      const float* sigma, uint16_t* pilot_u16, float* pilot_f32, void* stream);
+
+/* Training: mean squared error of the pilot against target (device float
+ * [B][H][W]) written to *loss (device float), and its gradient with respect
+ * to the master vector into grad (device float [P]), with the loaded weights.
+ * H and W >= 1. */
+int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target, int B, int H, int W,
+                     const float* sigma, float* grad, float* loss, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on the master vector with moments
+ * m, v (device float [P], zero before the first step), then reloads the
+ * packed weights. */
+int gbm3d_pilot_adam(gbm3d_ctx* ctx, float* master, float* m, float* v, const float* grad, int step,
+                     float lr, float beta1, float beta2, float eps, void* stream);
+
 /* Per-kernel timing for benchmarking.  While enabled, the context brackets
  * every kernel it launches with two HIP events recorded on the launch stream.
  * gbm3d_timing_read synchronises the pending events and returns, for one

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgbm3d.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["bm.hip", "stack.hip", "group.hip", "capi.cpp"]
+SOURCES = ["bm.hip", "stack.hip", "group.hip", "pilot.hip", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

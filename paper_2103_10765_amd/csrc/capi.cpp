@@ -16,6 +16,7 @@
 
 #include "../../include/gbm3d.h"
 #include "kernels.h"
+#include "pilot.h"
 
 using gbm3d::ImgRec;
 using gbm3d::WorkList;
@@ -64,6 +65,9 @@ struct gbm3d_ctx {
   hipEvent_t table_copied = nullptr;
   hipStream_t capture_stream = nullptr;
   GraphEntry graph;
+  // learned pilot
+  Buffer pilot_w, pilot_act, pilot_part;
+  bool pilot_loaded = false;
   // per-kernel timing (off by default)
   bool timing = false;
   std::vector<TimingRecord> pending;
@@ -523,7 +527,7 @@ void gbm3d_destroy(gbm3d_ctx* ctx) {
     (void)hipDeviceSynchronize();
     drop_graph(ctx);
     for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->batch_ws,
-                      &ctx->batch_table})
+                      &ctx->batch_table, &ctx->pilot_w, &ctx->pilot_act, &ctx->pilot_part})
       if (b->p) (void)hipFree(b->p);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
@@ -710,6 +714,159 @@ int gbm3d_quantize(gbm3d_ctx* ctx, const float* in, uint16_t* out, size_t n, voi
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
   HIP_TRY(ctx, gbm3d::launch_quantize(in, out, n, static_cast<hipStream_t>(stream)), "quantize launch");
   return GBM3D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned pilot
+// ---------------------------------------------------------------------------
+
+int gbm3d_pilot_param_count(void) { return gbm3d::kPilotParams; }
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kPilotC = 32;
+
+struct PilotWeights {
+  uint16_t* wf;   // [layer][9][32][32] forward
+  uint16_t* wb;   // [layer][9][32][32] input gradient
+  float* bias;    // [layer][32]
+};
+
+PilotWeights pilot_weights(gbm3d_ctx* ctx) {
+  char* base = static_cast<char*>(ctx->pilot_w.p);
+  const size_t half = gbm3d::pilot_packed_bytes() / 2;
+  return {reinterpret_cast<uint16_t*>(base), reinterpret_cast<uint16_t*>(base + half),
+          reinterpret_cast<float*>(base + 2 * half)};
+}
+
+size_t act_bytes(int B, int H, int W) { return static_cast<size_t>(B) * H * W * kPilotC * sizeof(uint16_t); }
+
+int check_pilot_shape(gbm3d_ctx* ctx, int B, int H, int W) {
+  if (B < 1 || H < 1 || W < 1 || H > 32768 || W > 32768)
+    return fail(ctx, GBM3D_EINVAL, "pilot batch %dx%dx%d invalid", B, H, W);
+  if (static_cast<double>(B) * H * W > 2.0e9) return fail(ctx, GBM3D_EINVAL, "pilot batch too large");
+  if (!ctx->pilot_loaded) return fail(ctx, GBM3D_EINVAL, "no pilot weights loaded (gbm3d_pilot_load)");
+  return GBM3D_OK;
+}
+
+// forward pass; keep_all: acts[l] of every layer input kept (training)
+int pilot_forward(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W, const float* sigma, bool keep_all,
+                  uint16_t* pilot_u16, float* pilot_f32, hipStream_t st) {
+  const size_t ab = act_bytes(B, H, W);
+  const PilotWeights pw = pilot_weights(ctx);
+  char* act = static_cast<char*>(ctx->pilot_act.p);
+  auto buf = [&](int l) { return reinterpret_cast<uint16_t*>(act + (keep_all ? l : (l & 1)) * ab); };
+  const int cap = 4 * ctx->n_cu;
+  HIP_TRY(ctx, timed(ctx, "pilot_prep", st, [&] { return gbm3d::launch_pilot_prep(noisy, sigma, B, H, W, buf(0), st); }),
+          "pilot input");
+  for (int l = 0; l < gbm3d::kPilotLayers; ++l) {
+    const bool last = l == gbm3d::kPilotLayers - 1;
+    const uint16_t* w = pw.wf + static_cast<size_t>(l) * 9 * kPilotC * kPilotC;
+    HIP_TRY(ctx, timed(ctx, "pilot_conv", st, [&] {
+              return gbm3d::launch_pilot_conv(last ? 1 : 0, buf(l), w, pw.bias + l * kPilotC, nullptr,
+                                              last ? nullptr : buf(l + 1), noisy, pilot_f32, pilot_u16, B, H, W, cap,
+                                              st);
+            }),
+            "pilot conv");
+  }
+  return GBM3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gbm3d_pilot_load(gbm3d_ctx* ctx, const float* master, void* stream) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!master) return fail(ctx, GBM3D_EINVAL, "NULL master vector");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  CHECK(ensure(ctx, ctx->pilot_w, gbm3d::pilot_packed_bytes() + gbm3d::kPilotLayers * kPilotC * sizeof(float),
+               "pilot weights"));
+  const PilotWeights pw = pilot_weights(ctx);
+  HIP_TRY(ctx, gbm3d::launch_pilot_pack(master, pw.wf, pw.wb, pw.bias, static_cast<hipStream_t>(stream)),
+          "pilot pack");
+  ctx->pilot_loaded = true;
+  return GBM3D_OK;
+}
+
+int gbm3d_pilot_infer(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W, const float* sigma,
+                      uint16_t* pilot_u16, float* pilot_f32, void* stream) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!noisy || !sigma || (!pilot_u16 && !pilot_f32)) return fail(ctx, GBM3D_EINVAL, "NULL input or no output");
+  CHECK(check_pilot_shape(ctx, B, H, W));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  CHECK(ensure(ctx, ctx->pilot_act, 2 * act_bytes(B, H, W), "pilot activations"));
+  return pilot_forward(ctx, noisy, B, H, W, sigma, false, pilot_u16, pilot_f32, static_cast<hipStream_t>(stream));
+}
+
+int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target, int B, int H, int W,
+                     const float* sigma, float* grad, float* loss, void* stream) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!noisy || !target || !sigma || !grad || !loss) return fail(ctx, GBM3D_EINVAL, "NULL argument");
+  CHECK(check_pilot_shape(ctx, B, H, W));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t ab = act_bytes(B, H, W);
+  const size_t npix = static_cast<size_t>(B) * H * W;
+  // layout: acts x0..x5 | grad ping-pong g0, g1 | pilot f32
+  CHECK(ensure(ctx, ctx->pilot_act, 8 * ab + align256(npix * sizeof(float)), "pilot training activations"));
+  const int wg_grid = 2 * ctx->n_cu;
+  const int loss_blocks = 1024;
+  CHECK(ensure(ctx, ctx->pilot_part,
+               gbm3d::pilot_wgrad_partial_floats(wg_grid) * sizeof(float) + loss_blocks * sizeof(double),
+               "pilot partial sums"));
+  char* act = static_cast<char*>(ctx->pilot_act.p);
+  auto x = [&](int l) { return reinterpret_cast<uint16_t*>(act + l * ab); };
+  uint16_t* gbuf[2] = {reinterpret_cast<uint16_t*>(act + 6 * ab), reinterpret_cast<uint16_t*>(act + 7 * ab)};
+  float* pil = reinterpret_cast<float*>(act + 8 * ab);
+  float* wpart = static_cast<float*>(ctx->pilot_part.p);
+  double* lpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->pilot_part.p) +
+                                            gbm3d::pilot_wgrad_partial_floats(wg_grid) * sizeof(float));
+  CHECK(pilot_forward(ctx, noisy, B, H, W, sigma, true, nullptr, pil, st));
+  HIP_TRY(ctx, timed(ctx, "pilot_loss", st, [&] {
+            return gbm3d::launch_pilot_loss(pil, target, npix, gbuf[0], lpart, loss_blocks, loss, st);
+          }),
+          "pilot loss");
+  const PilotWeights pw = pilot_weights(ctx);
+  const int cap = 4 * ctx->n_cu;
+  int cur = 0;
+  for (int l = gbm3d::kPilotLayers - 1; l >= 0; --l) {
+    HIP_TRY(ctx, timed(ctx, "pilot_wgrad", st, [&] {
+              return gbm3d::launch_pilot_wgrad(x(l), gbuf[cur], B, H, W, wg_grid, wpart, l,
+                                               grad + gbm3d::pilot_layer_offset(l), st);
+            }),
+            "pilot weight gradient");
+    if (l > 0) {
+      const uint16_t* w = pw.wb + static_cast<size_t>(l) * 9 * kPilotC * kPilotC;
+      HIP_TRY(ctx, timed(ctx, "pilot_dgrad", st, [&] {
+                return gbm3d::launch_pilot_conv(2, gbuf[cur], w, nullptr, x(l), gbuf[cur ^ 1], nullptr, nullptr,
+                                                nullptr, B, H, W, cap, st);
+              }),
+              "pilot input gradient");
+      cur ^= 1;
+    }
+  }
+  return GBM3D_OK;
+}
+
+int gbm3d_pilot_adam(gbm3d_ctx* ctx, float* master, float* m, float* v, const float* grad, int step, float lr,
+                     float beta1, float beta2, float eps, void* stream) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!master || !m || !v || !grad) return fail(ctx, GBM3D_EINVAL, "NULL argument");
+  if (step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return fail(ctx, GBM3D_EINVAL, "bad Adam hyper-parameters");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, gbm3d::launch_pilot_adam(master, m, v, grad, gbm3d::kPilotParams, lr, beta1, beta2, eps, step, st),
+          "adam");
+  return gbm3d_pilot_load(ctx, master, stream);
 }
 
 int gbm3d_timing_enable(gbm3d_ctx* ctx, int on) {

@@ -77,6 +77,11 @@ _SIGNATURES = {
     "gbm3d_denoise": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P, _P, _P]),
     "gbm3d_quantize": (_I, [_P, _P, _P, ctypes.c_size_t, _P]),
     "gbm3d_denoise_batch": (_I, [_P, ctypes.POINTER(Image), _I, ctypes.POINTER(Params), _I, _P]),
+    "gbm3d_pilot_param_count": (_I, []),
+    "gbm3d_pilot_load": (_I, [_P, _P, _P]),
+    "gbm3d_pilot_infer": (_I, [_P, _P, _I, _I, _I, _P, _P, _P, _P]),
+    "gbm3d_pilot_grad": (_I, [_P, _P, _P, _I, _I, _I, _P, _P, _P, _P]),
+    "gbm3d_pilot_adam": (_I, [_P, _P, _P, _P, _P, _I, _F, _F, _F, _F, _P]),
     "gbm3d_timing_enable": (_I, [_P, _I]),
     "gbm3d_timing_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)]),
@@ -108,6 +113,10 @@ def default_params(**overrides) -> Params:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def pilot_param_count() -> int:
+    return int(lib().gbm3d_pilot_param_count())
 
 
 def n_refs(H: int, W: int, step: int = 3) -> int:
@@ -257,6 +266,50 @@ class Context:
         self._check(lib().gbm3d_denoise_batch(self._h, arr, n, self._params(params), flags, _stream(stream)))
         return outs
 
+    # -- learned pilot -----------------------------------------------------
+    def pilot_load(self, master: torch.Tensor, stream=None):
+        if master.numel() != pilot_param_count():
+            raise ValueError("master vector has the wrong length")
+        self._check(lib().gbm3d_pilot_load(self._h, _dev(master, torch.float32, "master"), _stream(stream)))
+
+    def pilot_infer(self, noisy: torch.Tensor, sigma: torch.Tensor, u16: bool = True, f32: bool = False,
+                    stream=None):
+        """noisy: [B, H, W] uint16 CUDA; sigma: [B] float32 CUDA.  Returns (u16, f32) outputs."""
+        if noisy.dim() != 3:
+            raise ValueError("noisy must be [B, H, W]")
+        B, H, W = (int(v) for v in noisy.shape)
+        if sigma.numel() != B:
+            raise ValueError("one sigma per image")
+        pu = torch.empty((B, H, W), dtype=torch.uint16, device=noisy.device) if u16 else None
+        pf = torch.empty((B, H, W), dtype=torch.float32, device=noisy.device) if f32 else None
+        self._check(lib().gbm3d_pilot_infer(self._h, _dev(noisy, torch.uint16, "noisy"), B, H, W,
+                                            _dev(sigma, torch.float32, "sigma"),
+                                            _dev(pu, torch.uint16, "pilot_u16") if pu is not None else None,
+                                            _dev(pf, torch.float32, "pilot_f32") if pf is not None else None,
+                                            _stream(stream)))
+        return pu, pf
+
+    def pilot_grad(self, noisy: torch.Tensor, target: torch.Tensor, sigma: torch.Tensor, grad=None, loss=None,
+                   stream=None):
+        B, H, W = (int(v) for v in noisy.shape)
+        if tuple(target.shape) != (B, H, W) or sigma.numel() != B:
+            raise ValueError("shape mismatch")
+        if grad is None:
+            grad = torch.empty(pilot_param_count(), dtype=torch.float32, device=noisy.device)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=noisy.device)
+        self._check(lib().gbm3d_pilot_grad(self._h, _dev(noisy, torch.uint16, "noisy"),
+                                           _dev(target, torch.float32, "target"), B, H, W,
+                                           _dev(sigma, torch.float32, "sigma"), _dev(grad, torch.float32, "grad"),
+                                           _dev(loss, torch.float32, "loss"), _stream(stream)))
+        return grad, loss
+
+    def pilot_adam(self, master, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self._check(lib().gbm3d_pilot_adam(self._h, _dev(master, torch.float32, "master"),
+                                           _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"),
+                                           _dev(grad, torch.float32, "grad"), int(step), float(lr), float(beta1),
+                                           float(beta2), float(eps), _stream(stream)))
+
     def timing(self, on: bool = True):
         self._check(lib().gbm3d_timing_enable(self._h, 1 if on else 0))
 
@@ -297,3 +350,11 @@ def denoise(noisy: torch.Tensor, sigma: float, params: Params | None = None) -> 
 def basic(noisy: torch.Tensor, sigma: float, params: Params | None = None) -> torch.Tensor:
     """Stage 1 only (basic estimate)."""
     return context(noisy.device.index).basic(noisy, sigma, params)
+
+
+def psnr_db(Y, clean) -> float:
+    """10 log10(1 / MSE) of clip(Y, 0, 1) against a clean [0, 1] image (NumPy arrays)."""
+    import numpy as np
+    Y = np.clip(np.asarray(Y, dtype=np.float64), 0.0, 1.0)
+    mse = float(np.mean((Y - np.asarray(clean, dtype=np.float64)) ** 2))
+    return 10.0 * np.log10(1.0 / mse)

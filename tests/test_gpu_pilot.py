@@ -1,0 +1,121 @@
+"""GPU parity of the learned pilot against the fp64 oracle (bf16 rounding
+emulated where the kernels round): forward within max-abs 1e-2 on the [0, 1]
+scale, gradients within a few percent (bf16 operands in the backward
+products), and training steps that reduce the loss."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pilot_oracle as P
+from paper_2103_10765_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    return t
+
+
+@pytest.fixture(scope="module")
+def G(torch):
+    from paper_2103_10765_amd import gbm3d
+    return gbm3d
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _theta(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in P.LAYERS:
+        parts += [rng.standard_normal(9 * ci * co) * np.sqrt(2.0 / (9 * ci)) * scale, rng.standard_normal(co) * 0.05]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _batch(B, H, W, seed):
+    zs, sig = [], []
+    for i in range(B):
+        s = (15 + 10 * i) / 255
+        _, Z = synth.make_case(H, W, s, seed + i)
+        zs.append(Z)
+        sig.append(s)
+    return np.stack(zs), np.array(sig, dtype=np.float32)
+
+
+def test_pilot_zero_network_is_identity(torch, G, ctx):
+    theta = torch.zeros(G.pilot_param_count(), device="cuda")
+    ctx.pilot_load(theta)
+    Z, sig = _batch(2, 19, 45, 10)
+    pu, pf = ctx.pilot_infer(torch.from_numpy(Z).cuda(), torch.from_numpy(sig).cuda(), f32=True)
+    assert np.abs(pf.cpu().numpy() - Z / 65535.0).max() < 1e-6
+    assert np.array_equal(pu.cpu().numpy(), Z)
+
+
+@pytest.mark.parametrize("shape", [(2, 20, 37), (1, 8, 32), (3, 33, 70)])
+def test_pilot_forward_parity(torch, G, ctx, shape):
+    B, H, W = shape
+    say("pilot forward", shape)
+    theta = _theta(1)
+    ctx.pilot_load(torch.from_numpy(theta).cuda())
+    Z, sig = _batch(B, H, W, 20)
+    pu, pf = ctx.pilot_infer(torch.from_numpy(Z).cuda(), torch.from_numpy(sig).cuda(), f32=True)
+    ref, _ = P.forward(theta.astype(np.float64), Z / 65535.0, sig, bf16=True)
+    err = np.abs(pf.cpu().numpy() - ref)
+    assert err.max() <= 1e-2, err.max()
+    assert np.median(err) <= 1e-3
+    q = np.floor(np.clip(pf.cpu().numpy().astype(np.float64), 0, 1) * 65535 + 0.5).astype(np.uint16)
+    assert np.array_equal(pu.cpu().numpy(), q)
+
+
+def test_pilot_gradient_parity(torch, G, ctx):
+    B, H, W = 2, 16, 40
+    say("pilot gradient")
+    theta = _theta(2)
+    ctx.pilot_load(torch.from_numpy(theta).cuda())
+    Z, sig = _batch(B, H, W, 30)
+    target = np.random.default_rng(3).random((B, H, W)).astype(np.float32)
+    grad, loss = ctx.pilot_grad(torch.from_numpy(Z).cuda(), torch.from_numpy(target).cuda(), torch.from_numpy(sig).cuda())
+    lo, go = P.loss_and_grad(theta.astype(np.float64), Z / 65535.0, sig, target, bf16=True)
+    assert abs(loss.item() - lo) <= 1e-2 * lo
+    g = grad.cpu().numpy().astype(np.float64)
+    o = 0
+    for l, (ci, co) in enumerate(P.LAYERS):
+        n = 9 * ci * co + co
+        a, b = g[o:o + n], go[o:o + n]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        say("layer", l, "relative gradient error", rel)
+        assert rel <= 5e-2, (l, rel)
+        o += n
+
+
+def test_pilot_training_reduces_loss(torch, G, ctx):
+    B, H, W = 4, 32, 32
+    theta = torch.from_numpy(_theta(4, scale=0.5)).cuda()
+    ctx.pilot_load(theta)
+    Z, sig = _batch(B, H, W, 40)
+    Zt, st = torch.from_numpy(Z).cuda(), torch.from_numpy(sig).cuda()
+    target = torch.from_numpy(np.stack([synth.clean_image(H, W, 40 + i) for i in range(B)]).astype(np.float32)).cuda()
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    losses = []
+    for step in range(1, 41):
+        grad, loss = ctx.pilot_grad(Zt, target, st)
+        losses.append(loss.item())
+        ctx.pilot_adam(theta, m, v, grad, step, 1e-3)
+    say("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.7 * losses[0]
