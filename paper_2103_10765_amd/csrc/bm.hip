@@ -20,8 +20,14 @@
 //
 // A workgroup of four waves covers RPW reference rows x SPLIT parts of the
 // displacement rows (RPW * SPLIT = 4) and shares one LDS image tile with the
-// search halo.  With SPLIT > 1 the partial lists of a row are merged through
-// LDS at the end.
+// search halo.  The tile is held as uint16 in three sub-arrays by column
+// residue mod 3, so the 64 lanes of a wave, whose columns are 3 apart, read
+// 64 consecutive halfwords (no bank conflicts).  With SPLIT > 1 the waves of a
+// row publish their current worst kept key so every wave prunes with the
+// row's best bound, and the partial lists are merged at the end by a bitonic
+// network in registers.  LDS stays under 40 KB per workgroup, so residency is
+// bounded by registers (the float64 reference block, six prefetched columns
+// and the sorted list), not by LDS.
 #include "common.h"
 #include "kernels.h"
 
@@ -30,10 +36,10 @@ namespace gbm3d {
 namespace {
 
 constexpr int kLanesOut = 62;
-constexpr int kTileCols = 3 * kWave + 2 + 2 * kMaxR + 8;  // 238: columns 3q0-R .. (slack for prefetch)
-constexpr int kBuf = 12;                                   // buffered candidates per lane
-constexpr int kFlushAt = kBuf - 3;                         // an iteration appends at most 3
+constexpr int kSubCols = 80;  // per residue: columns 3j+m for j < 80 (needs 3*63 + 2*kMaxR + 8)
 constexpr double kInf = __builtin_huge_val();
+
+static_assert(3 * kSubCols >= 3 * (kWave - 1) + 2 + (2 * kMaxR + 1 + 5) + 1, "tile too narrow");
 
 template <int RPW>
 struct TileShape {
@@ -56,13 +62,19 @@ __device__ __forceinline__ double from_next_lane(double v) {
   return __hiloint2double(nhi, nlo);
 }
 
-template <int K, int RPW>
+template <int K, int RPW, int SPLIT>
 struct BmSmem {
   static constexpr int L = K - 1;
-  static constexpr size_t kTile = sizeof(float) * TileShape<RPW>::rows * kTileCols;
-  static constexpr size_t kScan = kTile + sizeof(double) * 4 * kBuf * kWave;
-  static constexpr size_t kMerge = sizeof(double) * 4 * (L > 0 ? L : 1) * kWave;
+  static constexpr int kBuf = RPW == 1 ? 8 : 7;  // buffered candidates per lane
+  static constexpr int kFlushAt = kBuf - 3;      // an iteration appends at most 3
+  static constexpr size_t kTile = sizeof(uint16_t) * 3 * TileShape<RPW>::rows * kSubCols;
+  static constexpr size_t kBufBytes = sizeof(double) * 4 * kBuf * kWave;
+  static constexpr size_t kBound = SPLIT > 1 ? sizeof(double) * 4 * kWave : 0;
+  static constexpr size_t kScan = kTile + kBufBytes + kBound;
+  // merge: SPLIT 4 exchanges two lists at a time, SPLIT 2 one per row (2 rows)
+  static constexpr size_t kMerge = SPLIT > 1 ? sizeof(double) * 2 * L * kWave : 0;
   static constexpr size_t bytes = kScan > kMerge ? kScan : kMerge;
+  static_assert(bytes <= 40960, "LDS no larger than a quarter of a CU");
 };
 
 __host__ __device__ constexpr int bm_segments(int W) { return ((W + kStep - 1) / kStep + kLanesOut - 1) / kLanesOut; }
@@ -72,14 +84,45 @@ __host__ __device__ constexpr int bm_items(int H, int W) {
   return (((H + kStep - 1) / kStep) + RPW - 1) / RPW * bm_segments(W);
 }
 
+// list := the L smallest of list and the sorted list b[0..L) (stride kWave):
+// with a = list + [inf] and b reversed, c[i] = min(a[i], b[P-1-i]) is bitonic
+// and holds the P = L+1 smallest of both; a half-cleaner cascade sorts it.
+template <int L>
+__device__ __forceinline__ void merge_lists(double (&list)[L], const double* b) {
+  constexpr int P = L + 1;
+  static_assert((P & (P - 1)) == 0, "K is a power of two");
+  double c[P];
+  c[0] = list[0];
+#pragma unroll
+  for (int i = 1; i < L; ++i) c[i] = fmin(list[i], b[(L - i) * kWave]);
+  c[L] = b[0];
+#pragma unroll
+  for (int s = P / 2; s >= 1; s >>= 1)
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      if (!(i & s)) {
+        const double lo = fmin(c[i], c[i + s]), hi = fmax(c[i], c[i + s]);
+        c[i] = lo;
+        c[i + s] = hi;
+      }
+#pragma unroll
+  for (int i = 0; i < L; ++i) list[i] = c[i];
+}
+
 // One work item: reference rows [RPW*pb, RPW*pb + RPW) x 62 reference columns.
 template <int K, int RPW, int SPLIT>
 __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __restrict__ img,
                                         int16_t* __restrict__ idx, int H, int W, int R, int item) {
   static_assert(RPW * SPLIT == 4, "four waves per workgroup");
+  using Smem = BmSmem<K, RPW, SPLIT>;
   constexpr int L = K - 1;
-  float(*tile)[kTileCols] = reinterpret_cast<float(*)[kTileCols]>(smem);
-  double* buf = reinterpret_cast<double*>(smem + BmSmem<K, RPW>::kTile);
+  constexpr int kBuf = Smem::kBuf;
+  constexpr int rows = TileShape<RPW>::rows;
+  // sub[m][r][j] = tile pixel (row r, column 3j + m)
+  uint16_t* sub = reinterpret_cast<uint16_t*>(smem);
+  double* buf = reinterpret_cast<double*>(smem + Smem::kTile);
+  // bound[w][lane]: the worst key of wave w's current list for its reference
+  unsigned long long* bound = reinterpret_cast<unsigned long long*>(smem + Smem::kTile + Smem::kBufBytes);
 
   const int nRy = (H + kStep - 1) / kStep, nRx = (W + kStep - 1) / kStep;
   const int segs = bm_segments(W);
@@ -94,20 +137,25 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
   // LDS image tile, periodic: rows 3p0-R .. 3(p0+RPW-1)+7+R, columns 3q0-R ..
   const int y0 = kStep * p0 - R;
   const int x0 = kStep * q0 - R;
-  const int rows = kStep * (RPW - 1) + kPatch + 2 * R;
-  for (int i = threadIdx.x; i < rows * kTileCols; i += blockDim.x) {
-    const int r = i / kTileCols, c = i - r * kTileCols;
+  const int nrows = kStep * (RPW - 1) + kPatch + 2 * R;
+  for (int i = threadIdx.x; i < nrows * 3 * kSubCols; i += blockDim.x) {
+    const int r = i / (3 * kSubCols), c = i - r * (3 * kSubCols);
     const int y = pmod(y0 + r, H), x = pmod(x0 + c, W);
-    tile[r][c] = static_cast<float>(img[static_cast<size_t>(y) * W + x]);
+    sub[((c % 3) * rows + r) * kSubCols + c / 3] = img[static_cast<size_t>(y) * W + x];
   }
+  if constexpr (SPLIT > 1) bound[threadIdx.x] = __double_as_longlong(kInf);
   __syncthreads();
 
+  // pixel (tile row r, column 3 * lane + c) for c >= 0
+  auto px = [&](int r, int c) -> double {
+    return static_cast<double>(sub[((c % 3) * rows + r) * kSubCols + lane + c / 3]);
+  };
   const int trow = kStep * row_in_wg;  // this wave's first tile row for dy = -R
   double rf[kPatch][3];
 #pragma unroll
   for (int a = 0; a < kPatch; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) rf[a][b] = static_cast<double>(tile[trow + R + a][R + 3 * lane + b]);
+    for (int b = 0; b < 3; ++b) rf[a][b] = px(trow + R + a, R + b);
 
   double list[L];
 #pragma unroll
@@ -124,7 +172,21 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
       insert_sorted<L>(list, k);
     }
     cnt = 0;
-    thr = list[L - 1];
+    // Keys are unique, so a key above any wave's current worst kept key has
+    // K-1 better keys already and can never enter the merged list: prune
+    // with the smallest bound published by the waves of this reference row.
+    double t = list[L - 1];
+    if constexpr (SPLIT > 1) {
+      // relaxed workgroup-scope atomics: another wave's bound may be stale,
+      // which only makes it larger (bounds never increase)
+      __hip_atomic_store(bound + wave * kWave + lane, static_cast<unsigned long long>(__double_as_longlong(t)),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+      for (int s2 = 0; s2 < SPLIT; ++s2)
+        t = fmin(t, __longlong_as_double(static_cast<long long>(__hip_atomic_load(
+                        bound + (row_in_wg * SPLIT + s2) * kWave + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))));
+    }
+    thr = t;
   };
 
   const int dy_begin = (part * S) / SPLIT, dy_end = ((part + 1) * S) / SPLIT;
@@ -132,11 +194,12 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
   const int r_center = R * S + R;
 
   for (int dyi = dy_begin; dyi < dy_end; ++dyi) {
-    const float* base = &tile[trow + dyi][3 * lane];
     const int rank_row = dyi * S;
-    auto load = [&](double* c, int col) {
+    // column 6 * it + 3 * jo + m of the candidate rows (8 tile rows from trow + dyi)
+    auto load = [&](double* c, int m, int j) {
+      const uint16_t* base = sub + (m * rows + trow + dyi) * kSubCols + lane + j;
 #pragma unroll
-      for (int a = 0; a < kPatch; ++a) c[a] = static_cast<double>(base[a * kTileCols + col]);
+      for (int a = 0; a < kPatch; ++a) c[a] = static_cast<double>(base[a * kSubCols]);
     };
     // partial sums of one displacement: (cols 0..1, col 2) of this lane
     auto partial = [&](const double* ca, const double* cb, const double* cc, double& a2, double& a1) {
@@ -165,12 +228,13 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
         ++cnt;
       }
     };
-    // three displacements dxi, dxi+1, dxi+2 from columns (c0 c1 c2 n0 n1); n2 is prefetched
+    // displacements dxi, dxi+1, dxi+2 from columns (c0 c1 c2 n0 n1); columns
+    // dxi+3 .. dxi+5 (residues 0, 1, 2 at sub-array column j) are prefetched
     auto iter3 = [&](const double* c0, const double* c1, const double* c2, double* n0, double* n1, double* n2,
-                     int dxi) {
-      load(n0, dxi + 3);
-      load(n1, dxi + 4);
-      load(n2, dxi + 5);
+                     int dxi, int j) {
+      load(n0, 0, j);
+      load(n1, 1, j);
+      load(n2, 2, j);
       double a2a, a1a, a2b, a1b, a2c, a1c;
       partial(c0, c1, c2, a2a, a1a);
       partial(c1, c2, n0, a2b, a1b);
@@ -178,67 +242,61 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
       finish(a2a, a1a, dxi);
       finish(a2b, a1b, dxi + 1);
       finish(a2c, a1c, dxi + 2);
-      if (__any(cnt > kFlushAt)) flush();
+      if (__any(cnt > Smem::kFlushAt)) flush();
     };
 
     double A0[kPatch], A1[kPatch], A2[kPatch], B0[kPatch], B1[kPatch], B2[kPatch];
-    load(A0, 0);
-    load(A1, 1);
-    load(A2, 2);
+    load(A0, 0, 0);
+    load(A1, 1, 0);
+    load(A2, 2, 0);
     for (int it = 0; it < nIter; ++it) {
       const int dxi = 6 * it;
-      iter3(A0, A1, A2, B0, B1, B2, dxi);
-      iter3(B0, B1, B2, A0, A1, A2, dxi + 3);
+      iter3(A0, A1, A2, B0, B1, B2, dxi, 2 * it + 1);
+      iter3(B0, B1, B2, A0, A1, A2, dxi + 3, 2 * it + 2);
     }
   }
   flush();
 
-  __syncthreads();
-  double* lists = reinterpret_cast<double*>(smem);
-  const int q = q0 + lane;
-  const bool valid = lane < kLanesOut && q < nRx && p < nRy;
-  int16_t* out = idx + (static_cast<size_t>(p) * nRx + q) * K;
-  if constexpr (SPLIT == 1) {
-    if (valid) {
-      out[0] = static_cast<int16_t>(r_center);
+  if constexpr (SPLIT > 1) {
+    // merge the SPLIT partial lists of each row into its part-0 wave
+    __syncthreads();  // tile, buffers and bounds are dead
+    double* ml = reinterpret_cast<double*>(smem);
+    auto put = [&](int slot) {
 #pragma unroll
-      for (int i = 0; i < L; ++i) {
-        const double m = list[i];
-        out[1 + i] = static_cast<int16_t>(m - 2048.0 * floor(m * (1.0 / 2048.0)));
-      }
+      for (int i = 0; i < L; ++i) ml[(slot * L + i) * kWave + lane] = list[i];
+    };
+    auto take = [&](int slot) { merge_lists<L>(list, ml + slot * L * kWave + lane); };
+    if constexpr (SPLIT == 2) {
+      if (part == 1) put(row_in_wg);
+      __syncthreads();
+      if (part == 0) take(row_in_wg);
+    } else {
+      if (part & 1) put(part >> 1);  // parts 1, 3 -> slots 0, 1
+      __syncthreads();
+      if (!(part & 1)) take(part >> 1);  // part 0 <- 1, part 2 <- 3
+      __syncthreads();
+      if (part == 2) put(0);
+      __syncthreads();
+      if (part == 0) take(0);
     }
-  } else {
-    // lists[w][i][lane]; the first wave of each row merges its row's SPLIT lists
-#pragma unroll
-    for (int i = 0; i < L; ++i) lists[(wave * L + i) * kWave + lane] = list[i];
-    __syncthreads();
     if (part != 0) return;
-    const double* ls = lists + static_cast<size_t>(wave) * L * kWave + lane;
-    int ptr[SPLIT];
+  }
+
+  const int q = q0 + lane;
+  if (lane < kLanesOut && q < nRx && p < nRy) {
+    int16_t* out = idx + (static_cast<size_t>(p) * nRx + q) * K;
+    out[0] = static_cast<int16_t>(r_center);
 #pragma unroll
-    for (int s = 0; s < SPLIT; ++s) ptr[s] = 0;
-    if (valid) out[0] = static_cast<int16_t>(r_center);
-    for (int o = 0; o < L; ++o) {
-      double m = kInf;
-      int best = 0;
-#pragma unroll
-      for (int s = 0; s < SPLIT; ++s) {
-        const double h = ptr[s] < L ? ls[(s * L + ptr[s]) * kWave] : kInf;
-        if (h < m) {
-          m = h;
-          best = s;
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < SPLIT; ++s) ptr[s] += (s == best) ? 1 : 0;
-      if (valid) out[1 + o] = static_cast<int16_t>(m - 2048.0 * floor(m * (1.0 / 2048.0)));
+    for (int i = 0; i < L; ++i) {
+      const double m = list[i];
+      out[1 + i] = static_cast<int16_t>(m - 2048.0 * floor(m * (1.0 / 2048.0)));
     }
   }
 }
 
 template <int K, int RPW, int SPLIT, bool BATCH>
 __global__ __launch_bounds__(256, 2) void bm_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
-  __shared__ __align__(16) unsigned char smem[BmSmem<K, RPW>::bytes];
+  __shared__ __align__(16) unsigned char smem[BmSmem<K, RPW, SPLIT>::bytes];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
     bm_body<K, RPW, SPLIT>(smem, use_pilot ? r.pilot : r.noisy, r.idx, r.H, r.W, R, item);
   });
