@@ -56,6 +56,14 @@ extern "C" {
                                      while the batch shape is unchanged            */
 #define GBM3D_BATCH_BASIC_ONLY 2  /* stage 1 only: out receives the basic estimate */
 
+/* block-matching kernels; both give the same indices (Sec. 2: eq. dfg
+ * summed shift by shift, or the norm/cross-correlation split of Theorem 1) */
+#define GBM3D_BM_AUTO  0  /* the autotuned choice for the shape, else SHIFT */
+#define GBM3D_BM_SHIFT 1  /* per displacement: squared differences, box sums
+                             at the reference positions (float64 vector ALU) */
+#define GBM3D_BM_CORR  2  /* per 4x4 reference tile: block norms plus int8
+                             matrix-core cross-correlations, exact           */
+
 /* patch-stack transforms */
 #define GBM3D_STACK_BIOR15 0   /* 3-level periodic Mallat bior1.5 (Sec. 5) */
 #define GBM3D_STACK_DCT    1   /* orthonormal 8x8 DCT-II (Sec. 4)           */
@@ -74,8 +82,11 @@ typedef struct {
   float tv_eps_rel;     /* > 0: w = 1 / (TV + tv_eps_rel * sigma * 64 * k_ht); 1e-3 */
   int32_t keep_dc;      /* 1: the 3-D DC coefficient is never shrunk        */
   /* launch tuning (results do not depend on it) */
-  int32_t bm_split;     /* block matching: parts of the displacement rows per
-                           reference row, 1 | 2 | 4; 0 = chosen by image size */
+  int32_t bm_split;     /* block matching: waves sharing one reference tile,
+                           each scanning a part of the search window,
+                           1 | 2 | 4; 0 = tuned or chosen by image size      */
+  int32_t bm_method;    /* GBM3D_BM_AUTO (tuned or default) | GBM3D_BM_SHIFT |
+                           GBM3D_BM_CORR                                     */
 } gbm3d_params;
 
 /* One image of a batch (see gbm3d_denoise_batch). */
@@ -194,12 +205,13 @@ int gbm3d_pilot_load(gbm3d_ctx* ctx, const float* master, void* stream);
 int gbm3d_pilot_infer(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W,
                       const float* sigma, uint16_t* pilot_u16, float* pilot_f32, void* stream);
 
-/* Training: mean squared error of the pilot against target (device float
- * [B][H][W]) written to *loss (device float), and its gradient with respect
- * to the master vector into grad (device float [P]), with the loaded weights.
- * H and W >= 1. */
+/* Training: the mean squared error of the pilot against target (device float
+ * [B][H][W]), each image's squared errors scaled by weight[b] (device float
+ * [B]; NULL = all 1), written to *loss (device float), and its gradient with
+ * respect to the master vector into grad (device float [P]), with the loaded
+ * weights.  H and W >= 1. */
 int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target, int B, int H, int W,
-                     const float* sigma, float* grad, float* loss, void* stream);
+                     const float* sigma, const float* weight, float* grad, float* loss, void* stream);
 
 /* One Adam step (bias-corrected, step >= 1) on the master vector with moments
  * m, v (device float [P], zero before the first step), then reloads the
@@ -210,12 +222,32 @@ int gbm3d_pilot_adam(gbm3d_ctx* ctx, float* master, float* m, float* v, const fl
 /* Per-kernel timing for benchmarking.  While enabled, the context brackets
  * every kernel it launches with two HIP events recorded on the launch stream.
  * gbm3d_timing_read synchronises the pending events and returns, for one
- * kernel name ("bm", "stack_bior", "stack_dct", "group_ht", "group_wiener",
- * "reduce"), the summed elapsed milliseconds and the number of launches since
- * the last reset.  Off by default. */
+ * kernel name ("bm", "bm_norm", "stack_bior", "stack_dct", "group_ht",
+ * "group_wiener", "reduce"), the summed elapsed milliseconds and the number of
+ * launches since the last reset.  Off by default. */
 int gbm3d_timing_enable(gbm3d_ctx* ctx, int on);
 int gbm3d_timing_read(gbm3d_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 int gbm3d_timing_reset(gbm3d_ctx* ctx);
+
+/* Autotuner of the block-matching launch.  Times every variant (GBM3D_BM_SHIFT
+ * and GBM3D_BM_CORR, each with bm_split 1, 2 and 4) on the device image img
+ * [H][W] with group size K, `reps` runs each after one warm-up run, with HIP
+ * events on `stream` (the call synchronises it), and records the fastest for
+ * the shape class of (H, W, K): the number of 4x4 reference tiles rounded down
+ * to a power of two.  Later calls whose params leave bm_method or bm_split at
+ * 0 use the recorded choice of their class (a batch: the class of all its
+ * tiles together); without one, the method recorded for the nearest class of
+ * the same K with the split chosen by size; else the built-in default.
+ * Indices do not depend on the choice.  best_method, best_split and best_ms (milliseconds per run) may be
+ * NULL.  Errors: GBM3D_EINVAL for bad shapes, K or reps < 1. */
+int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, int reps, int* best_method,
+                   int* best_split, float* best_ms, void* stream);
+
+/* The recorded choices as text, one "K class method split ms" line each:
+ * gbm3d_tune_save writes them to `path`, gbm3d_tune_load adds those of `path`
+ * to the context (GBM3D_EINVAL if the file cannot be read or parsed). */
+int gbm3d_tune_save(const gbm3d_ctx* ctx, const char* path);
+int gbm3d_tune_load(gbm3d_ctx* ctx, const char* path);
 
 #ifdef __cplusplus
 }

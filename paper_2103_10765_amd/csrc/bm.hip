@@ -15,8 +15,9 @@
 // Three consecutive dx are evaluated per iteration as independent chains, with
 // the next columns prefetched from LDS while they compute.  Each lane keeps
 // the K-1 best keys of its reference in a sorted register list; candidates
-// below the current worst key are appended to a per-lane LDS buffer and merged
-// into the list when some lane's buffer is nearly full.
+// below the current worst key are appended to a per-lane LDS buffer, which is
+// sorted and merged into the list as one batch when some lane's buffer is
+// nearly full.
 //
 // A workgroup of four waves covers RPW reference rows x SPLIT parts of the
 // displacement rows (RPW * SPLIT = 4) and shares one LDS image tile with the
@@ -30,6 +31,7 @@
 // and the sorted list), not by LDS.
 #include "common.h"
 #include "kernels.h"
+#include "topk.h"
 
 namespace gbm3d {
 
@@ -46,14 +48,6 @@ struct TileShape {
   static constexpr int rows = kStep * (RPW - 1) + kPatch + 2 * kMaxR;
 };
 
-template <int L>
-__device__ __forceinline__ void insert_sorted(double (&list)[L], double key) {
-  // list is ascending; a key not below list[L-1] leaves it unchanged
-#pragma unroll
-  for (int i = L - 1; i >= 1; --i) list[i] = (key < list[i - 1]) ? list[i - 1] : fmin(key, list[i]);
-  list[0] = fmin(key, list[0]);
-}
-
 // value of lane + 1 (DPP wave shift; lane 63 keeps its own value)
 __device__ __forceinline__ double from_next_lane(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
@@ -65,7 +59,7 @@ __device__ __forceinline__ double from_next_lane(double v) {
 template <int K, int RPW, int SPLIT>
 struct BmSmem {
   static constexpr int L = K - 1;
-  static constexpr int kBuf = RPW == 1 ? 8 : 7;  // buffered candidates per lane
+  static constexpr int kBuf = RPW == 1 ? 8 : 7;  // buffered candidates per lane (merged as a batch of 8)
   static constexpr int kFlushAt = kBuf - 3;      // an iteration appends at most 3
   static constexpr size_t kTile = sizeof(uint16_t) * 3 * TileShape<RPW>::rows * kSubCols;
   static constexpr size_t kBufBytes = sizeof(double) * 4 * kBuf * kWave;
@@ -82,31 +76,6 @@ __host__ __device__ constexpr int bm_segments(int W) { return ((W + kStep - 1) /
 template <int RPW>
 __host__ __device__ constexpr int bm_items(int H, int W) {
   return (((H + kStep - 1) / kStep) + RPW - 1) / RPW * bm_segments(W);
-}
-
-// list := the L smallest of list and the sorted list b[0..L) (stride kWave):
-// with a = list + [inf] and b reversed, c[i] = min(a[i], b[P-1-i]) is bitonic
-// and holds the P = L+1 smallest of both; a half-cleaner cascade sorts it.
-template <int L>
-__device__ __forceinline__ void merge_lists(double (&list)[L], const double* b) {
-  constexpr int P = L + 1;
-  static_assert((P & (P - 1)) == 0, "K is a power of two");
-  double c[P];
-  c[0] = list[0];
-#pragma unroll
-  for (int i = 1; i < L; ++i) c[i] = fmin(list[i], b[(L - i) * kWave]);
-  c[L] = b[0];
-#pragma unroll
-  for (int s = P / 2; s >= 1; s >>= 1)
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-      if (!(i & s)) {
-        const double lo = fmin(c[i], c[i + s]), hi = fmax(c[i], c[i + s]);
-        c[i] = lo;
-        c[i + s] = hi;
-      }
-#pragma unroll
-  for (int i = 0; i < L; ++i) list[i] = c[i];
 }
 
 // One work item: reference rows [RPW*pb, RPW*pb + RPW) x 62 reference columns.
@@ -165,12 +134,7 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
   double* mybuf = buf + wave * kBuf * kWave + lane;  // entry j at mybuf[j * kWave]
 
   auto flush = [&]() {
-#pragma unroll 1
-    for (int j = 0; j < kBuf; ++j) {
-      if (!__any(j < cnt)) break;
-      const double k = (j < cnt) ? mybuf[j * kWave] : kInf;
-      insert_sorted<L>(list, k);
-    }
+    merge_buffer<L, 8>(list, mybuf, kWave, cnt);
     cnt = 0;
     // Keys are unique, so a key above any wave's current worst kept key has
     // K-1 better keys already and can never enter the merged list: prune
@@ -255,7 +219,7 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
       iter3(B0, B1, B2, A0, A1, A2, dxi + 3, 2 * it + 2);
     }
   }
-  flush();
+  if (__any(cnt > 0)) flush();
 
   if constexpr (SPLIT > 1) {
     // merge the SPLIT partial lists of each row into its part-0 wave
@@ -265,7 +229,10 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
 #pragma unroll
       for (int i = 0; i < L; ++i) ml[(slot * L + i) * kWave + lane] = list[i];
     };
-    auto take = [&](int slot) { merge_lists<L>(list, ml + slot * L * kWave + lane); };
+    auto take = [&](int slot) {
+      const double* b = ml + slot * L * kWave + lane;
+      merge_sorted<L>(list, [&](int j) { return b[j * kWave]; });
+    };
     if constexpr (SPLIT == 2) {
       if (part == 1) put(row_in_wg);
       __syncthreads();
@@ -288,8 +255,7 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
     out[0] = static_cast<int16_t>(r_center);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      const double m = list[i];
-      out[1 + i] = static_cast<int16_t>(m - 2048.0 * floor(m * (1.0 / 2048.0)));
+      out[1 + i] = key_rank(list[i]);
     }
   }
 }

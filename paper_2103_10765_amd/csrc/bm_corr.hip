@@ -1,0 +1,416 @@
+// Block matching in the correlation form of Theorem 1 (Sec. 2), on the
+// matrix cores.  Same result as the shift-wise kernel: for every reference the
+// K-1 smallest keys dist * 2048 + rank over the search window, reference in
+// slot 0.
+//
+// ||a - b||^2 = N(a) + N(b) - 2 <a, b>, with N the block's squared norm.  The
+// distance is translation invariant, so pixels are first shifted by 32896:
+// z = Z - 32896 = 256 h + l with signed bytes h = (Z >> 8) - 128 and
+// l = (Z & 255) - 128.  Then <a, b> = 65536 Phh + 256 (Phl + Plh) + Pll, four
+// exact int8 x int8 -> int32 dot products of length 64, which is one
+// v_mfma_i32_16x16x64_i8 each for 16 candidates x 16 references.
+//
+// A wave owns a 4 x 4 tile of references (step 3); the union of their search
+// windows is a (2R + 10)^2 square of candidate positions, walked in 4 x 4
+// candidate blocks from the centre outwards.  Result lane (g, n) holds
+// reference n and candidates (row g, columns 0..3) of the block.  Each pair is
+// first tested with a conservative bound that drops the Pll term
+// (|2 Pll| <= 2^21); survivors get the exact key in float64.  Norms come from
+// a table written beforehand by bm_norm_kernel (float64, exact).
+//
+// Every lane keeps the K-1 best keys of its reference among its quarter of
+// the candidates; the four quarters, and the SPLIT waves that share a tile,
+// publish their worst kept key so every lane prunes with the best bound of
+// its reference, and merge with bitonic networks at the end.
+#include "common.h"
+#include "kernels.h"
+#include "topk.h"
+
+namespace gbm3d {
+
+namespace {
+
+constexpr int kNormPad = 32;                       // periodic border of the norm table
+constexpr int kPitch = 96;                         // bytes per LDS plane row
+constexpr int kMaxNb = (2 * kMaxR + 10 + 3) / 4;   // candidate blocks per axis
+constexpr int kRows = 4 * kMaxNb + 7;              // LDS plane rows
+constexpr int kBuf = 8;                            // buffered candidates per lane
+constexpr int kFlushAt = kBuf - 4;                 // a block appends at most 4
+constexpr int kZShift = 32896;
+constexpr double kInf = __builtin_huge_val();
+
+static_assert(12 * 3 + 4 * kMaxNb + 12 <= kPitch, "plane rows too short");
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Candidate blocks of an nb x nb grid in rings of growing Chebyshev distance
+// from its centre (near displacements first tighten the bounds early).
+struct BlockOrder {
+  unsigned char b[kMaxNb + 1][kMaxNb * kMaxNb];
+};
+
+constexpr BlockOrder make_block_order() {
+  BlockOrder o{};
+  for (int nb = 1; nb <= kMaxNb; ++nb) {
+    int n = 0;
+    for (int ring = 0; ring <= 2 * nb; ++ring)
+      for (int b = 0; b < nb * nb; ++b) {
+        int dr = 2 * (b / nb) - (nb - 1), dc = 2 * (b % nb) - (nb - 1);
+        dr = dr < 0 ? -dr : dr;
+        dc = dc < 0 ? -dc : dc;
+        if ((dr > dc ? dr : dc) == ring) o.b[nb][n++] = static_cast<unsigned char>(b);
+      }
+  }
+  return o;
+}
+
+__constant__ BlockOrder kOrder = make_block_order();
+
+__device__ __forceinline__ int norm_pitch(int W) { return W + 2 * kNormPad; }
+
+// ---------------------------------------------------------------------------
+// Norm table: N[ey][ex] = sum over the 8 x 8 block at image position
+// ((ey - pad) mod H, (ex - pad) mod W) of (Z - 32896)^2, for
+// ey < H + 2 pad, ex < W + 2 pad.  Items are 16 x 64 output tiles.
+// ---------------------------------------------------------------------------
+constexpr int kNTy = 16, kNTx = 64;
+
+__host__ __device__ constexpr int norm_items(int H, int W) {
+  return ((H + 2 * kNormPad + kNTy - 1) / kNTy) * ((W + 2 * kNormPad + kNTx - 1) / kNTx);
+}
+
+__device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img, double* __restrict__ norm, int H, int W,
+                                          int item, int* zt, double* hs) {
+  const int He = H + 2 * kNormPad, We = norm_pitch(W);
+  const int tiles_x = (We + kNTx - 1) / kNTx;
+  const int ty0 = (item / tiles_x) * kNTy, tx0 = (item % tiles_x) * kNTx;
+  constexpr int ZR = kNTy + 7, ZC = kNTx + 7;
+  for (int i = threadIdx.x; i < ZR * ZC; i += blockDim.x) {
+    const int r = i / ZC, c = i - r * ZC;
+    const int y = pmod(ty0 + r - kNormPad, H), x = pmod(tx0 + c - kNormPad, W);
+    zt[i] = static_cast<int>(img[static_cast<size_t>(y) * W + x]) - kZShift;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ZR * kNTx; i += blockDim.x) {
+    const int r = i / kNTx, c = i - r * kNTx;
+    double h = 0.0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int v = zt[r * ZC + c + b];
+      h += static_cast<double>(v * v);  // |v| <= 32896: v * v < 2^31
+    }
+    hs[i] = h;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNTy * kNTx; i += blockDim.x) {
+    const int r = i / kNTx, c = i - r * kNTx;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) s += hs[(r + a) * kNTx + c];
+    if (ty0 + r < He && tx0 + c < We) norm[static_cast<size_t>(ty0 + r) * We + tx0 + c] = s;
+  }
+}
+
+template <bool BATCH>
+__global__ __launch_bounds__(256) void bm_norm_kernel(ImgRec one, WorkList wl, int use_pilot) {
+  __shared__ int zt[(kNTy + 7) * (kNTx + 7)];
+  __shared__ double hs[(kNTy + 7) * kNTx];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
+    norm_body(use_pilot ? r.pilot : r.noisy, r.norm, r.H, r.W, item, zt, hs);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// matching
+// ---------------------------------------------------------------------------
+
+template <int K, int TPW, int SPLIT>
+struct CorrSmem {
+  static constexpr int L = K - 1;
+  static constexpr size_t kPlanes = 2 * kRows * kPitch;
+  static constexpr size_t kBufBytes = sizeof(double) * 4 * kBuf * kWave;
+  static constexpr size_t kBound = SPLIT > 1 ? sizeof(double) * 4 * kWave : 0;
+  static constexpr size_t kScan = kPlanes + kBufBytes + kBound;
+  static constexpr size_t kMerge = SPLIT > 1 ? sizeof(double) * 2 * L * kWave : 0;
+  static constexpr size_t bytes = kScan > kMerge ? kScan : kMerge;
+};
+
+template <int TPW>
+__host__ __device__ constexpr int corr_col_items(int W) {
+  return ((W + kStep - 1) / kStep + 4 * TPW - 1) / (4 * TPW);
+}
+
+template <int TPW>
+__host__ __device__ constexpr int corr_items(int H, int W) {
+  return ((H + kStep - 1) / kStep + 3) / 4 * corr_col_items<TPW>(W);
+}
+
+// 8 bytes of LDS plane row r from byte column x (any alignment) as 2 dwords
+__device__ __forceinline__ void seg8(const unsigned char* plane, int r, int x, int& w0, int& w1) {
+  const unsigned* p = reinterpret_cast<const unsigned*>(plane + r * kPitch + (x & ~3));
+  const unsigned d0 = p[0], d1 = p[1], d2 = p[2];
+  const unsigned sh = static_cast<unsigned>(x & 3);
+  w0 = static_cast<int>(__builtin_amdgcn_alignbyte(d1, d0, sh));
+  w1 = static_cast<int>(__builtin_amdgcn_alignbyte(d2, d1, sh));
+}
+
+// MFMA operand of the block at LDS (row, col): rows 2g, 2g + 1 of the block,
+// 8 bytes each, for the h and l planes (byte j of the 16 <-> k = 16 g + j,
+// block pixel (2g + j / 8, j % 8); the same map for both operands).
+__device__ __forceinline__ void load_operand(const unsigned char* hp, const unsigned char* lp, int row, int col, int g,
+                                             i32x4& oh, i32x4& ol) {
+  int a0, a1, a2, a3;
+  seg8(hp, row + 2 * g, col, a0, a1);
+  seg8(hp, row + 2 * g + 1, col, a2, a3);
+  oh = i32x4{a0, a1, a2, a3};
+  seg8(lp, row + 2 * g, col, a0, a1);
+  seg8(lp, row + 2 * g + 1, col, a2, a3);
+  ol = i32x4{a0, a1, a2, a3};
+}
+
+// One work item: reference rows [4 pb, 4 pb + 4) x columns [4 TPW qb, 4 TPW (qb + 1)).
+template <int K, int TPW, int SPLIT>
+__device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* __restrict__ img,
+                                          const double* __restrict__ norm, int16_t* __restrict__ idx, int H, int W,
+                                          int R, int item) {
+  static_assert(TPW * SPLIT == 4, "four waves per workgroup");
+  using Smem = CorrSmem<K, TPW, SPLIT>;
+  constexpr int L = K - 1;
+  unsigned char* hp = smem;
+  unsigned char* lp = smem + kRows * kPitch;
+  double* buf = reinterpret_cast<double*>(smem + Smem::kPlanes);
+  unsigned long long* bound = reinterpret_cast<unsigned long long*>(smem + Smem::kPlanes + Smem::kBufBytes);
+
+  const int nRy = (H + kStep - 1) / kStep, nRx = (W + kStep - 1) / kStep;
+  const int S = 2 * R + 1;
+  const int nb = (2 * R + 10 + 3) / 4;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int t = wave / SPLIT, part = wave % SPLIT;
+  const int g = lane >> 4, n = lane & 15;
+  const int u = n >> 2, v = n & 3;
+  const int segs = corr_col_items<TPW>(W);
+  const int p0 = (item / segs) * 4;
+  const int q0 = (item % segs) * 4 * TPW;
+  const int qt = q0 + 4 * t;  // first reference column of this wave's tile
+
+  // LDS planes of the image region rows 3 p0 - R + [0, 4 nb + 7), columns 3 q0 - R + [0, kPitch)
+  const int y0 = kStep * p0 - R, x0 = kStep * q0 - R;
+  const int rows = 4 * nb + 7;
+  for (int i = threadIdx.x; i < rows * (kPitch / 4); i += blockDim.x) {
+    const int r = i / (kPitch / 4), c = (i - r * (kPitch / 4)) * 4;
+    const int y = pmod(y0 + r, H), xb = pmod(x0 + c, W);
+    unsigned wh = 0, wl = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = xb + j < W ? xb + j : xb + j - W;  // W >= 8 > j
+      const unsigned z = img[static_cast<size_t>(y) * W + x];
+      wh |= ((z >> 8) ^ 0x80u) << (8 * j);
+      wl |= ((z & 0xFFu) ^ 0x80u) << (8 * j);
+    }
+    reinterpret_cast<unsigned*>(hp + r * kPitch)[c / 4] = wh;
+    reinterpret_cast<unsigned*>(lp + r * kPitch)[c / 4] = wl;
+  }
+  if constexpr (SPLIT > 1) bound[threadIdx.x] = __double_as_longlong(kInf);
+  __syncthreads();
+
+  // this lane's reference (p0 + u, qt + v): operand rows 2g, 2g + 1, and norm
+  i32x4 rh, rl;
+  load_operand(hp, lp, R + 3 * u, R + 12 * t + 3 * v, g, rh, rl);
+  const int We = norm_pitch(W);
+  // (a tile right of the last reference column only takes part in the merges)
+  const double nr =
+      qt < nRx ? norm[static_cast<size_t>(kStep * (p0 + u) + kNormPad) * We + kStep * (qt + v) + kNormPad] : 0.0;
+  // norms of this lane's result candidates: block (br, bc) row g, columns 0..3
+  const double* ncand = norm + static_cast<size_t>(y0 + g + kNormPad) * We + (x0 + 12 * t + kNormPad);
+
+  double list[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) list[i] = kInf;
+  double thr = kInf, bnd = kInf;  // key bound, and the matching bound on N(b) - 512 S
+  int cnt = 0;
+  double* mybuf = buf + wave * kBuf * kWave + lane;
+  const int r_center = R * S + R;
+
+  auto flush = [&]() {
+    merge_buffer<L, kBuf>(list, mybuf, kWave, cnt);
+    cnt = 0;
+    // keys are unique: a key above any list's worst kept key for the same
+    // reference cannot be among its K-1 best
+    double tb = fmin(list[L - 1], shfl_xor_double(list[L - 1], 16));
+    tb = fmin(tb, shfl_xor_double(tb, 32));
+    if constexpr (SPLIT > 1) {
+      __hip_atomic_store(bound + wave * kWave + lane, static_cast<unsigned long long>(__double_as_longlong(tb)),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+      for (int s2 = 0; s2 < SPLIT; ++s2)
+        tb = fmin(tb, __longlong_as_double(static_cast<long long>(__hip_atomic_load(
+                          bound + (t * SPLIT + s2) * kWave + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))));
+    }
+    thr = tb;
+    // key < thr needs dist < thr / 2048; dist >= nr + (N(b) - 512 S) - 2^21
+    bnd = thr * (1.0 / 2048.0) - nr + 2097152.0;
+  };
+
+  if (qt < nRx) {
+    const int nblk = nb * nb;
+    for (int j = part; j < nblk; j += SPLIT) {
+      const int b = kOrder.b[nb][j];
+      const int br = b / nb, bc = b - br * nb;
+      // operand: candidate m = n -> block row n / 4, column n % 4
+      i32x4 ch, cl;
+      load_operand(hp, lp, 4 * br + (n >> 2), 12 * t + 4 * bc + (n & 3), g, ch, cl);
+      const double* nc = ncand + static_cast<size_t>(4 * br) * We + 4 * bc;
+      double nv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nv[i] = nc[i];
+      const i32x4 zero = {0, 0, 0, 0};
+      const i32x4 hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ch, rh, zero, 0, 0, 0);
+      i32x4 cc = __builtin_amdgcn_mfma_i32_16x16x64_i8(ch, rl, zero, 0, 0, 0);
+      cc = __builtin_amdgcn_mfma_i32_16x16x64_i8(cl, rh, cc, 0, 0, 0);
+      const i32x4 ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(cl, rl, zero, 0, 0, 0);
+      // result lane (g, n): candidates (4 br + g, 4 bc + i) vs reference (3u, 3v), in window units
+      const int ey = 4 * br + g - 3 * u;     // dy + R
+      const int ex0 = 4 * bc - 3 * v;        // dx + R for i = 0
+      const bool row_ok = static_cast<unsigned>(ey) <= static_cast<unsigned>(2 * R);
+      const int rank0 = ey * S + ex0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int s = hh[i] * 256 + cc[i];  // 256 Phh + Phl + Plh, |s| < 2^29
+        const double f = fma(-512.0, static_cast<double>(s), nv[i]);
+        const bool ok = row_ok && static_cast<unsigned>(ex0 + i) <= static_cast<unsigned>(2 * R) && f < bnd;
+        if (__any(ok)) {
+          const double dist = fma(-2.0, static_cast<double>(ll[i]), f) + nr;
+          const int rank = rank0 + i;
+          const double key = fma(dist, 2048.0, static_cast<double>(rank));
+          if (ok && rank != r_center && key < thr) {
+            mybuf[cnt * kWave] = key;
+            ++cnt;
+          }
+        }
+      }
+      if (__any(cnt > kFlushAt)) flush();
+    }
+  }
+  if (__any(cnt > 0)) flush();
+
+  // the four quarters of each reference, then the SPLIT waves of the tile
+  merge_sorted<L>(list, [&](int j) { return shfl_xor_double(list[j], 16); });
+  merge_sorted<L>(list, [&](int j) { return shfl_xor_double(list[j], 32); });
+  if constexpr (SPLIT > 1) {
+    __syncthreads();  // planes, buffers and bounds are dead
+    double* ml = reinterpret_cast<double*>(smem);
+    auto put = [&](int slot) {
+#pragma unroll
+      for (int i = 0; i < L; ++i) ml[(slot * L + i) * kWave + lane] = list[i];
+    };
+    auto take = [&](int slot) {
+      const double* b = ml + slot * L * kWave + lane;
+      merge_sorted<L>(list, [&](int j) { return b[j * kWave]; });
+    };
+    if constexpr (SPLIT == 2) {
+      if (part == 1) put(t);
+      __syncthreads();
+      if (part == 0) take(t);
+    } else {
+      if (part & 1) put(part >> 1);
+      __syncthreads();
+      if (!(part & 1)) take(part >> 1);
+      __syncthreads();
+      if (part == 2) put(0);
+      __syncthreads();
+      if (part == 0) take(0);
+    }
+    if (part != 0) return;
+  }
+
+  const int p = p0 + u, q = qt + v;
+  if (g == 0 && p < nRy && q < nRx) {
+    int16_t* out = idx + (static_cast<size_t>(p) * nRx + q) * K;
+    out[0] = static_cast<int16_t>(r_center);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      out[1 + i] = key_rank(list[i]);
+    }
+  }
+}
+
+template <int K, int TPW, int SPLIT, bool BATCH>
+__global__ __launch_bounds__(256, 2) void bm_corr_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
+  __shared__ __align__(16) unsigned char smem[CorrSmem<K, TPW, SPLIT>::bytes];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
+    corr_body<K, TPW, SPLIT>(smem, use_pilot ? r.pilot : r.noisy, r.norm, r.idx, r.H, r.W, R, item);
+  });
+}
+
+template <int K, int TPW, int SPLIT>
+hipError_t launch_corr_shape(const ImgRec& one, const WorkList* wl, int R, int use_pilot, int grid_cap,
+                             hipStream_t st) {
+  if (!wl) {
+    hipLaunchKernelGGL((bm_corr_kernel<K, TPW, SPLIT, false>), dim3(corr_items<TPW>(one.H, one.W)), dim3(256), 0, st,
+                       one, WorkList{}, R, use_pilot);
+  } else {
+    if (wl->total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((bm_corr_kernel<K, TPW, SPLIT, true>), dim3(std::min(wl->total, grid_cap)), dim3(256), 0, st,
+                       one, *wl, R, use_pilot);
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_corr_k(const ImgRec& one, const WorkList* wl, int R, int split, int use_pilot, int grid_cap,
+                         hipStream_t st) {
+  switch (split) {
+    case 1: return launch_corr_shape<K, 4, 1>(one, wl, R, use_pilot, grid_cap, st);
+    case 2: return launch_corr_shape<K, 2, 2>(one, wl, R, use_pilot, grid_cap, st);
+    case 4: return launch_corr_shape<K, 1, 4>(one, wl, R, use_pilot, grid_cap, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+size_t norm_bytes(int H, int W) {
+  return static_cast<size_t>(H + 2 * kNormPad) * (W + 2 * kNormPad) * sizeof(double);
+}
+
+int norm_items_for(int H, int W) { return norm_items(H, W); }
+
+int corr_items_for(int H, int W, int split) {
+  switch (split) {
+    case 1: return corr_items<4>(H, W);
+    case 2: return corr_items<2>(H, W);
+    default: return corr_items<1>(H, W);
+  }
+}
+
+long corr_tiles(int H, int W) { return static_cast<long>(corr_items<1>(H, W)); }
+
+int corr_auto_split(long tiles) { return tiles >= 4096 ? 1 : (tiles >= 2048 ? 2 : 4); }
+
+hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int use_pilot, int grid_cap, hipStream_t st) {
+  if (!wl) {
+    hipLaunchKernelGGL((bm_norm_kernel<false>), dim3(norm_items(one.H, one.W)), dim3(256), 0, st, one, WorkList{},
+                       use_pilot);
+  } else {
+    if (wl->total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((bm_norm_kernel<true>), dim3(std::min(wl->total, grid_cap)), dim3(256), 0, st, one, *wl,
+                       use_pilot);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bm_corr(const ImgRec& one, const WorkList* wl, int R, int K, int split, int use_pilot, int grid_cap,
+                          hipStream_t st) {
+  if (split <= 0) split = corr_auto_split(corr_tiles(one.H, one.W));
+  switch (K) {
+    case 2: return launch_corr_k<2>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 4: return launch_corr_k<4>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 8: return launch_corr_k<8>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 16: return launch_corr_k<16>(one, wl, R, split, use_pilot, grid_cap, st);
+    case 32: return launch_corr_k<32>(one, wl, R, split, use_pilot, grid_cap, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace gbm3d

@@ -36,13 +36,20 @@ struct TimingRecord {
 thread_local std::string g_thread_error;
 
 // Work lists of the batch phases: per-image prefix offsets of the items.
-enum Phase { kBm1, kStack1, kGroup1, kReduce1, kBm2, kStack2, kGroup2, kReduce2, kPhases };
+enum Phase { kNorm1, kBm1, kStack1, kGroup1, kReduce1, kNorm2, kBm2, kStack2, kGroup2, kReduce2, kPhases };
 
 struct BatchPlan {
   std::vector<ImgRec> recs;
   std::vector<int> begin[kPhases];  // n + 1 each
+  int bm_method1 = GBM3D_BM_SHIFT, bm_method2 = GBM3D_BM_SHIFT;
   int bm_split1 = 1, bm_split2 = 1;
   bool any_stage1 = false, any_stage2 = false;
+};
+
+// A block-matching launch choice recorded by the autotuner.
+struct TuneEntry {
+  int method = GBM3D_BM_SHIFT, split = 1;
+  float ms = 0.0f;
 };
 
 struct GraphEntry {
@@ -57,7 +64,9 @@ struct gbm3d_ctx {
   int device = 0;
   int n_cu = 256;
   std::string err;
-  Buffer stack_a, stack_b, idx, partials, basic, q;
+  Buffer stack_a, stack_b, idx, partials, basic, q, norm;
+  // block-matching choices per (K, shape class)
+  std::map<std::pair<int, int>, TuneEntry> tuned;
   // batches
   Buffer batch_ws, batch_table;
   void* host_stage = nullptr;  // pinned staging of the batch table
@@ -145,6 +154,8 @@ int check_params(gbm3d_ctx* ctx, const gbm3d_params& p) {
     return fail(ctx, GBM3D_EINVAL, "search %d must be odd and in [1, 39]", p.search);
   if (p.bm_split != 0 && p.bm_split != 1 && p.bm_split != 2 && p.bm_split != 4)
     return fail(ctx, GBM3D_EINVAL, "bm_split %d must be 0, 1, 2 or 4", p.bm_split);
+  if (p.bm_method != GBM3D_BM_AUTO && p.bm_method != GBM3D_BM_SHIFT && p.bm_method != GBM3D_BM_CORR)
+    return fail(ctx, GBM3D_EINVAL, "bm_method %d unknown", p.bm_method);
   return GBM3D_OK;
 }
 
@@ -229,6 +240,63 @@ ImgRec blank_rec(int H, int W, float sigma) {
   return r;
 }
 
+// Shape class of a block-matching launch: floor(log2) of its 4x4 reference tiles.
+int tile_class(long tiles) {
+  int c = 0;
+  while (tiles >= (2L << c)) ++c;
+  return c;
+}
+
+struct BmChoice {
+  int method, split;  // split 0: by size inside the launcher
+};
+
+// Explicit params win.  Zeros take the tuned choice of the class; without one,
+// the method of the nearest tuned class of the same K (split then by size),
+// else the default.
+BmChoice choose_bm(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles, int K) {
+  BmChoice c{p.bm_method, p.bm_split};
+  const int cls = tile_class(tiles);
+  const auto it = ctx->tuned.find({K, cls});
+  if (it != ctx->tuned.end()) {
+    if (c.method == GBM3D_BM_AUTO) c.method = it->second.method;
+    if (c.split == 0 && c.method == it->second.method) c.split = it->second.split;
+  } else if (c.method == GBM3D_BM_AUTO) {
+    int best = 1 << 30;
+    for (const auto& kv : ctx->tuned) {
+      const int d = std::abs(kv.first.second - cls);
+      if (kv.first.first == K && d < best) {
+        best = d;
+        c.method = kv.second.method;
+      }
+    }
+  }
+  if (c.method == GBM3D_BM_AUTO) c.method = GBM3D_BM_SHIFT;
+  return c;
+}
+
+// Block matching of one image (r.noisy, or r.pilot with use_pilot) into r.idx.
+int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const BmChoice& c, int use_pilot, hipStream_t st) {
+  if (c.method == GBM3D_BM_CORR) {
+    CHECK(ensure(ctx, ctx->norm, gbm3d::norm_bytes(r.H, r.W), "norm table"));
+    r.norm = static_cast<double*>(ctx->norm.p);
+    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(r, nullptr, use_pilot, 0, st); }),
+            "norm table launch");
+    HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
+              return gbm3d::launch_bm_corr(r, nullptr, R, K, c.split, use_pilot, 0, st);
+            }),
+            "block matching launch");
+  } else {
+    HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(r, nullptr, R, K, c.split, use_pilot, 0, st); }),
+            "block matching launch");
+  }
+  return GBM3D_OK;
+}
+
+int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const gbm3d_params& p, int use_pilot, hipStream_t st) {
+  return run_match(ctx, r, R, K, choose_bm(ctx, p, gbm3d::corr_tiles(r.H, r.W), K), use_pilot, st);
+}
+
 float tv_eps(const gbm3d_params& p, float sigma) { return p.tv_eps_rel * sigma * 64.0f * static_cast<float>(p.k_ht); }
 
 // Stage 1 of one image into `basic` (and optionally its quantisation into q).
@@ -246,8 +314,7 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
   r.idx = static_cast<int16_t*>(ctx->idx.p);
   r.partials = static_cast<unsigned long long*>(ctx->partials.p);
   r.eps = tv_eps(p, sigma);
-  HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(r, nullptr, R, p.k_ht, p.bm_split, 0, 0, st); }),
-          "block matching launch");
+  CHECK(run_match(ctx, r, R, p.k_ht, p, 0, st));
   HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(r, nullptr, 0, 0, 0, 0, st); }),
           "stack launch");
   HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
@@ -274,9 +341,7 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
   r.stack_b = static_cast<float*>(ctx->stack_b.p);
   r.idx = static_cast<int16_t*>(ctx->idx.p);
   r.partials = static_cast<unsigned long long*>(ctx->partials.p);
-  HIP_TRY(ctx,
-          timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(r, nullptr, R, p.k_wiener, p.bm_split, 1, 0, st); }),
-          "block matching launch");
+  CHECK(run_match(ctx, r, R, p.k_wiener, p, 1, st));
   HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 0, 0, 0, st); }),
           "stack launch");
   HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 1, 1, 0, st); }),
@@ -301,6 +366,29 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
   const int R = p.search / 2;
   const bool basic_only = (flags & GBM3D_BATCH_BASIC_ONLY) != 0;
   const int kmax = std::max(p.k_ht, p.k_wiener);
+  // matching kernels of the two stages, from the tiles of all their images
+  long tiles1 = 0, tiles2 = 0, waves1 = 0, waves2 = 0;
+  for (int i = 0; i < n; ++i) {
+    const int H = imgs[i].H, W = imgs[i].W;
+    if (imgs[i].pilot == nullptr) {
+      tiles1 += gbm3d::corr_tiles(H, W);
+      waves1 += gbm3d::bm_waves_unsplit(H, W);
+    }
+    if (!basic_only) {
+      tiles2 += gbm3d::corr_tiles(H, W);
+      waves2 += gbm3d::bm_waves_unsplit(H, W);
+    }
+  }
+  const BmChoice c1 = choose_bm(ctx, p, tiles1, p.k_ht), c2 = choose_bm(ctx, p, tiles2, p.k_wiener);
+  plan.bm_method1 = c1.method;
+  plan.bm_method2 = c2.method;
+  auto split_of = [](const BmChoice& c, long tiles, long waves) {
+    if (c.split > 0) return c.split;
+    return c.method == GBM3D_BM_CORR ? gbm3d::corr_auto_split(tiles) : gbm3d::bm_auto_split(waves);
+  };
+  plan.bm_split1 = split_of(c1, tiles1, waves1);
+  plan.bm_split2 = split_of(c2, tiles2, waves2);
+  const bool need_norm = (tiles1 > 0 && c1.method == GBM3D_BM_CORR) || (tiles2 > 0 && c2.method == GBM3D_BM_CORR);
   // workspace slices
   size_t total = 0;
   std::vector<size_t> off(n);
@@ -308,6 +396,7 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
     const int H = imgs[i].H, W = imgs[i].W;
     const bool s1 = imgs[i].pilot == nullptr;
     off[i] = total;
+    if (need_norm) total += align256(gbm3d::norm_bytes(H, W));              // norm table
     total += align256(stack_bytes(H, W));                                   // stack_a
     if (!basic_only) total += align256(stack_bytes(H, W));                  // stack_b
     total += align256(n_refs(H, W) * kmax * sizeof(int16_t));               // idx
@@ -317,13 +406,16 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
   CHECK(ensure(ctx, ctx->batch_ws, total, "batch workspace"));
   char* base = static_cast<char*>(ctx->batch_ws.p);
   plan.recs.resize(n);
-  long waves1 = 0, waves2 = 0;
   for (int i = 0; i < n; ++i) {
     const gbm3d_image& im = imgs[i];
     const int H = im.H, W = im.W;
     const bool s1 = im.pilot == nullptr;
     ImgRec r = blank_rec(H, W, im.sigma);
     char* c = base + off[i];
+    if (need_norm) {
+      r.norm = reinterpret_cast<double*>(c);
+      c += align256(gbm3d::norm_bytes(H, W));
+    }
     r.stack_a = reinterpret_cast<float*>(c);
     c += align256(stack_bytes(H, W));
     if (!basic_only) {
@@ -349,24 +441,23 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
       r.out = im.out;
     }
     plan.recs[i] = r;
-    if (s1) waves1 += gbm3d::bm_waves_unsplit(H, W);
-    if (!basic_only) waves2 += gbm3d::bm_waves_unsplit(H, W);
     plan.any_stage1 = plan.any_stage1 || s1;
   }
   plan.any_stage2 = !basic_only;
-  plan.bm_split1 = p.bm_split > 0 ? p.bm_split : gbm3d::bm_auto_split(waves1);
-  plan.bm_split2 = p.bm_split > 0 ? p.bm_split : gbm3d::bm_auto_split(waves2);
   for (int ph = 0; ph < kPhases; ++ph) plan.begin[ph].assign(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     const int H = imgs[i].H, W = imgs[i].W;
     const bool s1 = imgs[i].pilot == nullptr;
     const bool s2 = !basic_only;
+    const bool corr1 = plan.bm_method1 == GBM3D_BM_CORR, corr2 = plan.bm_method2 == GBM3D_BM_CORR;
     const int items[kPhases] = {
-        s1 ? gbm3d::bm_items_for(H, W, plan.bm_split1) : 0,
+        s1 && corr1 ? gbm3d::norm_items_for(H, W) : 0,
+        s1 ? (corr1 ? gbm3d::corr_items_for(H, W, plan.bm_split1) : gbm3d::bm_items_for(H, W, plan.bm_split1)) : 0,
         s1 ? gbm3d::stack_items_for(H, W) : 0,
         s1 ? gbm3d::group_items_for(H, W, R) : 0,
         s1 ? gbm3d::reduce_items_for(H, W) : 0,
-        s2 ? gbm3d::bm_items_for(H, W, plan.bm_split2) : 0,
+        s2 && corr2 ? gbm3d::norm_items_for(H, W) : 0,
+        s2 ? (corr2 ? gbm3d::corr_items_for(H, W, plan.bm_split2) : gbm3d::bm_items_for(H, W, plan.bm_split2)) : 0,
         s2 ? gbm3d::stack_items_for(H, W) : 0,
         s2 ? gbm3d::group_items_for(H, W, R) : 0,
         s2 ? gbm3d::reduce_items_for(H, W) : 0,
@@ -386,6 +477,25 @@ WorkList worklist(const gbm3d_ctx* ctx, const BatchPlan& plan, int n, int phase)
   return w;
 }
 
+// Batch matching phase: norm tables first when the correlation kernel runs.
+int launch_batch_match(gbm3d_ctx* ctx, const WorkList& nm, const WorkList& bm, int R, int K, int method, int split,
+                       int use_pilot, hipStream_t st) {
+  const ImgRec none = blank_rec(0, 0, 0.0f);
+  const int cu = ctx->n_cu;
+  if (method == GBM3D_BM_CORR) {
+    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(none, &nm, use_pilot, 4 * cu, st); }),
+            "batch norm tables");
+    HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
+              return gbm3d::launch_bm_corr(none, &bm, R, K, split, use_pilot, 4 * cu, st);
+            }),
+            "batch block matching");
+  } else {
+    HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(none, &bm, R, K, split, use_pilot, 2 * cu, st); }),
+            "batch block matching");
+  }
+  return GBM3D_OK;
+}
+
 // The batch launch sequence (also what a graph captures).  Persistent grids:
 // two matching / stack workgroups, one group workgroup and eight reduction
 // workgroups per compute unit.
@@ -394,12 +504,10 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
   const ImgRec none = blank_rec(0, 0, 0.0f);
   const int cu = ctx->n_cu;
   if (plan.any_stage1) {
-    const WorkList bm = worklist(ctx, plan, n, kBm1), sk = worklist(ctx, plan, n, kStack1);
+    const WorkList nm = worklist(ctx, plan, n, kNorm1), bm = worklist(ctx, plan, n, kBm1);
+    const WorkList sk = worklist(ctx, plan, n, kStack1);
     const WorkList gr = worklist(ctx, plan, n, kGroup1), rd = worklist(ctx, plan, n, kReduce1);
-    HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
-              return gbm3d::launch_bm(none, &bm, R, p.k_ht, plan.bm_split1, 0, 2 * cu, st);
-            }),
-            "batch block matching");
+    CHECK(launch_batch_match(ctx, nm, bm, R, p.k_ht, plan.bm_method1, plan.bm_split1, 0, st));
     HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, 2 * cu, st); }),
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
@@ -410,12 +518,10 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
             "batch aggregation");
   }
   if (plan.any_stage2) {
-    const WorkList bm = worklist(ctx, plan, n, kBm2), sk = worklist(ctx, plan, n, kStack2);
+    const WorkList nm = worklist(ctx, plan, n, kNorm2), bm = worklist(ctx, plan, n, kBm2);
+    const WorkList sk = worklist(ctx, plan, n, kStack2);
     const WorkList gr = worklist(ctx, plan, n, kGroup2), rd = worklist(ctx, plan, n, kReduce2);
-    HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
-              return gbm3d::launch_bm(none, &bm, R, p.k_wiener, plan.bm_split2, 1, 2 * cu, st);
-            }),
-            "batch block matching");
+    CHECK(launch_batch_match(ctx, nm, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
     HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, 2 * cu, st); }),
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, 2 * cu, st); }),
@@ -473,6 +579,8 @@ std::string graph_key(const BatchPlan& plan, int n, const gbm3d_params& p, int f
   add(&ctx->batch_table.p, sizeof(void*));
   add(&plan.bm_split1, sizeof(int));
   add(&plan.bm_split2, sizeof(int));
+  add(&plan.bm_method1, sizeof(int));
+  add(&plan.bm_method2, sizeof(int));
   for (int ph = 0; ph < kPhases; ++ph) add(plan.begin[ph].data(), sizeof(int) * (n + 1));
   return k;
 }
@@ -496,6 +604,7 @@ void gbm3d_default_params(gbm3d_params* p) {
   p->tv_eps_rel = 1e-3f;
   p->keep_dc = 1;
   p->bm_split = 0;
+  p->bm_method = GBM3D_BM_AUTO;
 }
 
 int gbm3d_create(gbm3d_ctx** out, int hip_device) {
@@ -526,7 +635,7 @@ void gbm3d_destroy(gbm3d_ctx* ctx) {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     drop_graph(ctx);
-    for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->batch_ws,
+    for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->norm, &ctx->batch_ws,
                       &ctx->batch_table, &ctx->pilot_w, &ctx->pilot_act, &ctx->pilot_part})
       if (b->p) (void)hipFree(b->p);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
@@ -574,9 +683,99 @@ int gbm3d_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, const 
   r.noisy = img;
   r.idx = idx;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(ctx,
-          timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(r, nullptr, p.search / 2, K, p.bm_split, 0, 0, st); }),
-          "block matching launch");
+  return run_match(ctx, r, p.search / 2, K, p, 0, st);
+}
+
+int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, int reps, int* best_method,
+                   int* best_split, float* best_ms, void* stream) {
+  gbm3d_params p;
+  gbm3d_default_params(&p);
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!img) return fail(ctx, GBM3D_EINVAL, "NULL image pointer");
+  if (reps < 1) return fail(ctx, GBM3D_EINVAL, "reps %d must be >= 1", reps);
+  CHECK(check_shape(ctx, H, W, p));
+  CHECK(check_k(ctx, K, p, "K"));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * K * sizeof(int16_t), "idx"));
+  ImgRec r = blank_rec(H, W, 1.0f);
+  r.noisy = img;
+  r.idx = static_cast<int16_t*>(ctx->idx.p);
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIP_TRY(ctx, hipEventCreate(&ev.a), "hipEventCreate");
+  HIP_TRY(ctx, hipEventCreate(&ev.b), "hipEventCreate");
+  struct TimingOff {
+    gbm3d_ctx* c;
+    bool was;
+    ~TimingOff() { c->timing = was; }
+  } off{ctx, ctx->timing};
+  ctx->timing = false;
+  TuneEntry best;
+  best.ms = INFINITY;
+  const int R = p.search / 2;
+  for (int method : {GBM3D_BM_SHIFT, GBM3D_BM_CORR}) {
+    for (int split : {1, 2, 4}) {
+      const BmChoice c{method, split};
+      CHECK(run_match(ctx, r, R, K, c, 0, st));  // warm-up (and workspace)
+      HIP_TRY(ctx, hipEventRecord(ev.a, st), "hipEventRecord");
+      for (int i = 0; i < reps; ++i) CHECK(run_match(ctx, r, R, K, c, 0, st));
+      HIP_TRY(ctx, hipEventRecord(ev.b, st), "hipEventRecord");
+      HIP_TRY(ctx, hipEventSynchronize(ev.b), "hipEventSynchronize");
+      float ms = 0.0f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+      ms /= static_cast<float>(reps);
+      if (ms < best.ms) best = TuneEntry{method, split, ms};
+    }
+  }
+  ctx->tuned[{K, tile_class(gbm3d::corr_tiles(H, W))}] = best;
+  if (best_method) *best_method = best.method;
+  if (best_split) *best_split = best.split;
+  if (best_ms) *best_ms = best.ms;
+  return GBM3D_OK;
+}
+
+int gbm3d_tune_save(const gbm3d_ctx* ctx, const char* path) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  gbm3d_ctx* c = const_cast<gbm3d_ctx*>(ctx);
+  if (!path) return fail(c, GBM3D_EINVAL, "NULL path");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(c, GBM3D_EINVAL, "cannot write %s", path);
+  for (const auto& kv : ctx->tuned)
+    std::fprintf(f, "%d %d %d %d %.6f\n", kv.first.first, kv.first.second, kv.second.method, kv.second.split,
+                 static_cast<double>(kv.second.ms));
+  const bool ok = std::fclose(f) == 0;
+  return ok ? GBM3D_OK : fail(c, GBM3D_EINVAL, "cannot write %s", path);
+}
+
+int gbm3d_tune_load(gbm3d_ctx* ctx, const char* path) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!path) return fail(ctx, GBM3D_EINVAL, "NULL path");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(ctx, GBM3D_EINVAL, "cannot read %s", path);
+  std::vector<std::pair<std::pair<int, int>, TuneEntry>> rows;
+  int K, cls, method, split, line = 0;
+  double ms;
+  int got;
+  while ((got = std::fscanf(f, "%d %d %d %d %lf", &K, &cls, &method, &split, &ms)) == 5) {
+    ++line;
+    if (!is_pow2_group(K) || cls < 0 || cls > 62 || (method != GBM3D_BM_SHIFT && method != GBM3D_BM_CORR) ||
+        (split != 1 && split != 2 && split != 4) || !(ms >= 0.0)) {
+      std::fclose(f);
+      return fail(ctx, GBM3D_EINVAL, "%s: entry %d out of range", path, line);
+    }
+    rows.push_back({{K, cls}, TuneEntry{method, split, static_cast<float>(ms)}});
+  }
+  const bool at_end = got == EOF && std::feof(f);
+  std::fclose(f);
+  if (!at_end) return fail(ctx, GBM3D_EINVAL, "%s: cannot parse entry %d", path, line + 1);
+  for (const auto& r : rows) ctx->tuned[r.first] = r.second;
   return GBM3D_OK;
 }
 
@@ -804,7 +1003,7 @@ int gbm3d_pilot_infer(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W
 }
 
 int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target, int B, int H, int W,
-                     const float* sigma, float* grad, float* loss, void* stream) {
+                     const float* sigma, const float* weight, float* grad, float* loss, void* stream) {
   if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
   if (!noisy || !target || !sigma || !grad || !loss) return fail(ctx, GBM3D_EINVAL, "NULL argument");
   CHECK(check_pilot_shape(ctx, B, H, W));
@@ -829,7 +1028,8 @@ int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target,
                                             gbm3d::pilot_wgrad_partial_floats(wg_grid) * sizeof(float));
   CHECK(pilot_forward(ctx, noisy, B, H, W, sigma, true, nullptr, pil, st));
   HIP_TRY(ctx, timed(ctx, "pilot_loss", st, [&] {
-            return gbm3d::launch_pilot_loss(pil, target, npix, gbuf[0], lpart, loss_blocks, loss, st);
+            return gbm3d::launch_pilot_loss(pil, target, weight, static_cast<size_t>(H) * W, npix, gbuf[0], lpart,
+                                            loss_blocks, loss, st);
           }),
           "pilot loss");
   const PilotWeights pw = pilot_weights(ctx);

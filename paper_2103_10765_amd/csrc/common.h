@@ -217,6 +217,7 @@ struct ImgRec {
   float* stack_b;                  // f32 [H*W][64]
   int16_t* idx;                    // i16 [n_ref][K]
   unsigned long long* partials;    // 64-bit fixed-point tile sums
+  double* norm;                    // block norms with a periodic border (correlation matching)
   int H, W;
   float sigma, eps;
 };

@@ -24,6 +24,19 @@ int bm_auto_split(long total_waves_unsplit);
 long bm_waves_unsplit(int H, int W);
 int bm_items_for(int H, int W, int split);
 
+// Correlation-form matching (Theorem 1, int8 matrix cores): the same indices.
+// launch_bm_norm writes rec.norm (norm_bytes: the block norms of the noisy or
+// pilot image with a periodic border) and must precede launch_bm_corr on the
+// stream.  split: waves sharing a 4x4 reference tile (1, 2, 4; 0 = by size).
+hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int use_pilot, int grid_cap, hipStream_t st);
+hipError_t launch_bm_corr(const ImgRec& one, const WorkList* wl, int R, int K, int split, int use_pilot, int grid_cap,
+                          hipStream_t st);
+size_t norm_bytes(int H, int W);
+int norm_items_for(int H, int W);
+int corr_items_for(int H, int W, int split);
+long corr_tiles(int H, int W);
+int corr_auto_split(long tiles);
+
 // 2-D transform (kind 0 = bior1.5 Mallat, 1 = DCT) of every block of noisy
 // (src_sel 0) or pilot (1) into stack_a (dst_sel 0) or stack_b (1), [H*W][64].
 hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src_sel, int dst_sel, int grid_cap,

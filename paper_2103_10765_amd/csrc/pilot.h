@@ -33,8 +33,9 @@ hipError_t launch_pilot_prep(const uint16_t* noisy, const float* sigma, int N, i
 hipError_t launch_pilot_conv(int mode, const uint16_t* in, const uint16_t* w, const float* bias, const uint16_t* mask,
                              uint16_t* out, const uint16_t* noisy, float* pilot_f32, uint16_t* pilot_u16, int N,
                              int H, int W, int grid_cap, hipStream_t st);
-hipError_t launch_pilot_loss(const float* pilot, const float* target, size_t n, uint16_t* g, double* part, int n_part,
-                             float* loss, hipStream_t st);
+// loss = sum_p weight[p / hw] (pilot - target)^2 / n (weight NULL: 1), and dL/df
+hipError_t launch_pilot_loss(const float* pilot, const float* target, const float* weight, size_t hw, size_t n,
+                             uint16_t* g, double* part, int n_part, float* loss, hipStream_t st);
 hipError_t launch_pilot_wgrad(const uint16_t* x, const uint16_t* g, int N, int H, int W, int grid, float* partial,
                               int layer, float* grad_layer, hipStream_t st);
 hipError_t launch_pilot_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1, float b2,

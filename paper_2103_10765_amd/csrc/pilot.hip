@@ -282,20 +282,23 @@ __global__ void prep_kernel(const uint16_t* __restrict__ noisy, const float* __r
   }
 }
 
-// loss gradient of the mean squared error: dL/df = -2 (pilot - target) / n,
-// written as channel 0 of a 32-channel bf16 tensor; per-block partial sums of
-// the squared error in double.
+// loss gradient of the (per-image weighted) mean squared error:
+// dL/df = -2 w_b (pilot - target) / n with w_b = weight[pixel / hw] (1 if no
+// weights), written as channel 0 of a 32-channel bf16 tensor; per-block
+// partial sums of the weighted squared error in double.
 __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ pilot, const float* __restrict__ target,
-                                                   size_t n, uint16_t* __restrict__ g, double* __restrict__ part) {
+                                                   const float* __restrict__ weight, size_t hw, size_t n,
+                                                   uint16_t* __restrict__ g, double* __restrict__ part) {
   __shared__ double red[256];
   double s = 0.0;
   const float scale = -2.0f / static_cast<float>(n);
   for (size_t p = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; p < n;
        p += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const float w = weight ? weight[p / hw] : 1.0f;
     const float d = pilot[p] - target[p];
-    s += static_cast<double>(d) * d;
+    s += static_cast<double>(w) * d * d;
     uint4* dst = reinterpret_cast<uint4*>(g + p * kC);
-    dst[0] = make_uint4(f2bf(scale * d), 0, 0, 0);
+    dst[0] = make_uint4(f2bf(scale * w * d), 0, 0, 0);
     dst[1] = make_uint4(0, 0, 0, 0);
     dst[2] = make_uint4(0, 0, 0, 0);
     dst[3] = make_uint4(0, 0, 0, 0);
@@ -396,9 +399,9 @@ hipError_t launch_pilot_conv(int mode, const uint16_t* in, const uint16_t* w, co
   return hipGetLastError();
 }
 
-hipError_t launch_pilot_loss(const float* pilot, const float* target, size_t n, uint16_t* g, double* part, int n_part,
-                             float* loss, hipStream_t st) {
-  hipLaunchKernelGGL(loss_kernel, dim3(n_part), dim3(256), 0, st, pilot, target, n, g, part);
+hipError_t launch_pilot_loss(const float* pilot, const float* target, const float* weight, size_t hw, size_t n,
+                             uint16_t* g, double* part, int n_part, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(loss_kernel, dim3(n_part), dim3(256), 0, st, pilot, target, weight, hw, n, g, part);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, st, part, n_part, n, loss);
   return hipGetLastError();
 }

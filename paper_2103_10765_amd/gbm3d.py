@@ -19,6 +19,7 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
 BATCH_GRAPH, BATCH_BASIC_ONLY = 1, 2
 W_TV, W_NNZ, W_UNIT = 0, 1, 2
 STACK_BIOR15, STACK_DCT = 0, 1
+BM_AUTO, BM_SHIFT, BM_CORR = 0, 1, 2
 
 
 class Params(ctypes.Structure):
@@ -35,6 +36,7 @@ class Params(ctypes.Structure):
         ("tv_eps_rel", ctypes.c_float),
         ("keep_dc", ctypes.c_int32),
         ("bm_split", ctypes.c_int32),
+        ("bm_method", ctypes.c_int32),
     ]
 
 
@@ -80,12 +82,16 @@ _SIGNATURES = {
     "gbm3d_pilot_param_count": (_I, []),
     "gbm3d_pilot_load": (_I, [_P, _P, _P]),
     "gbm3d_pilot_infer": (_I, [_P, _P, _I, _I, _I, _P, _P, _P, _P]),
-    "gbm3d_pilot_grad": (_I, [_P, _P, _P, _I, _I, _I, _P, _P, _P, _P]),
+    "gbm3d_pilot_grad": (_I, [_P, _P, _P, _I, _I, _I, _P, _P, _P, _P, _P]),
     "gbm3d_pilot_adam": (_I, [_P, _P, _P, _P, _P, _I, _F, _F, _F, _F, _P]),
     "gbm3d_timing_enable": (_I, [_P, _I]),
     "gbm3d_timing_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)]),
     "gbm3d_timing_reset": (_I, [_P]),
+    "gbm3d_autotune": (_I, [_P, _P, _I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                            ctypes.POINTER(_F), _P]),
+    "gbm3d_tune_save": (_I, [_P, ctypes.c_char_p]),
+    "gbm3d_tune_load": (_I, [_P, ctypes.c_char_p]),
 }
 
 
@@ -186,12 +192,15 @@ class Context:
 
     # -- entry points ------------------------------------------------------
     def match(self, img: torch.Tensor, K: int, params: Params | None = None, out=None, stream=None,
-              split: int | None = None):
+              split: int | None = None, method: int | None = None):
         H, W = _hw(img)
         p = params if params is not None else default_params()
-        if split is not None:
+        if split is not None or method is not None:
             p = Params.from_buffer_copy(p)
-            p.bm_split = split
+            if split is not None:
+                p.bm_split = split
+            if method is not None:
+                p.bm_method = method
         n = n_refs(H, W, p.step)
         if out is None:
             out = torch.empty((n, K), dtype=torch.int16, device=img.device)
@@ -290,17 +299,21 @@ class Context:
         return pu, pf
 
     def pilot_grad(self, noisy: torch.Tensor, target: torch.Tensor, sigma: torch.Tensor, grad=None, loss=None,
-                   stream=None):
+                   stream=None, weight: torch.Tensor | None = None):
         B, H, W = (int(v) for v in noisy.shape)
         if tuple(target.shape) != (B, H, W) or sigma.numel() != B:
             raise ValueError("shape mismatch")
+        if weight is not None and weight.numel() != B:
+            raise ValueError("weight needs one value per image")
         if grad is None:
             grad = torch.empty(pilot_param_count(), dtype=torch.float32, device=noisy.device)
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=noisy.device)
         self._check(lib().gbm3d_pilot_grad(self._h, _dev(noisy, torch.uint16, "noisy"),
                                            _dev(target, torch.float32, "target"), B, H, W,
-                                           _dev(sigma, torch.float32, "sigma"), _dev(grad, torch.float32, "grad"),
+                                           _dev(sigma, torch.float32, "sigma"),
+                                           None if weight is None else _dev(weight, torch.float32, "weight"),
+                                           _dev(grad, torch.float32, "grad"),
                                            _dev(loss, torch.float32, "loss"), _stream(stream)))
         return grad, loss
 
@@ -322,6 +335,21 @@ class Context:
         n = ctypes.c_int64()
         self._check(lib().gbm3d_timing_read(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def autotune(self, img: torch.Tensor, K: int, reps: int = 3, stream=None):
+        """Times every block-matching variant on img and records the fastest
+        for its shape class; returns (method, split, ms per run)."""
+        H, W = _hw(img)
+        m, sp, ms = _I(), _I(), _F()
+        self._check(lib().gbm3d_autotune(self._h, _dev(img, torch.uint16, "img"), H, W, K, reps,
+                                         ctypes.byref(m), ctypes.byref(sp), ctypes.byref(ms), _stream(stream)))
+        return m.value, sp.value, ms.value
+
+    def tune_save(self, path: str):
+        self._check(lib().gbm3d_tune_save(self._h, os.fsencode(path)))
+
+    def tune_load(self, path: str):
+        self._check(lib().gbm3d_tune_load(self._h, os.fsencode(path)))
 
     def quantize(self, x: torch.Tensor, out=None, stream=None):
         if out is None:

@@ -40,6 +40,7 @@ def test_default_params(G):
     assert (p.patch, p.step, p.search, p.k_ht, p.k_wiener) == (8, 3, 39, 16, 32)
     assert abs(p.ht_a - 3.6) < 1e-6 and abs(p.ht_b - 0.3) < 1e-6
     assert p.ht_weight == G.W_TV and p.keep_dc == 1
+    assert p.bm_split == 0 and p.bm_method == G.BM_AUTO
 
 
 def test_status_strings_and_version(G):
@@ -75,6 +76,10 @@ def test_validation_rules(G):
     assert G.check_args(512, 512, s25, G.default_params(ht_weight=7)) == G.EINVAL
     assert G.check_args(512, 512, s25, G.default_params(tv_eps_rel=-1.0)) == G.EINVAL
     assert G.check_args(512, 512, s25, G.default_params(tv_eps_rel=0.0)) == G.EINVAL
+    for m in (G.BM_AUTO, G.BM_SHIFT, G.BM_CORR):
+        assert G.check_args(512, 512, s25, G.default_params(bm_method=m)) == G.OK
+    assert G.check_args(512, 512, s25, G.default_params(bm_method=3)) == G.EINVAL
+    assert G.check_args(512, 512, s25, G.default_params(bm_split=3)) == G.EINVAL
     p = G.default_params()
     p.struct_size = 4
     assert G.check_args(512, 512, s25, p) == G.EINVAL
@@ -86,6 +91,9 @@ def test_null_context_is_rejected(G):
     assert L.gbm3d_basic(None, None, 64, 64, 0.1, None, None, None) == G.EINVAL
     assert L.gbm3d_denoise(None, None, 64, 64, 0.1, None, None, None, None, None) == G.EINVAL
     assert "ctx" in G.last_thread_error()
+    assert L.gbm3d_autotune(None, None, 64, 64, 16, 1, None, None, None, None) == G.EINVAL
+    assert L.gbm3d_tune_load(None, b"/nonexistent") == G.EINVAL
+    assert L.gbm3d_tune_save(None, b"/nonexistent") == G.EINVAL
 
 
 def test_create_without_device_fails_cleanly(G):

@@ -93,21 +93,26 @@ MATCH_CASES = [
 ]
 
 
+METHODS = [1, 2]   # shift-wise, correlation (matrix cores)
+
+
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("H,W,S,K,seed", MATCH_CASES)
-def test_match_bit_exact(torch, G, ctx, H, W, S, K, seed):
-    say("match", H, W, S, K)
+def test_match_bit_exact(torch, G, ctx, H, W, S, K, seed, method):
+    say("match", H, W, S, K, "method", method)
     _, Z = synth.make_case(H, W, SIG, seed)
-    p = G.default_params(search=S)
+    p = G.default_params(search=S, bm_method=method)
     got = ctx.match(up(torch, Z), K, p).cpu().numpy().astype(np.int64)
     exp = O.match(Z, K, O.DEFAULT.with_(search=S))
     bad = np.nonzero((got != exp).any(axis=1))[0]
     assert bad.size == 0, (bad[:5], got[bad[:2]], exp[bad[:2]])
 
 
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("kind", ["flat", "lowbits", "periodic", "extremes"])
-def test_match_ties(torch, G, ctx, kind):
+def test_match_ties(torch, G, ctx, kind, method):
     H, W, S, K = 60, 70, 15, 16
-    say("match ties", kind)
+    say("match ties", kind, "method", method)
     rng = np.random.default_rng(40)
     if kind == "flat":
         Z = np.full((H, W), 777, dtype=np.uint16)
@@ -117,30 +122,32 @@ def test_match_ties(torch, G, ctx, kind):
         Z = np.tile(rng.integers(0, 65536, size=(5, 7)), (12, 10))[:H, :W].astype(np.uint16)
     else:
         Z = (rng.integers(0, 2, size=(H, W)) * 65535).astype(np.uint16)
-    p = G.default_params(search=S)
+    p = G.default_params(search=S, bm_method=method)
     got = ctx.match(up(torch, Z), K, p).cpu().numpy().astype(np.int64)
     exp = O.match(Z, K, O.DEFAULT.with_(search=S))
     assert np.array_equal(got, exp)
 
 
-def test_match_full_size_sampled(torch, G, ctx):
+@pytest.mark.parametrize("method", METHODS)
+def test_match_full_size_sampled(torch, G, ctx, method):
     """512 x 512, search 39, K = 16 and 32: 400 sampled references."""
     _, Z = synth.single_image_case(512, SIG, 2)
     ids = np.random.default_rng(0).choice(O.n_refs(512, 512, 3), 400, replace=False)
     for K in (16, 32):
-        say("match 512 sampled K", K)
-        got = ctx.match(up(torch, Z), K).cpu().numpy().astype(np.int64)[ids]
+        say("match 512 sampled K", K, "method", method)
+        got = ctx.match(up(torch, Z), K, method=method).cpu().numpy().astype(np.int64)[ids]
         exp = O.match(Z, K, O.DEFAULT, ref_ids=ids)
         assert np.array_equal(got, exp)
 
 
-def test_match_max_width_sampled(torch, G, ctx):
+@pytest.mark.parametrize("method", METHODS)
+def test_match_max_width_sampled(torch, G, ctx, method):
     """The widest supported image (W = 32768), 40 rows; sampled references."""
     H, W = 40, 32768
-    say("match max width")
+    say("match max width", "method", method)
     _, Z = synth.make_case(H, W, SIG, 8)
     ids = np.random.default_rng(1).choice(O.n_refs(H, W, 3), 200, replace=False)
-    got = ctx.match(up(torch, Z), 16).cpu().numpy().astype(np.int64)[ids]
+    got = ctx.match(up(torch, Z), 16, method=method).cpu().numpy().astype(np.int64)[ids]
     exp = O.match(Z, 16, O.DEFAULT, ref_ids=ids)
     assert np.array_equal(got, exp)
 
@@ -328,13 +335,60 @@ def test_side_stream_and_repeat(torch, G, ctx):
         assert np.array_equal(a, ctx.denoise(Zt, SIG).cpu().numpy())
 
 
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("split", [1, 2, 4])
-def test_match_workgroup_shapes_agree(torch, G, ctx, split):
-    """Every workgroup shape of the matching kernel gives the oracle's indices."""
+def test_match_workgroup_shapes_agree(torch, G, ctx, split, method):
+    """Every workgroup shape of both matching kernels gives the oracle's indices."""
+    say("match workgroup shape", split, "method", method)
     _, Z = synth.make_case(90, 200, SIG, 17)
-    exp = O.match(Z, 16, O.DEFAULT.with_(search=21))
-    got = ctx.match(up(torch, Z), 16, G.default_params(search=21), split=split).cpu().numpy().astype(np.int64)
-    assert np.array_equal(got, exp)
+    for K in (16, 32):
+        exp = O.match(Z, K, O.DEFAULT.with_(search=21))
+        got = ctx.match(up(torch, Z), K, G.default_params(search=21), split=split,
+                        method=method).cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, exp)
+
+
+def test_methods_give_identical_denoising(torch, G, ctx):
+    """Same indices, so both stages give bit-identical outputs with either
+    matching kernel (single image and batch)."""
+    say("denoise shift vs corr")
+    clean, Z = synth.make_case(200, 230, SIG, 18)
+    Zt = up(torch, Z)
+    a = ctx.denoise(Zt, SIG, G.default_params(bm_method=1)).cpu().numpy()
+    b = ctx.denoise(Zt, SIG, G.default_params(bm_method=2)).cpu().numpy()
+    assert np.array_equal(a, b)
+    imgs, sig = _batch_inputs(torch, 4, 39, 140, 720)
+    ra = [o.cpu().numpy() for o in ctx.denoise_batch(imgs, sig, params=G.default_params(bm_method=1))]
+    rb = [o.cpu().numpy() for o in ctx.denoise_batch(imgs, sig, params=G.default_params(bm_method=2), graph=True)]
+    torch.cuda.synchronize()
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y)
+
+
+def test_autotune_records_and_reloads(torch, G, ctx, tmp_path):
+    """The autotuner times every variant, its choice is then used for auto
+    params (same indices), and the choices survive a save / load."""
+    say("autotune")
+    _, Z = synth.make_case(150, 160, SIG, 19)
+    Zt = up(torch, Z)
+    m, sp, ms = ctx.autotune(Zt, 16, reps=2)
+    assert m in (1, 2) and sp in (1, 2, 4) and ms > 0
+    exp = O.match(Z, 16, O.DEFAULT)
+    assert np.array_equal(ctx.match(Zt, 16).cpu().numpy().astype(np.int64), exp)
+    path = str(tmp_path / "tune.txt")
+    ctx.tune_save(path)
+    line = open(path).read().split()
+    assert [int(x) for x in line[:4]][2:] == [m, sp]
+    c2 = G.Context(0)
+    try:
+        c2.tune_load(path)
+        assert np.array_equal(c2.match(Zt, 16).cpu().numpy().astype(np.int64), exp)
+        bad = tmp_path / "bad.txt"
+        bad.write_text("16 5 9 1 0.1\n")
+        with pytest.raises(G.GBM3DError):
+            c2.tune_load(str(bad))
+    finally:
+        c2.close()
 
 
 # ---------------------------------------------------------------------------
@@ -407,3 +461,49 @@ def test_batch_oracle_psnr(torch, G, ctx):
     for (clean, Z), s, o in zip(cases, sig, outs):
         Y, _, _ = O.denoise(Z, s, O.DEFAULT.with_(search=21))
         assert abs(O.psnr(o.cpu().numpy().astype(np.float64), clean) - O.psnr(Y, clean)) <= PSNR_TOL
+
+
+# ---------------------------------------------------------------------------
+# the large single image (4096 x 4096 with edge-rich rectangles)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def large_case():
+    return synth.large_image_case(4096, SIG, 4)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_large_match_sampled(torch, G, ctx, large_case, method):
+    """4096 x 4096, search 39, K = 16: 300 sampled references bit-exact."""
+    _, Z = large_case
+    say("match 4096 sampled", "method", method)
+    ids = np.random.default_rng(3).choice(O.n_refs(4096, 4096, 3), 300, replace=False)
+    got = ctx.match(up(torch, Z), 16, method=method).cpu().numpy().astype(np.int64)[ids]
+    exp = O.match(Z, 16, O.DEFAULT, ref_ids=ids)
+    assert np.array_equal(got, exp)
+
+
+def test_large_stages_windows(torch, G, ctx, large_case):
+    """4096 x 4096: stage 1 and stage 2 (pilot = clean image quantised) on
+    windows that the oracle evaluates exactly (interior and wrapping)."""
+    clean, Z = large_case
+    Zt = up(torch, Z)
+    say("basic 4096")
+    Yg = ctx.basic(Zt, SIG).cpu().numpy().astype(np.float64)
+    p = O.DEFAULT
+    for (y0, x0, h, w) in _windows(4096, 4096, 16, 16):
+        say("basic 4096 window", y0, x0)
+        ids = O.refs_for_window(4096, 4096, p, y0, x0, h, w)
+        Yo, (idx, margin, _, _) = O.basic_estimate(Z, SIG, p, ref_ids=ids, return_parts=True)
+        rows, cols = (y0 + np.arange(h)) % 4096, (x0 + np.arange(w)) % 4096
+        _check_stage1(Yg, Yo, idx, margin, p, ref_ids=ids, window=(rows, cols))
+    del Yg
+    pilot = synth.to_u16(clean)
+    say("wiener 4096")
+    Yw = ctx.wiener(Zt, up(torch, pilot), SIG).cpu().numpy().astype(np.float64)
+    for (y0, x0, h, w) in _windows(4096, 4096, 12, 12):
+        say("wiener 4096 window", y0, x0)
+        ids = O.refs_for_window(4096, 4096, O.DEFAULT, y0, x0, h, w)
+        Yo = O.wiener_estimate(Z, pilot, SIG, O.DEFAULT, ref_ids=ids)
+        rows, cols = (y0 + np.arange(h)) % 4096, (x0 + np.arange(w)) % 4096
+        assert np.abs(Yw[np.ix_(rows, cols)] - Yo[np.ix_(rows, cols)]).max() <= MAXABS
