@@ -86,16 +86,19 @@ def forward(theta: np.ndarray, z: np.ndarray, sigma, bf16: bool = True):
     return np.asarray(z, dtype=np.float64) - f, acts
 
 
-def loss_and_grad(theta: np.ndarray, z: np.ndarray, sigma, target: np.ndarray, bf16: bool = True):
-    """Mean squared error of the pilot against `target` and its gradient with
-    respect to theta (backpropagation through the convolutions; ReLU
-    derivative taken as 1 where the layer output is positive)."""
+def loss_and_grad(theta: np.ndarray, z: np.ndarray, sigma, target: np.ndarray, bf16: bool = True, weight=None):
+    """Mean squared error of the pilot against `target` (each image's squared
+    errors scaled by weight[b] when given) and its gradient with respect to
+    theta (backpropagation through the convolutions; ReLU derivative taken as
+    1 where the layer output is positive)."""
     params = unpack(np.asarray(theta, dtype=np.float64))
     pilot, acts = forward(theta, z, sigma, bf16)
     diff = pilot - np.asarray(target, dtype=np.float64)
     n = diff.size
-    loss = float(np.mean(diff * diff))
-    g = (-2.0 / n * diff)[..., None]            # dL/df, one channel
+    wb = np.ones(diff.shape[0]) if weight is None else np.asarray(weight, dtype=np.float64)
+    wd = wb[:, None, None] * diff
+    loss = float(np.sum(wd * diff) / n)
+    g = (-2.0 / n * wd)[..., None]              # dL/df, one channel
     grads = []
     for l in range(len(params) - 1, -1, -1):
         W, _ = params[l]

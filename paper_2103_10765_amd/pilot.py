@@ -95,11 +95,22 @@ def lr_at(step: int, total: int, lr0: float = 1e-3, lr1: float = 1e-5) -> float:
     return lr1 + 0.5 * (lr0 - lr1) * (1.0 + np.cos(np.pi * t))
 
 
+def loss_weights(sig_t, mode: str):
+    """Per-crop loss weights: 'none' (plain mean squared error) or 'sigma'
+    ((sigma_ref / sigma)^2 with sigma_ref = 25/255, so that every noise level
+    contributes errors of the same relative size)."""
+    if mode == "none":
+        return None
+    if mode == "sigma":
+        return (synth.SIGMA25 / sig_t) ** 2
+    raise ValueError(mode)
+
+
 def train(ctx, Zt, target, sig_t, steps: int, batch: int = 64, seed: int = 0, ckpt: str | None = None,
-          ckpt_every: int = 500, resume: bool = True, log=print):
-    """Adam on the mean squared error between the pilot and the stage-1
-    target.  The batch order is a seeded permutation per epoch, so a resumed
-    run continues exactly where it stopped."""
+          ckpt_every: int = 500, resume: bool = True, log=print, weighting: str = "none"):
+    """Adam on the (optionally per-crop weighted) mean squared error between
+    the pilot and the stage-1 target.  The batch order is a seeded permutation
+    per epoch, so a resumed run continues exactly where it stopped."""
     import torch
     n = Zt.shape[0]
     dev = Zt.device
@@ -116,6 +127,7 @@ def train(ctx, Zt, target, sig_t, steps: int, batch: int = 64, seed: int = 0, ck
     grad = torch.empty_like(master)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     per_epoch = max(n // batch, 1)
+    w_all = loss_weights(sig_t, weighting)
     t0 = time.perf_counter()
     hist = []
     for step in range(step0 + 1, steps + 1):
@@ -123,13 +135,15 @@ def train(ctx, Zt, target, sig_t, steps: int, batch: int = 64, seed: int = 0, ck
         perm = np.random.default_rng(seed * 100003 + epoch).permutation(n)
         ids = torch.from_numpy(perm[k * batch:(k + 1) * batch].astype(np.int64)).to(dev)
         ctx.pilot_grad(Zt.index_select(0, ids).contiguous(), target.index_select(0, ids).contiguous(),
-                       sig_t.index_select(0, ids).contiguous(), grad=grad, loss=loss)
+                       sig_t.index_select(0, ids).contiguous(), grad=grad, loss=loss,
+                       weight=None if w_all is None else w_all.index_select(0, ids).contiguous())
         ctx.pilot_adam(master, m, v, grad, step, lr_at(step, steps))
         if step % 100 == 0 or step == steps:
             hist.append((step, loss.item()))
             log(f"step {step} loss {hist[-1][1]:.3e} lr {lr_at(step, steps):.2e} {time.perf_counter() - t0:.1f}s")
         if ckpt and (step % ckpt_every == 0 or step == steps):
-            save_checkpoint(ckpt, master, m, v, step, {"batch": batch, "seed": seed, "steps": steps})
+            save_checkpoint(ckpt, master, m, v, step, {"batch": batch, "seed": seed, "steps": steps,
+                                                       "weighting": weighting})
     torch.cuda.synchronize()
     return master, hist
 
@@ -195,6 +209,7 @@ def main(argv=None):
     t.add_argument("--ckpt", default=None)
     t.add_argument("--workers", type=int, default=8)
     t.add_argument("--eval", action="store_true")
+    t.add_argument("--weighting", choices=["none", "sigma"], default="none")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
     e.add_argument("--n", type=int, default=32)
@@ -214,7 +229,7 @@ def main(argv=None):
         target = basic_targets(ctx, Zt, sig)
         print(f"stage-1 targets in {time.perf_counter() - t1:.1f}s", flush=True)
         master, _ = train(ctx, Zt, target, sig_t, args.steps, args.batch, args.seed, ckpt=args.ckpt,
-                          log=lambda s: print(s, flush=True))
+                          log=lambda s: print(s, flush=True), weighting=args.weighting)
         np.savez(args.out, master=master.cpu().numpy())
         print(f"saved {args.out}", flush=True)
         if args.eval:

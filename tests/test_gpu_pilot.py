@@ -82,15 +82,18 @@ def test_pilot_forward_parity(torch, G, ctx, shape):
     assert np.array_equal(pu.cpu().numpy(), q)
 
 
-def test_pilot_gradient_parity(torch, G, ctx):
+@pytest.mark.parametrize("weight", [None, [0.25, 3.0]])
+def test_pilot_gradient_parity(torch, G, ctx, weight):
     B, H, W = 2, 16, 40
-    say("pilot gradient")
+    say("pilot gradient", weight)
     theta = _theta(2)
     ctx.pilot_load(torch.from_numpy(theta).cuda())
     Z, sig = _batch(B, H, W, 30)
     target = np.random.default_rng(3).random((B, H, W)).astype(np.float32)
-    grad, loss = ctx.pilot_grad(torch.from_numpy(Z).cuda(), torch.from_numpy(target).cuda(), torch.from_numpy(sig).cuda())
-    lo, go = P.loss_and_grad(theta.astype(np.float64), Z / 65535.0, sig, target, bf16=True)
+    wt = None if weight is None else torch.tensor(weight, dtype=torch.float32, device="cuda")
+    grad, loss = ctx.pilot_grad(torch.from_numpy(Z).cuda(), torch.from_numpy(target).cuda(), torch.from_numpy(sig).cuda(),
+                                weight=wt)
+    lo, go = P.loss_and_grad(theta.astype(np.float64), Z / 65535.0, sig, target, bf16=True, weight=weight)
     assert abs(loss.item() - lo) <= 1e-2 * lo
     g = grad.cpu().numpy().astype(np.float64)
     o = 0

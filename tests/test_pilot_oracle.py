@@ -37,13 +37,14 @@ def test_bf16_round_matches_torch():
     assert P.bf16_round(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6
 
 
-def test_gradient_finite_differences():
+@pytest.mark.parametrize("weight", [None, [0.3, 2.5]])
+def test_gradient_finite_differences(weight):
     rng = np.random.default_rng(2)
     theta = rng.standard_normal(P.n_params()) * 0.2
     z = rng.random((2, 6, 5))
     sigma = np.array([0.1, 0.2])
     target = rng.random((2, 6, 5))
-    loss, g = P.loss_and_grad(theta, z, sigma, target, bf16=False)
+    loss, g = P.loss_and_grad(theta, z, sigma, target, bf16=False, weight=weight)
     idx = rng.choice(P.n_params(), 40, replace=False)
     # include every layer's bias and the last layer's weights
     idx = np.concatenate([idx, [608 - 1, P.n_params() - 1, P.n_params() - 2]])
@@ -52,8 +53,25 @@ def test_gradient_finite_differences():
         tp, tm = theta.copy(), theta.copy()
         tp[i] += h
         tm[i] -= h
-        fd = (P.loss_and_grad(tp, z, sigma, target, False)[0] - P.loss_and_grad(tm, z, sigma, target, False)[0]) / (2 * h)
+        fd = (P.loss_and_grad(tp, z, sigma, target, False, weight)[0] -
+              P.loss_and_grad(tm, z, sigma, target, False, weight)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 + 1e-4 * abs(fd), (i, fd, g[i])
+
+
+def test_weighted_loss_is_the_weighted_mean_of_image_losses():
+    """Per-image weights: loss = (sum_b w_b * n_b * loss_b) / n, where loss_b is
+    image b's own (unweighted) mean squared error."""
+    rng = np.random.default_rng(5)
+    theta = rng.standard_normal(P.n_params()) * 0.2
+    z = rng.random((3, 5, 7))
+    sigma = np.array([0.05, 0.1, 0.2])
+    target = rng.random((3, 5, 7))
+    w = np.array([0.5, 1.0, 4.0])
+    lw, gw = P.loss_and_grad(theta, z, sigma, target, bf16=False, weight=w)
+    parts = [P.loss_and_grad(theta, z[b:b + 1], sigma[b:b + 1], target[b:b + 1], bf16=False) for b in range(3)]
+    assert abs(lw - sum(w[b] * parts[b][0] for b in range(3)) / 3) <= 1e-12 * abs(lw)
+    g_sum = sum(w[b] * parts[b][1] for b in range(3)) / 3
+    assert np.allclose(gw, g_sum, rtol=1e-10, atol=1e-14)
 
 
 def test_residual_output_and_zero_network():
