@@ -37,12 +37,67 @@ def algorithmic_work(H, W, search, k1, k2):
     return {
         # one difference + one fused square-accumulate per (pixel, displacement)
         "bm": ("alu", 3.0 * H * W * (S2 - 1), "FLOP"),
+        "bm_norm": ("hbm", H * W * 2 + (H + 64) * (W + 64) * 8, "B"),
         "stack_bior": ("hbm", H * W * (2 + 256), "B"),
         "stack_dct": ("hbm", H * W * (2 + 256), "B"),
         "group_ht": ("hbm", nref * (k1 * 256 + 2 * k1) + partial_bytes, "B"),
         "group_wiener": ("hbm", nref * (2 * k2 * 256 + 2 * k2) + partial_bytes, "B"),
         "reduce": ("hbm", partial_bytes + H * W * 6, "B"),
     }
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_denoise_512.txt")
+KERNEL_SOURCES = {
+    "bm": ["bm.hip", "bm_corr.hip", "common.h"], "bm_norm": ["bm_corr.hip", "common.h"], "stack_bior": ["stack.hip", "common.h"], "stack_dct": ["stack.hip", "common.h"],
+    "group_ht": ["group.hip", "common.h"], "group_wiener": ["group.hip", "common.h"], "reduce": ["group.hip", "common.h"],
+}
+
+
+def source_digest(kernel):
+    """sha256 over the sources a kernel is compiled from (first 16 hex digits)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2103_10765_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary:
+    (FETCH_SIZE + WRITE_SIZE) per dispatch, each divided by what the same
+    counter reads per byte of a plain device copy of known size.  None when
+    the summary is missing or the kernel's sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0].startswith("@"):
+                vals[parts[0][1:]] = parts[1:]
+    try:
+        fetch_scale = float(vals["copy_fetch_kib_per_byte"][0])
+        write_scale = float(vals["copy_write_kib_per_byte"][0])
+        digest, fetch_kib, write_kib = vals[f"kernel_{kernel}"][:3]
+    except (KeyError, ValueError, IndexError):
+        return None
+    if digest != source_digest(kernel):
+        return None
+    return float(fetch_kib) / fetch_scale + float(write_kib) / write_scale
+
+
+def copy_calibration(mib):
+    """One plain device-to-device copy of `mib` MiB (the reference kernel for
+    scaling FETCH_SIZE / WRITE_SIZE to bytes)."""
+    import torch
+    n = mib << 20
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "ok": bool(y[-1].item() == 1)}), flush=True)
 
 
 def cpu_baseline(Z, sigma, size=192):
@@ -61,6 +116,70 @@ def cpu_baseline(Z, sigma, size=192):
                       f"{dt:.1f} s, float64 NumPy, 1 thread"}
 
 
+def batch_bench(ctx, reps=5):
+    """64 images of uneven sizes (256..1024 per side), sigma U[10,50]/255, one
+    batched call under hipGraph replay; Mpixel/s over all images."""
+    import torch
+    from paper_2103_10765_amd import synth
+    specs = synth.batch_specs()
+    imgs, sig = [], []
+    for (h, w, s, sd) in specs:
+        _, Z = synth.make_case(h, w, s, sd)
+        imgs.append(torch.from_numpy(Z).cuda())
+        sig.append(s)
+    outs = [torch.empty(tuple(x.shape), dtype=torch.float32, device="cuda") for x in imgs]
+    ctx.denoise_batch(imgs, sig, outs=outs, graph=True)   # capture
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.denoise_batch(imgs, sig, outs=outs, graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    mpx = sum(h * w for (h, w, _, _) in specs) / 1e6
+    return {"images": len(specs), "mpixels": mpx, "ms_per_batch": ms, "mpix_s": mpx / (ms * 1e-3),
+            "mode": "hipGraph replay, persistent kernels over per-image work lists"}
+
+
+def size_bench(ctx, p):
+    """Two-stage Mpixel/s on the small (128^2, seed 1) and the large
+    (4096^2 with edge-rich rectangles, seed 4) single images, sigma 25/255."""
+    import torch
+    from paper_2103_10765_amd import synth
+    res = {}
+    for name, (clean, Z), steps in (("128x128", synth.make_case(128, 128, synth.SIGMA25, 1), 50),
+                                     ("4096x4096", synth.large_image_case(4096, synth.SIGMA25, 4), 3)):
+        Zt = torch.from_numpy(Z).cuda()
+        out = torch.empty(Zt.shape, dtype=torch.float32, device="cuda")
+        ctx.denoise(Zt, synth.SIGMA25, p, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ctx.denoise(Zt, synth.SIGMA25, p, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms_per_image": ms, "mpix_s": Z.size / (ms * 1e-3) / 1e6, "steps": steps}
+        del Zt, out
+        torch.cuda.empty_cache()
+    return res
+
+
+def pilot_bench(ctx):
+    """Learned pilot vs plain stage 1, both followed by the Wiener stage, on the
+    32 x 512^2 evaluation batch at sigma 25/255 (needs trained weights)."""
+    import numpy as np
+    import torch
+    from paper_2103_10765_amd import pilot
+    if not os.path.exists(pilot.DEFAULT_WEIGHTS):
+        return {"skipped": "no trained pilot weights (python -m paper_2103_10765_amd.pilot train)"}
+    with np.load(pilot.DEFAULT_WEIGHTS, allow_pickle=False) as f:
+        master = torch.from_numpy(f["master"]).cuda()
+    return pilot.evaluate(ctx, master, log=lambda s: None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,7 +188,15 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--sigma", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batch and learned-pilot measurements")
+    ap.add_argument("--bm-method", choices=["tuned", "shift", "corr"], default="tuned",
+                    help="block-matching kernel: autotuned on the benchmark image (default) or fixed")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "images are independent, so a multi-GPU run is a per-GPU split of the batch", file=sys.stderr)
@@ -90,6 +217,14 @@ def main():
     ctx = gbm3d.Context(0)
     p = gbm3d.default_params()
     stream = torch.cuda.current_stream()
+    tuned = {}
+    if args.bm_method == "tuned":
+        # stage 2 matches on the pilot; the noisy image has the same shape class
+        for K in (p.k_ht, p.k_wiener):
+            m, sp, t = ctx.autotune(Zt, K, reps=3)
+            tuned[f"K{K}"] = {"method": {1: "shift", 2: "corr"}[m], "split": sp, "ms": t}
+    else:
+        p.bm_method = {"shift": gbm3d.BM_SHIFT, "corr": gbm3d.BM_CORR}[args.bm_method]
 
     for _ in range(args.warmup):
         ctx.denoise(Zt, sigma, p, out=out)
@@ -116,7 +251,7 @@ def main():
         ctx.denoise(Zt, sigma, p, out=out)
     torch.cuda.synchronize()
     kernels = {}
-    for name in ("bm", "stack_bior", "stack_dct", "group_ht", "group_wiener", "reduce"):
+    for name in ("bm", "bm_norm", "stack_bior", "stack_dct", "group_ht", "group_wiener", "reduce"):
         tot, n = ctx.timing_read(name)
         if n:
             kernels[name] = {"avg_us": 1e3 * tot / n, "launches_per_step": n / args.steps,
@@ -127,6 +262,7 @@ def main():
     for name, k in kernels.items():
         bound, amount, unit = work[name]
         sec = k["avg_us"] * 1e-6
+        k["traffic_bytes"] = measured_traffic(name)
         if bound == "hbm":
             k["gbs"] = amount / sec / 1e9
             k["frac_hbm"] = k["gbs"] / HBM_PEAK_GBS
@@ -138,10 +274,10 @@ def main():
     sec = kernels[dom]["avg_us"] * 1e-6
     if bound == "hbm":
         roof = {"bound": "hbm", "kernel": dom, "achieved": amount / sec / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "traffic": None}
+                "unit": "GB/s", "traffic": measured_traffic(dom)}
     else:
         roof = {"bound": "alu", "kernel": dom, "achieved": amount / sec / 1e12, "peak": FP64_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "traffic": None}
+                "unit": "TFLOP/s", "traffic": measured_traffic(dom)}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["avg_us"] = kernels[dom]["avg_us"]
 
@@ -160,13 +296,21 @@ def main():
         "dtype": "f32 (u16 input, exact f64 distances)",
         "data": "synthetic",
         "config": {"workload": f"plain G-BM3D two-stage, one {H}x{W} grayscale image, sigma={args.sigma:g}/255, "
-                               "patch 8, step 3, search 39, K 16/32", "image_seed": 2},
+                               "patch 8, step 3, search 39, K 16/32", "image_seed": 2,
+                   "block_matching": tuned if tuned else args.bm_method},
         "psnr_db": psnr,
         "psnr_noisy_db": O.psnr(Z / 65535.0, clean),
         "psnr_gap_db": None,
         "roofline": roof,
         "kernels": kernels,
     }
+    if not args.no_extras:
+        pb = pilot_bench(ctx)
+        rec["pilot"] = pb
+        if "psnr_gap_db" in pb:
+            rec["psnr_gap_db"] = pb["psnr_gap_db"]
+        rec["batch"] = batch_bench(ctx)
+        rec["sizes"] = size_bench(ctx, p)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(Z, sigma)
     print(json.dumps(rec), flush=True)

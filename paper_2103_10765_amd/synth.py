@@ -55,11 +55,13 @@ def _paint(img: np.ndarray, rng: np.random.Generator, n_shapes: int) -> None:
             for j in range(3):
                 a = theta + 2 * np.pi * j / 3
                 mask &= (dx * np.cos(a) + dy * np.sin(a)) <= 0.5 * size
-        val = c0 + ramp * (dx * np.cos(ramp_dir) + dy * np.sin(ramp_dir))
+        # fill values, evaluated only where the shape covers the image
+        mdx, mdy, mxx, myy = dx[mask], dy[mask], xx[mask], yy[mask]
+        val = c0 + ramp * (mdx * np.cos(ramp_dir) + mdy * np.sin(ramp_dir))
         if tex:
-            val = val + amp * np.sin(2 * np.pi * freq * (xx * np.cos(fdir) + yy * np.sin(fdir)) + phase)
+            val = val + amp * np.sin(2 * np.pi * freq * (mxx * np.cos(fdir) + myy * np.sin(fdir)) + phase)
         sub = img[y0:y1, x0:x1]
-        sub[mask] = val[mask]
+        sub[mask] = val
 
 
 def clean_image(H: int, W: int, seed: int, edge_rects: int = 0) -> np.ndarray:
