@@ -112,15 +112,15 @@ __device__ __forceinline__ void inverse_level(float* xw, int lane, F&& line) {
   wave_lds_sync();
 }
 
-// Block positions of the group of reference (p, q): lane k < K decodes slot k
-// into a stack position (pixel index) and a packed tile-local top-left.
+// Block positions of the group of reference (p, q): lane k < K decodes the
+// rank r of slot k into a stack position (pixel index) and a packed
+// tile-local top-left.
 template <int K>
-__device__ __forceinline__ void decode_slots(const GroupArgs& g, const int16_t* __restrict__ idx, int p, int q,
-                                             int fy0, int fx0, int lane, int& pos, int& lyx) {
+__device__ __forceinline__ void slot_pos(const GroupArgs& g, int r, int p, int q, int fy0, int fx0, int lane, int& pos,
+                                         int& lyx) {
   pos = 0;
   lyx = 0;
   if (lane < K) {
-    const int r = idx[(static_cast<size_t>(p) * g.nRx + q) * K + lane];
     const int dyi = r / g.S, dxi = r - dyi * g.S;
     const int y = kStep * p + dyi - g.R, x = kStep * q + dxi - g.R;
     pos = pmod(y, g.H) * g.W + pmod(x, g.W);
@@ -155,6 +155,48 @@ __device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __rest
   __syncthreads();  // the accumulator is reused by the next item
 }
 
+// The groups a wave filters in a tile: reference t = wave + j * kWaves,
+// j < kGroupsPerWave.  Loads run ahead of the filtering: the ranks of group
+// j + 2 and the spectra of group j + 1 are in flight while group j is
+// filtered.
+constexpr int kGroupsPerWave = kTPY * kTPX / kWaves;
+
+struct GroupWalk {
+  const GroupArgs& g;
+  const int16_t* __restrict__ idx;
+  int tyi, txi, wave, lane, fy0, fx0;
+
+  __device__ __forceinline__ bool ref_of(int j, int& p, int& q) const {
+    const int t = wave + j * kWaves;
+    p = tyi * kTPY + t / kTPX;
+    q = txi * kTPX + t % kTPX;
+    return j < kGroupsPerWave && p < g.nRy && q < g.nRx;
+  }
+  // rank of slot `lane` of group j (0 where there is none)
+  template <int K>
+  __device__ __forceinline__ int rank(int j) const {
+    int p, q;
+    if (!ref_of(j, p, q) || lane >= K) return 0;
+    return idx[(static_cast<size_t>(p) * g.nRx + q) * K + lane];
+  }
+  // stack rows of group j from its ranks: v[k] = stack[pos_k * 64 + lane]
+  template <int K, int NS>
+  __device__ __forceinline__ bool gather(int j, int r, const float* const (&stacks)[NS], float (&v)[NS][K],
+                                         int& lyx) const {
+    int p, q;
+    if (!ref_of(j, p, q)) return false;
+    int pos_v;
+    slot_pos<K>(g, r, p, q, fy0, fx0, lane, pos_v, lyx);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const size_t o = static_cast<size_t>(__builtin_amdgcn_readlane(pos_v, k)) * 64 + lane;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[s][k] = stacks[s][o];
+    }
+    return true;
+  }
+};
+
 // One work item = one tile of references: stage-1 groups.
 template <int K>
 __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * kBlockFloats], const ImgRec& r, int R,
@@ -173,17 +215,22 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
   const float tau = r.sigma * (hp.ht_a - hp.ht_b * static_cast<float>(bior_level(lane)));
   const bool dc_lane = hp.keep_dc && lane == 0;
 
-  for (int t = wave; t < kTPY * kTPX; t += kWaves) {
-    const int p = tyi * kTPY + t / kTPX, q = txi * kTPX + t % kTPX;
-    if (p >= g.nRy || q >= g.nRx) continue;
-    int pos_v, lyx_v;
-    decode_slots<K>(g, r.idx, p, q, fy0, fx0, lane, pos_v, lyx_v);
+  const GroupWalk walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  const float* const stacks[1] = {stack};
+  int r1 = walk.rank<K>(1);
+  float cur[1][K];
+  int lyx_c = 0;
+  bool ok_c = walk.gather<K, 1>(0, walk.rank<K>(0), stacks, cur, lyx_c);
+  for (int j = 0; j < kGroupsPerWave; ++j) {
+    const int r2 = walk.rank<K>(j + 2);
+    float nxt[1][K];
+    int lyx_n = 0;
+    const bool ok_n = walk.gather<K, 1>(j + 1, r1, stacks, nxt, lyx_n);
+    if (ok_c) {
+    const int lyx_v = lyx_c;
     float v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int pos = __builtin_amdgcn_readlane(pos_v, k);
-      v[k] = stack[static_cast<size_t>(pos) * 64 + lane];
-    }
+    for (int k = 0; k < K; ++k) v[k] = cur[0][k];
     haar_fwd<K>(v);
     int nnz = 0;
 #pragma unroll
@@ -224,6 +271,12 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
       w = 1.0f;
     }
     accumulate<K>(acc, g, lyx_v, u, w, lane);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) cur[0][k] = nxt[0][k];
+    lyx_c = lyx_n;
+    ok_c = ok_n;
+    r1 = r2;
   }
   flush_acc(acc, n_acc, r.partials + static_cast<size_t>(item) * n_acc);
 }
@@ -246,17 +299,24 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K
   const int a = lane >> 3, b = lane & 7;
   const float s2 = r.sigma * r.sigma;
 
-  for (int t = wave; t < kTPY * kTPX; t += kWaves) {
-    const int p = tyi * kTPY + t / kTPX, q = txi * kTPX + t % kTPX;
-    if (p >= g.nRy || q >= g.nRx) continue;
-    int pos_v, lyx_v;
-    decode_slots<K>(g, r.idx, p, q, fy0, fx0, lane, pos_v, lyx_v);
+  const GroupWalk walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  const float* const stacks[2] = {stack_n, stack_p};
+  int r1 = walk.rank<K>(1);
+  float cur[2][K];
+  int lyx_c = 0;
+  bool ok_c = walk.gather<K, 2>(0, walk.rank<K>(0), stacks, cur, lyx_c);
+  for (int j = 0; j < kGroupsPerWave; ++j) {
+    const int r2 = walk.rank<K>(j + 2);
+    float nxt[2][K];
+    int lyx_n = 0;
+    const bool ok_n = walk.gather<K, 2>(j + 1, r1, stacks, nxt, lyx_n);
+    if (ok_c) {
+    const int lyx_v = lyx_c;
     float vn[K], vp[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const size_t o = static_cast<size_t>(__builtin_amdgcn_readlane(pos_v, k)) * 64 + lane;
-      vn[k] = stack_n[o];
-      vp[k] = stack_p[o];
+      vn[k] = cur[0][k];
+      vp[k] = cur[1][k];
     }
     haar_fwd<K>(vp);
     haar_fwd<K>(vn);
@@ -280,6 +340,15 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = xw[k * kBlockFloats + a * kScratchPitch + b];
     accumulate<K>(acc, g, lyx_v, u, w, lane);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      cur[0][k] = nxt[0][k];
+      cur[1][k] = nxt[1][k];
+    }
+    lyx_c = lyx_n;
+    ok_c = ok_n;
+    r1 = r2;
   }
   flush_acc(acc, n_acc, r.partials + static_cast<size_t>(item) * n_acc);
 }
