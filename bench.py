@@ -100,7 +100,7 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes": n, "ok": bool(y[-1].item() == 1)}), flush=True)
 
 
-def cpu_baseline(Z, sigma, size=192):
+def cpu_baseline(Z, sigma, size=320):
     """The CPU oracle (one thread) on a size x size crop of the same image."""
     import numpy as np
     from threadpoolctl import threadpool_limits

@@ -254,16 +254,27 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 
   if (qt < nRx) {
     const int nblk = nb * nb;
+    // norms of this lane's four candidates of block number j (global loads,
+    // issued one block ahead of their use)
+    auto norms = [&](int j, double (&nv)[4]) {
+      if (j < nblk) {
+        const int b = kOrder.b[nb][j];
+        const int br = b / nb, bc = b - br * nb;
+        const double* nc = ncand + static_cast<size_t>(4 * br) * We + 4 * bc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) nv[i] = nc[i];
+      }
+    };
+    double nv[4] = {0.0, 0.0, 0.0, 0.0};
+    norms(part, nv);
     for (int j = part; j < nblk; j += SPLIT) {
+      double nvn[4] = {0.0, 0.0, 0.0, 0.0};
+      norms(j + SPLIT, nvn);
       const int b = kOrder.b[nb][j];
       const int br = b / nb, bc = b - br * nb;
       // operand: candidate m = n -> block row n / 4, column n % 4
       i32x4 ch, cl;
       load_operand(hp, lp, 4 * br + (n >> 2), 12 * t + 4 * bc + (n & 3), g, ch, cl);
-      const double* nc = ncand + static_cast<size_t>(4 * br) * We + 4 * bc;
-      double nv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) nv[i] = nc[i];
       const i32x4 zero = {0, 0, 0, 0};
       const i32x4 hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ch, rh, zero, 0, 0, 0);
       i32x4 cc = __builtin_amdgcn_mfma_i32_16x16x64_i8(ch, rl, zero, 0, 0, 0);
@@ -290,6 +301,8 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
         }
       }
       if (__any(cnt > kFlushAt)) flush();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nv[i] = nvn[i];
     }
   }
   if (__any(cnt > 0)) flush();
