@@ -58,7 +58,7 @@ extern "C" {
 
 /* block-matching kernels; both give the same indices (Sec. 2: eq. dfg
  * summed shift by shift, or the norm/cross-correlation split of Theorem 1) */
-#define GBM3D_BM_AUTO  0  /* the autotuned choice for the shape, else SHIFT */
+#define GBM3D_BM_AUTO  0  /* the autotuned choice for the shape, else CORR  */
 #define GBM3D_BM_SHIFT 1  /* per displacement: squared differences, box sums
                              at the reference positions (float64 vector ALU) */
 #define GBM3D_BM_CORR  2  /* per 4x4 reference tile: block norms plus int8
@@ -237,7 +237,7 @@ int gbm3d_timing_reset(gbm3d_ctx* ctx);
  * to a power of two.  Later calls whose params leave bm_method or bm_split at
  * 0 use the recorded choice of their class (a batch: the class of all its
  * tiles together); without one, the method recorded for the nearest class of
- * the same K with the split chosen by size; else the built-in default.
+ * the same K with the split chosen by size; else GBM3D_BM_CORR.
  * Indices do not depend on the choice.  best_method, best_split and best_ms (milliseconds per run) may be
  * NULL.  Errors: GBM3D_EINVAL for bad shapes, K or reps < 1. */
 int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, int reps, int* best_method,

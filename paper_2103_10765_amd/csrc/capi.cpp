@@ -271,7 +271,7 @@ BmChoice choose_bm(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles, int 
       }
     }
   }
-  if (c.method == GBM3D_BM_AUTO) c.method = GBM3D_BM_SHIFT;
+  if (c.method == GBM3D_BM_AUTO) c.method = GBM3D_BM_CORR;  // the faster kernel on every measured shape
   return c;
 }
 

@@ -7,7 +7,7 @@ learning-rate schedule through the library's gradient and update kernels,
 writes and resumes checkpoints (NumPy .npz, no pickled objects), and compares
 learned-pilot two-stage denoising with the plain two-stage path.
 
-    python -m paper_2103_10765_amd.pilot train --crops 20000 --steps 3000 --out w.npz
+    python -m paper_2103_10765_amd.pilot train --crops 20000 --steps 60000 --weighting sigma --out w.npz
     python -m paper_2103_10765_amd.pilot eval --weights w.npz
 """
 from __future__ import annotations
@@ -202,14 +202,14 @@ def main(argv=None):
     t = sub.add_parser("train")
     t.add_argument("--crops", type=int, default=20000)
     t.add_argument("--size", type=int, default=128)
-    t.add_argument("--steps", type=int, default=3000)
+    t.add_argument("--steps", type=int, default=60000)
     t.add_argument("--batch", type=int, default=64)
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
     t.add_argument("--ckpt", default=None)
     t.add_argument("--workers", type=int, default=8)
     t.add_argument("--eval", action="store_true")
-    t.add_argument("--weighting", choices=["none", "sigma"], default="none")
+    t.add_argument("--weighting", choices=["none", "sigma"], default="sigma")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
     e.add_argument("--n", type=int, default=32)
