@@ -27,9 +27,15 @@ FLAGS = [
 ]
 
 
+# The matching kernels hold only finite keys or +inf in their min/max
+# networks: with NaNs ruled out, v_min_f64 / v_max_f64 need no NaN-quieting
+# operand canonicalisation.
+EXTRA = {"bm.hip": ["-fno-honor-nans"], "bm_corr.hip": ["-fno-honor-nans"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -97,7 +97,7 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
   const int segs = bm_segments(W);
   const int S = 2 * R + 1;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int row_in_wg = wave / SPLIT, part = wave % SPLIT;
   const int p0 = (item / segs) * RPW;
   const int p = p0 + row_in_wg;
@@ -206,7 +206,7 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
       finish(a2a, a1a, dxi);
       finish(a2b, a1b, dxi + 1);
       finish(a2c, a1c, dxi + 2);
-      if (__any(cnt > Smem::kFlushAt)) flush();
+      if (wave_any(cnt > Smem::kFlushAt)) flush();
     };
 
     double A0[kPatch], A1[kPatch], A2[kPatch], B0[kPatch], B1[kPatch], B2[kPatch];
@@ -219,7 +219,7 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
       iter3(B0, B1, B2, A0, A1, A2, dxi + 3, 2 * it + 2);
     }
   }
-  if (__any(cnt > 0)) flush();
+  if (wave_any(cnt > 0)) flush();
 
   if constexpr (SPLIT > 1) {
     // merge the SPLIT partial lists of each row into its part-0 wave

@@ -13,15 +13,18 @@
 // A wave owns a 4 x 4 tile of references (step 3); the union of their search
 // windows is a (2R + 10)^2 square of candidate positions, walked in 4 x 4
 // candidate blocks from the centre outwards.  Result lane (g, n) holds
-// reference n and candidates (row g, columns 0..3) of the block.  Each pair is
-// first tested with a conservative bound that drops the Pll term
-// (|2 Pll| <= 2^21); survivors get the exact key in float64.  Norms come from
-// a table written beforehand by bm_norm_kernel (float64, exact).
+// reference n and candidates (row g, columns 0..3) of the block.  Every pair
+// gets its exact key 2048 (N(a) + N(b) - 512 (256 Phh + Phl + Plh) - 2 Pll) +
+// rank in float64 (all terms integers below 2^50) with no data-dependent
+// branch; keys below the lane's bound go to its candidate buffer.  Norms come
+// from a table written beforehand by bm_norm_kernel (float64, exact).
 //
 // Every lane keeps the K-1 best keys of its reference among its quarter of
 // the candidates; the four quarters, and the SPLIT waves that share a tile,
 // publish their worst kept key so every lane prunes with the best bound of
 // its reference, and merge with bitonic networks at the end.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 #include "topk.h"
@@ -46,7 +49,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 // Candidate blocks of an nb x nb grid in rings of growing Chebyshev distance
 // from its centre (near displacements first tighten the bounds early).
 struct BlockOrder {
-  unsigned char b[kMaxNb + 1][kMaxNb * kMaxNb];
+  int b[kMaxNb + 1][kMaxNb * kMaxNb];  // 32-bit entries: read with scalar loads
 };
 
 constexpr BlockOrder make_block_order() {
@@ -58,7 +61,7 @@ constexpr BlockOrder make_block_order() {
         int dr = 2 * (b / nb) - (nb - 1), dc = 2 * (b % nb) - (nb - 1);
         dr = dr < 0 ? -dr : dr;
         dc = dc < 0 ? -dc : dc;
-        if ((dr > dc ? dr : dc) == ring) o.b[nb][n++] = static_cast<unsigned char>(b);
+        if ((dr > dc ? dr : dc) == ring) o.b[nb][n++] = b;
       }
   }
   return o;
@@ -185,7 +188,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   const int S = 2 * R + 1;
   const int nb = (2 * R + 10 + 3) / 4;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int t = wave / SPLIT, part = wave % SPLIT;
   const int g = lane >> 4, n = lane & 15;
   const int u = n >> 2, v = n & 3;
@@ -227,7 +230,8 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   double list[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) list[i] = kInf;
-  double thr = kInf, bnd = kInf;  // key bound, and the matching bound on N(b) - 512 S
+  double thr = kInf;  // no key at or above it can enter the list
+  const double key_base = 2048.0 * nr;
   int cnt = 0;
   double* mybuf = buf + wave * kBuf * kWave + lane;
   const int r_center = R * S + R;
@@ -248,8 +252,6 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
                           bound + (t * SPLIT + s2) * kWave + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))));
     }
     thr = tb;
-    // key < thr needs dist < thr / 2048; dist >= nr + (N(b) - 512 S) - 2^21
-    bnd = thr * (1.0 / 2048.0) - nr + 2097152.0;
   };
 
   if (qt < nRx) {
@@ -265,11 +267,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
         for (int i = 0; i < 4; ++i) nv[i] = nc[i];
       }
     };
-    double nv[4] = {0.0, 0.0, 0.0, 0.0};
-    norms(part, nv);
-    for (int j = part; j < nblk; j += SPLIT) {
-      double nvn[4] = {0.0, 0.0, 0.0, 0.0};
-      norms(j + SPLIT, nvn);
+    auto block = [&](int j, const double (&nv)[4]) {
       const int b = kOrder.b[nb][j];
       const int br = b / nb, bc = b - br * nb;
       // operand: candidate m = n -> block row n / 4, column n % 4
@@ -284,28 +282,48 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       const int ey = 4 * br + g - 3 * u;     // dy + R
       const int ex0 = 4 * bc - 3 * v;        // dx + R for i = 0
       const bool row_ok = static_cast<unsigned>(ey) <= static_cast<unsigned>(2 * R);
-      const int rank0 = ey * S + ex0;
+      // key = 2048 (N(a) + N(b) - 512 s - 2 Pll) + rank, every term an integer below 2^50
+      const double kb = key_base + static_cast<double>(ey * S + ex0);
+      // the reference itself (dy = dx = 0) is candidate ic of this block in at most a few lanes
+      const int ic = R - ex0;
+      const bool center_here = ey == R && static_cast<unsigned>(ic) < 4u;
+      auto pairs = [&](auto check_center) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int s = hh[i] * 256 + cc[i];  // 256 Phh + Phl + Plh, |s| < 2^29
-        const double f = fma(-512.0, static_cast<double>(s), nv[i]);
-        const bool ok = row_ok && static_cast<unsigned>(ex0 + i) <= static_cast<unsigned>(2 * R) && f < bnd;
-        if (__any(ok)) {
-          const double dist = fma(-2.0, static_cast<double>(ll[i]), f) + nr;
-          const int rank = rank0 + i;
-          const double key = fma(dist, 2048.0, static_cast<double>(rank));
-          if (ok && rank != r_center && key < thr) {
+        for (int i = 0; i < 4; ++i) {
+          const int s = hh[i] * 256 + cc[i];  // 256 Phh + Phl + Plh, |s| < 2^29
+          const double c = fma(nv[i], 2048.0, kb + static_cast<double>(i));
+          const double key =
+              fma(-1048576.0, static_cast<double>(s), fma(-4096.0, static_cast<double>(ll[i]), c));
+          // (bitwise: no short-circuit branches)
+          bool ok = row_ok & (static_cast<unsigned>(ex0 + i) <= static_cast<unsigned>(2 * R)) & (key < thr);
+          if constexpr (decltype(check_center)::value) ok = ok & !(center_here & (i == ic));
+          if (ok) {
             mybuf[cnt * kWave] = key;
             ++cnt;
           }
         }
-      }
-      if (__any(cnt > kFlushAt)) flush();
-#pragma unroll
-      for (int i = 0; i < 4; ++i) nv[i] = nvn[i];
+      };
+      if (wave_any(center_here))
+        pairs(std::true_type{});
+      else
+        pairs(std::false_type{});
+      if (wave_any(cnt > kFlushAt)) flush();
+    };
+    // two norm buffers in turn: the loads for the next block are in flight
+    // while this one is processed
+    double na[4], nb4[4];
+    norms(part, na);
+    norms(part + SPLIT, nb4);
+#pragma unroll 1
+    for (int j = part; j < nblk; j += 2 * SPLIT) {
+      block(j, na);
+      norms(j + 2 * SPLIT, na);
+      if (j + SPLIT >= nblk) break;
+      block(j + SPLIT, nb4);
+      norms(j + 3 * SPLIT, nb4);
     }
   }
-  if (__any(cnt > 0)) flush();
+  if (wave_any(cnt > 0)) flush();
 
   // the four quarters of each reference, then the SPLIT waves of the tile
   merge_sorted<L>(list, [&](int j) { return shfl_xor_double(list[j], 16); });

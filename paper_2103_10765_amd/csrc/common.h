@@ -259,6 +259,13 @@ __device__ __forceinline__ void for_each_item(const ImgRec& one, const WorkList&
 // Wavefront helpers (wave64)
 // ---------------------------------------------------------------------------
 
+// True if the predicate holds in any active lane (a scalar-mask test).
+__device__ __forceinline__ bool wave_any(bool pred) { return __builtin_amdgcn_ballot_w64(pred) != 0; }
+
+// This thread's wave index in the workgroup, as a wave-uniform (scalar) value,
+// so that control flow and table lookups keyed on it stay scalar.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave); }
+
 // Orders this wave's LDS accesses: every lane's earlier LDS writes are visible
 // to every lane's later LDS reads.
 __device__ __forceinline__ void wave_lds_sync() {

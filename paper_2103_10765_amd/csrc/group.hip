@@ -205,7 +205,7 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
   const float* __restrict__ stack = r.stack_a;
   const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int n_acc = 2 * g.FY * g.FXP;
   zero_acc(acc, n_acc);
   const int fy0 = kStep * tyi * kTPY - g.R;
@@ -290,7 +290,7 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K
   const float* __restrict__ stack_p = r.stack_b;
   const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int n_acc = 2 * g.FY * g.FXP;
   zero_acc(acc, n_acc);
   const int fy0 = kStep * tyi * kTPY - g.R;
