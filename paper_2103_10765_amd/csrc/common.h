@@ -157,6 +157,7 @@ __device__ __forceinline__ void dct8_inv(const float* X, float* x) {
 
 // round(x * 2^40) as a 64-bit integer, exact for |x| < 2^11: the fixed-point
 // format of the aggregation sums (integer addition is order-independent).
+// Weights can be small (1/TV), so the format keeps 40 fractional bits.
 constexpr double kFixScale = 1099511627776.0;  // 2^40
 __device__ __forceinline__ long long to_fixed(float x) {
   const double magic = 6755399441055744.0;  // 1.5 * 2^52
@@ -165,21 +166,40 @@ __device__ __forceinline__ long long to_fixed(float x) {
 }
 
 // ---------------------------------------------------------------------------
-// Orthonormal full-depth Haar along a group of K registers (K power of two).
-// Forward: at each level, pairs (2j, 2j+1) of the current sums become the
-// sum (x0+x1)/sqrt2 at j and the difference (x0-x1)/sqrt2 at half+j; the
-// group DC ends at index 0.  Inverse undoes the levels in reverse.
+// Full-depth Haar along a group of K registers (K power of two).  The
+// orthonormal forward step turns pairs (2j, 2j+1) of the current sums into the
+// sum (x0+x1)/sqrt2 at j and the difference (x0-x1)/sqrt2 at half+j, the
+// group DC ending at index 0.  The kernels run it unnormalised:
 // ---------------------------------------------------------------------------
+// the same butterflies without the 1/sqrt2.  Orthonormal
+// coefficient k equals haar_gain<K>(k) times unnormalised coefficient k, with
+// haar_gain^2 = h/K for the detail band [h, 2h) that holds k (1/K for the
+// DC); the orthonormal inverse of c is haar_inv_raw of haar_gain^2 * c', since
+// the unnormalised inverse is the transpose of the unnormalised forward.
 template <int K>
-__device__ __forceinline__ void haar_fwd(float* v) {
-  const float s = static_cast<float>(kInvSqrt2);
+__host__ __device__ constexpr float haar_gain2(int k) {
+  int h = 1;
+  while (2 * h <= k) h *= 2;
+  return static_cast<float>(k == 0 ? 1.0 / K : static_cast<double>(h) / K);
+}
+
+template <int K>
+__host__ __device__ constexpr float haar_gain(int k) {
+  // the square root of haar_gain2: one factor 1/sqrt2 per butterfly stage on k's path
+  double g = 1.0;
+  for (int m = K; m > 1; m /= 2) g *= (k < m) ? kInvSqrt2 : 1.0;
+  return static_cast<float>(g);
+}
+
+template <int K>
+__device__ __forceinline__ void haar_fwd_raw(float* v) {
 #pragma unroll
   for (int half = K / 2; half >= 1; half /= 2) {
     float t[K];
 #pragma unroll
     for (int j = 0; j < half; ++j) {
-      t[j] = (v[2 * j] + v[2 * j + 1]) * s;
-      t[half + j] = (v[2 * j] - v[2 * j + 1]) * s;
+      t[j] = v[2 * j] + v[2 * j + 1];
+      t[half + j] = v[2 * j] - v[2 * j + 1];
     }
 #pragma unroll
     for (int j = 0; j < 2 * half; ++j) v[j] = t[j];
@@ -187,15 +207,14 @@ __device__ __forceinline__ void haar_fwd(float* v) {
 }
 
 template <int K>
-__device__ __forceinline__ void haar_inv(float* v) {
-  const float s = static_cast<float>(kInvSqrt2);
+__device__ __forceinline__ void haar_inv_raw(float* v) {
 #pragma unroll
   for (int half = 1; half <= K / 2; half *= 2) {
     float t[K];
 #pragma unroll
     for (int j = 0; j < half; ++j) {
-      t[2 * j] = (v[j] + v[half + j]) * s;
-      t[2 * j + 1] = (v[j] - v[half + j]) * s;
+      t[2 * j] = v[j] + v[half + j];
+      t[2 * j + 1] = v[j] - v[half + j];
     }
 #pragma unroll
     for (int j = 0; j < 2 * half; ++j) v[j] = t[j];

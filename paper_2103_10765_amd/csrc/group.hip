@@ -231,15 +231,18 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = cur[0][k];
-    haar_fwd<K>(v);
+    // unnormalised Haar: coefficient k of the orthonormal transform is
+    // haar_gain(k) * v[k]; the kept ones are scaled by haar_gain^2 (a power of
+    // two) for the unnormalised inverse
+    haar_fwd_raw<K>(v);
     int nnz = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const bool keep = fabsf(v[k]) >= tau || (k == 0 && dc_lane);
-      v[k] = keep ? v[k] : 0.0f;
+      const bool keep = fabsf(v[k]) * haar_gain<K>(k) >= tau || (k == 0 && dc_lane);
+      v[k] = keep ? v[k] * haar_gain2<K>(k) : 0.0f;
       nnz += keep ? 1 : 0;
     }
-    haar_inv<K>(v);
+    haar_inv_raw<K>(v);
     wave_lds_sync();  // the previous group's reads of the scratch are done
 #pragma unroll
     for (int k = 0; k < K; ++k) xw[k * kBlockFloats + a * kScratchPitch + b] = v[k];
@@ -318,19 +321,21 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K
       vn[k] = cur[0][k];
       vp[k] = cur[1][k];
     }
-    haar_fwd<K>(vp);
-    haar_fwd<K>(vn);
+    // unnormalised Haar (orthonormal coefficient k = haar_gain(k) * raw);
+    // haar_gain^2 is a power of two, so b^2 and the rescaling are exact
+    haar_fwd_raw<K>(vp);
+    haar_fwd_raw<K>(vn);
     float sw2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float b2 = vp[k] * vp[k];
+      const float b2 = vp[k] * vp[k] * haar_gain2<K>(k);
       float wt = b2 * __builtin_amdgcn_rcpf(b2 + s2);
       if (k == 0 && lane == 0) wt = 1.0f;
-      vn[k] *= wt;
+      vn[k] *= wt * haar_gain2<K>(k);
       sw2 = fmaf(wt, wt, sw2);
     }
     const float w = 1.0f / wave_sum(sw2);
-    haar_inv<K>(vn);
+    haar_inv_raw<K>(vn);
     wave_lds_sync();
 #pragma unroll
     for (int k = 0; k < K; ++k) xw[k * kBlockFloats + a * kScratchPitch + b] = vn[k];

@@ -7,7 +7,7 @@ learning-rate schedule through the library's gradient and update kernels,
 writes and resumes checkpoints (NumPy .npz, no pickled objects), and compares
 learned-pilot two-stage denoising with the plain two-stage path.
 
-    python -m paper_2103_10765_amd.pilot train --crops 20000 --steps 60000 --weighting sigma --out w.npz
+    python -m paper_2103_10765_amd.pilot train --crops 20000 --steps 200000 --weighting sigma --out w.npz
     python -m paper_2103_10765_amd.pilot eval --weights w.npz
 """
 from __future__ import annotations
@@ -202,7 +202,7 @@ def main(argv=None):
     t = sub.add_parser("train")
     t.add_argument("--crops", type=int, default=20000)
     t.add_argument("--size", type=int, default=128)
-    t.add_argument("--steps", type=int, default=60000)
+    t.add_argument("--steps", type=int, default=200000)
     t.add_argument("--batch", type=int, default=64)
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
