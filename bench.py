@@ -204,9 +204,17 @@ def main():
                     help="block-matching kernel: autotuned on the benchmark image (default) or fixed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only time the 64-image batch under graph replay (for profiling the batch path)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.batch_only:
+        from paper_2103_10765_amd import gbm3d
+        ctx = gbm3d.Context(0)
+        print(json.dumps(batch_bench(ctx, reps=args.steps)), flush=True)
+        ctx.close()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "

@@ -236,11 +236,9 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   double* mybuf = buf + wave * kBuf * kWave + lane;
   const int r_center = R * S + R;
 
-  auto flush = [&]() {
-    merge_buffer<L, kBuf>(list, mybuf, kWave, cnt);
-    cnt = 0;
-    // keys are unique: a key above any list's worst kept key for the same
-    // reference cannot be among its K-1 best
+  // keys are unique: a key above any list's worst kept key for the same
+  // reference cannot be among its K-1 best
+  auto publish = [&]() {
     double tb = fmin(list[L - 1], shfl_xor_double(list[L - 1], 16));
     tb = fmin(tb, shfl_xor_double(tb, 32));
     if constexpr (SPLIT > 1) {
@@ -252,6 +250,11 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
                           bound + (t * SPLIT + s2) * kWave + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))));
     }
     thr = tb;
+  };
+  auto flush = [&]() {
+    merge_buffer<L, kBuf>(list, mybuf, kWave, cnt);
+    cnt = 0;
+    publish();
   };
 
   if (qt < nRx) {
@@ -267,7 +270,9 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
         for (int i = 0; i < 4; ++i) nv[i] = nc[i];
       }
     };
-    auto block = [&](int j, const double (&nv)[4]) {
+    // WARM: return the four keys (+inf for a position outside the window or
+    // the reference itself) instead of buffering those below the bound
+    auto block = [&](int j, const double (&nv)[4], auto warm, double (&keys)[4]) {
       const int b = kOrder.b[nb][j];
       const int br = b / nb, bc = b - br * nb;
       // operand: candidate m = n -> block row n / 4, column n % 4
@@ -295,9 +300,11 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
           const double key =
               fma(-1048576.0, static_cast<double>(s), fma(-4096.0, static_cast<double>(ll[i]), c));
           // (bitwise: no short-circuit branches)
-          bool ok = row_ok & (static_cast<unsigned>(ex0 + i) <= static_cast<unsigned>(2 * R)) & (key < thr);
+          bool ok = row_ok & (static_cast<unsigned>(ex0 + i) <= static_cast<unsigned>(2 * R));
           if constexpr (decltype(check_center)::value) ok = ok & !(center_here & (i == ic));
-          if (ok) {
+          if constexpr (decltype(warm)::value) {
+            keys[i] = ok ? key : kInf;
+          } else if (ok & (key < thr)) {
             mybuf[cnt * kWave] = key;
             ++cnt;
           }
@@ -307,19 +314,52 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
         pairs(std::true_type{});
       else
         pairs(std::false_type{});
-      if (wave_any(cnt > kFlushAt)) flush();
+      if constexpr (!decltype(warm)::value) {
+        if (wave_any(cnt > kFlushAt)) flush();
+      }
     };
+    // Warm start: the first kWarm blocks of this part give 16 candidates per
+    // block and reference (four per lane group); their L best form the first
+    // list (held by lane group 0, so the four quarters stay disjoint) and
+    // its worst key the first bound.
+    constexpr int kWarm = L < 16 ? 1 : 2;
+    {
+      double seed[16 * kWarm];
+#pragma unroll
+      for (int w = 0; w < kWarm; ++w) {
+        double k4[4] = {kInf, kInf, kInf, kInf};
+        const int jw = part + w * SPLIT;
+        if (jw < nblk) {
+          double nvw[4];
+          norms(jw, nvw);
+          block(jw, nvw, std::true_type{}, k4);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          seed[4 * w + i] = k4[i];
+          seed[4 * kWarm + 4 * w + i] = shfl_xor_double(k4[i], 16);
+          seed[8 * kWarm + 4 * w + i] = shfl_xor_double(k4[i], 32);
+          seed[12 * kWarm + 4 * w + i] = shfl_xor_double(k4[i], 48);
+        }
+      }
+      bitonic_sort<16 * kWarm>(seed);
+#pragma unroll
+      for (int i = 0; i < L && i < 16 * kWarm; ++i) list[i] = g == 0 ? seed[i] : kInf;
+      publish();
+    }
+    double unused[4];
     // two norm buffers in turn: the loads for the next block are in flight
     // while this one is processed
+    const int jb = part + kWarm * SPLIT;
     double na[4], nb4[4];
-    norms(part, na);
-    norms(part + SPLIT, nb4);
+    norms(jb, na);
+    norms(jb + SPLIT, nb4);
 #pragma unroll 1
-    for (int j = part; j < nblk; j += 2 * SPLIT) {
-      block(j, na);
+    for (int j = jb; j < nblk; j += 2 * SPLIT) {
+      block(j, na, std::false_type{}, unused);
       norms(j + 2 * SPLIT, na);
       if (j + SPLIT >= nblk) break;
-      block(j + SPLIT, nb4);
+      block(j + SPLIT, nb4, std::false_type{}, unused);
       norms(j + 3 * SPLIT, nb4);
     }
   }
