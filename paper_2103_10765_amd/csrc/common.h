@@ -159,6 +159,17 @@ __device__ __forceinline__ void dct8_inv(const float* X, float* x) {
 // format of the aggregation sums (integer addition is order-independent).
 // Weights can be small (1/TV), so the format keeps 40 fractional bits.
 constexpr double kFixScale = 1099511627776.0;  // 2^40
+// Element `lane` of the 64 floats at `blk` (a wave-uniform address) by a raw
+// buffer load: the base lives in scalar registers, the offset lane * 4 in
+// the instruction, so a gather of whole blocks costs no vector address
+// arithmetic.  The resource spans exactly the 256 bytes of the block.
+__device__ __forceinline__ float load_block_lane(const float* blk, int lane) {
+  constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dwords on gfx9
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(blk), 0, 64 * sizeof(float), kRsrcWord3);
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, 0, 0));
+}
+
 __device__ __forceinline__ long long to_fixed(float x) {
   const double magic = 6755399441055744.0;  // 1.5 * 2^52
   const double y = fma(static_cast<double>(x), kFixScale, magic);

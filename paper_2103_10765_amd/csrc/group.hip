@@ -1,6 +1,6 @@
 // Collaborative filtering of matched groups and their aggregation.
 //
-// A workgroup of eight waves owns a tile of 8 x 8 references; each wave
+// A workgroup of sixteen (eight for K = 32) waves owns a tile of 8 x 8 references; each wave
 // filters one group at a time with lane = 2-D coefficient index (64 lanes =
 // 8x8 coefficients) and the group axis in registers:
 //   decode the K block positions (lane k decodes slot k, the values are
@@ -31,12 +31,11 @@ namespace gbm3d {
 
 namespace {
 
-constexpr int kWaves = 8;
-constexpr int kThreads = kWaves * kWave;
 constexpr int kScratchPitch = 9;                  // LDS row pitch of a parked 8x8 block
 constexpr int kBlockFloats = 8 * kScratchPitch;   // 72
 constexpr int kTPY = 8, kTPX = 8;                 // references per tile
 constexpr int kReduceThreads = 256;
+constexpr int kLdsBytes = 160 * 1024;             // LDS of one workgroup
 
 using acc_t = unsigned long long;
 
@@ -46,6 +45,17 @@ struct Foot {
   static constexpr int FXPmax = FXmax + ((8 - FXmax) % 32 + 32) % 32;
   static constexpr int entries = 2 * FYmax * FXPmax;
 };
+
+// Waves per tile: sixteen (four per SIMD, the groups' LDS round trips hide
+// each other) where the per-wave transform scratch of K blocks still fits
+// beside the footprint accumulator, else eight.
+template <int K>
+constexpr int group_waves() {
+  return Foot::entries * static_cast<int>(sizeof(acc_t)) + 16 * K * kBlockFloats * static_cast<int>(sizeof(float)) <=
+                 kLdsBytes
+             ? 16
+             : 8;
+}
 
 struct GroupArgs {
   int H, W, R, S, nRy, nRx, nTx, nTy;
@@ -113,32 +123,31 @@ __device__ __forceinline__ void inverse_level(float* xw, int lane, F&& line) {
 }
 
 // Block positions of the group of reference (p, q): lane k < K decodes the
-// rank r of slot k into a stack position (pixel index) and a packed
-// tile-local top-left.
+// rank r of slot k into a stack position (pixel index) and the offset of the
+// block's top-left in the tile's footprint.
 template <int K>
 __device__ __forceinline__ void slot_pos(const GroupArgs& g, int r, int p, int q, int fy0, int fx0, int lane, int& pos,
-                                         int& lyx) {
+                                         int& fo) {
   pos = 0;
-  lyx = 0;
+  fo = 0;
   if (lane < K) {
     const int dyi = r / g.S, dxi = r - dyi * g.S;
     const int y = kStep * p + dyi - g.R, x = kStep * q + dxi - g.R;
     pos = pmod(y, g.H) * g.W + pmod(x, g.W);
-    lyx = ((y - fy0) << 16) | (x - fx0);
+    fo = (y - fy0) * g.FXP + (x - fx0);
   }
 }
 
 template <int K>
-__device__ __forceinline__ void accumulate(acc_t* acc, const GroupArgs& g, int lyx_v, const float (&u)[K], float w,
+__device__ __forceinline__ void accumulate(acc_t* acc, const GroupArgs& g, int fo_v, const float (&u)[K], float w,
                                            int lane) {
-  const int a = lane >> 3, b = lane & 7;
+  const int ab = (lane >> 3) * g.FXP + (lane & 7);
   acc_t* num = acc;
   acc_t* den = acc + g.FY * g.FXP;
   const acc_t wf = static_cast<acc_t>(to_fixed(w));
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int lyx = __builtin_amdgcn_readlane(lyx_v, k);
-    const int o = ((lyx >> 16) + a) * g.FXP + (lyx & 0xffff) + b;
+    const int o = __builtin_amdgcn_readlane(fo_v, k) + ab;
     atomicAdd(num + o, static_cast<acc_t>(to_fixed(w * u[k])));
     atomicAdd(den + o, wf);
   }
@@ -155,22 +164,22 @@ __device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __rest
   __syncthreads();  // the accumulator is reused by the next item
 }
 
-// The groups a wave filters in a tile: reference t = wave + j * kWaves,
-// j < kGroupsPerWave.  Loads run ahead of the filtering: the ranks of group
+// The groups a wave filters in a tile: reference t = wave + j * WAVES,
+// j < kGroups.  Loads run ahead of the filtering: the ranks of group
 // j + 2 and the spectra of group j + 1 are in flight while group j is
 // filtered.
-constexpr int kGroupsPerWave = kTPY * kTPX / kWaves;
-
+template <int WAVES>
 struct GroupWalk {
+  static constexpr int kGroups = kTPY * kTPX / WAVES;
   const GroupArgs& g;
   const int16_t* __restrict__ idx;
   int tyi, txi, wave, lane, fy0, fx0;
 
   __device__ __forceinline__ bool ref_of(int j, int& p, int& q) const {
-    const int t = wave + j * kWaves;
+    const int t = wave + j * WAVES;
     p = tyi * kTPY + t / kTPX;
     q = txi * kTPX + t % kTPX;
-    return j < kGroupsPerWave && p < g.nRy && q < g.nRx;
+    return j < kGroups && p < g.nRy && q < g.nRx;
   }
   // rank of slot `lane` of group j (0 where there is none)
   template <int K>
@@ -182,16 +191,18 @@ struct GroupWalk {
   // stack rows of group j from its ranks: v[k] = stack[pos_k * 64 + lane]
   template <int K, int NS>
   __device__ __forceinline__ bool gather(int j, int r, const float* const (&stacks)[NS], float (&v)[NS][K],
-                                         int& lyx) const {
+                                         int& fo) const {
     int p, q;
     if (!ref_of(j, p, q)) return false;
     int pos_v;
-    slot_pos<K>(g, r, p, q, fy0, fx0, lane, pos_v, lyx);
+    slot_pos<K>(g, r, p, q, fy0, fx0, lane, pos_v, fo);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const size_t o = static_cast<size_t>(__builtin_amdgcn_readlane(pos_v, k)) * 64 + lane;
+      // the block's base address is uniform: it goes into a buffer resource
+      // (scalar arithmetic only), the lane offset into the load itself
+      const size_t blk = static_cast<size_t>(__builtin_amdgcn_readlane(pos_v, k)) * 64;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) v[s][k] = stacks[s][o];
+      for (int s = 0; s < NS; ++s) v[s][k] = load_block_lane(stacks[s] + blk, lane);
     }
     return true;
   }
@@ -215,19 +226,19 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
   const float tau = r.sigma * (hp.ht_a - hp.ht_b * static_cast<float>(bior_level(lane)));
   const bool dc_lane = hp.keep_dc && lane == 0;
 
-  const GroupWalk walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  const GroupWalk<group_waves<K>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
   const float* const stacks[1] = {stack};
-  int r1 = walk.rank<K>(1);
+  int r1 = walk.template rank<K>(1);
   float cur[1][K];
-  int lyx_c = 0;
-  bool ok_c = walk.gather<K, 1>(0, walk.rank<K>(0), stacks, cur, lyx_c);
-  for (int j = 0; j < kGroupsPerWave; ++j) {
-    const int r2 = walk.rank<K>(j + 2);
+  int fo_c = 0;
+  bool ok_c = walk.template gather<K, 1>(0, walk.template rank<K>(0), stacks, cur, fo_c);
+  for (int j = 0; j < walk.kGroups; ++j) {
+    const int r2 = walk.template rank<K>(j + 2);
     float nxt[1][K];
-    int lyx_n = 0;
-    const bool ok_n = walk.gather<K, 1>(j + 1, r1, stacks, nxt, lyx_n);
+    int fo_n = 0;
+    const bool ok_n = walk.template gather<K, 1>(j + 1, r1, stacks, nxt, fo_n);
     if (ok_c) {
-    const int lyx_v = lyx_c;
+    const int fo_v = fo_c;
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = cur[0][k];
@@ -273,11 +284,11 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
     } else {
       w = 1.0f;
     }
-    accumulate<K>(acc, g, lyx_v, u, w, lane);
+    accumulate<K>(acc, g, fo_v, u, w, lane);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) cur[0][k] = nxt[0][k];
-    lyx_c = lyx_n;
+    fo_c = fo_n;
     ok_c = ok_n;
     r1 = r2;
   }
@@ -302,19 +313,19 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K
   const int a = lane >> 3, b = lane & 7;
   const float s2 = r.sigma * r.sigma;
 
-  const GroupWalk walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  const GroupWalk<group_waves<K>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
   const float* const stacks[2] = {stack_n, stack_p};
-  int r1 = walk.rank<K>(1);
+  int r1 = walk.template rank<K>(1);
   float cur[2][K];
-  int lyx_c = 0;
-  bool ok_c = walk.gather<K, 2>(0, walk.rank<K>(0), stacks, cur, lyx_c);
-  for (int j = 0; j < kGroupsPerWave; ++j) {
-    const int r2 = walk.rank<K>(j + 2);
+  int fo_c = 0;
+  bool ok_c = walk.template gather<K, 2>(0, walk.template rank<K>(0), stacks, cur, fo_c);
+  for (int j = 0; j < walk.kGroups; ++j) {
+    const int r2 = walk.template rank<K>(j + 2);
     float nxt[2][K];
-    int lyx_n = 0;
-    const bool ok_n = walk.gather<K, 2>(j + 1, r1, stacks, nxt, lyx_n);
+    int fo_n = 0;
+    const bool ok_n = walk.template gather<K, 2>(j + 1, r1, stacks, nxt, fo_n);
     if (ok_c) {
-    const int lyx_v = lyx_c;
+    const int fo_v = fo_c;
     float vn[K], vp[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -344,14 +355,14 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K
     float u[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = xw[k * kBlockFloats + a * kScratchPitch + b];
-    accumulate<K>(acc, g, lyx_v, u, w, lane);
+    accumulate<K>(acc, g, fo_v, u, w, lane);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       cur[0][k] = nxt[0][k];
       cur[1][k] = nxt[1][k];
     }
-    lyx_c = lyx_n;
+    fo_c = fo_n;
     ok_c = ok_n;
     r1 = r2;
   }
@@ -359,16 +370,17 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K
 }
 
 template <int K, bool BATCH>
-__global__ __launch_bounds__(kThreads) void group_ht_kernel(ImgRec one, WorkList wl, int R, HtParams hp) {
+__global__ __launch_bounds__(group_waves<K>() * kWave) void group_ht_kernel(ImgRec one, WorkList wl, int R,
+                                                                            HtParams hp) {
   __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[kWaves][K * kBlockFloats];
+  __shared__ float scratch[group_waves<K>()][K * kBlockFloats];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_ht_body<K>(acc, scratch, r, R, hp, item); });
 }
 
 template <int K, bool BATCH>
-__global__ __launch_bounds__(kThreads) void group_wiener_kernel(ImgRec one, WorkList wl, int R) {
+__global__ __launch_bounds__(group_waves<K>() * kWave) void group_wiener_kernel(ImgRec one, WorkList wl, int R) {
   __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[kWaves][K * kBlockFloats];
+  __shared__ float scratch[group_waves<K>()][K * kBlockFloats];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_wiener_body<K>(acc, scratch, r, R, item); });
 }
 
@@ -414,14 +426,43 @@ __device__ __forceinline__ void reduce_body(const ImgRec& r, int R, int final_st
     }
   }
   const size_t plane = static_cast<size_t>(g.FY) * g.FXP;
+  auto at = [&](int i, int j) -> const acc_t* {
+    return partials + (static_cast<size_t>(cty[i]) * g.nTx + ctx[j]) * 2 * plane +
+           static_cast<size_t>(cly[i]) * g.FXP + clx[j];
+  };
   acc_t num = 0, den = 0;
-  for (int i = 0; i < ny; ++i)
-    for (int j = 0; j < nx; ++j) {
-      const acc_t* t = partials + (static_cast<size_t>(cty[i]) * g.nTx + ctx[j]) * 2 * plane;
-      const size_t o = static_cast<size_t>(cly[i]) * g.FXP + clx[j];
-      num += t[o];
-      den += t[plane + o];
-    }
+  if (ny <= 3 && nx <= 3) {
+    // the usual case: at most 3 x 3 footprints; every load is issued before
+    // the sums so their latencies overlap
+    acc_t vn[3][3], vd[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        vn[i][j] = 0;
+        vd[i][j] = 0;
+        if (i < ny && j < nx) {
+          const acc_t* t = at(i, j);
+          vn[i][j] = t[0];
+          vd[i][j] = t[plane];
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        num += vn[i][j];
+        den += vd[i][j];
+      }
+  } else {
+    // small images whose footprints wrap around more than once
+    for (int i = 0; i < ny; ++i)
+      for (int j = 0; j < nx; ++j) {
+        const acc_t* t = at(i, j);
+        num += t[0];
+        den += t[plane];
+      }
+  }
   const float v = static_cast<float>(static_cast<double>(static_cast<long long>(num)) /
                                      static_cast<double>(static_cast<long long>(den)));
   const size_t o = static_cast<size_t>(y) * g.W + x;
@@ -463,11 +504,11 @@ template <int K>
 static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int grid_cap,
                               hipStream_t st) {
   if (!wl) {
-    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(group_waves<K>() * kWave), 0, st,
                        one, WorkList{}, R, hp);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(kThreads), 0, st, one,
+    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(group_waves<K>() * kWave), 0, st, one,
                        *wl, R, hp);
   }
   return hipGetLastError();
@@ -489,11 +530,11 @@ hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, 
 template <int K>
 static hipError_t launch_wiener_k(const ImgRec& one, const WorkList* wl, int R, int grid_cap, hipStream_t st) {
   if (!wl) {
-    hipLaunchKernelGGL((group_wiener_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(kThreads), 0,
+    hipLaunchKernelGGL((group_wiener_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(group_waves<K>() * kWave), 0,
                        st, one, WorkList{}, R);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_wiener_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((group_wiener_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(group_waves<K>() * kWave), 0, st,
                        one, *wl, R);
   }
   return hipGetLastError();
