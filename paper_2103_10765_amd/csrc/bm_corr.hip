@@ -21,8 +21,12 @@
 //
 // Every lane keeps the K-1 best keys of its reference among its quarter of
 // the candidates; the four quarters, and the SPLIT waves that share a tile,
-// publish their worst kept key so every lane prunes with the best bound of
-// its reference, and merge with bitonic networks at the end.
+// share two upper bounds on the (K-1)-th best key seen so far for the
+// reference: the smallest worst kept key of any list, and the largest m-th
+// best of any list, where m lists-worth of keys make K-1 (n lists each with m
+// keys at or below a value hold n m >= K-1 of them).  Keys are unique, so a
+// key at or above either bound cannot be among the K-1 best.  The lists merge
+// with bitonic networks at the end.
 #include <type_traits>
 
 #include "common.h"
@@ -132,7 +136,7 @@ struct CorrSmem {
   static constexpr int L = K - 1;
   static constexpr size_t kPlanes = 2 * kRows * kPitch;
   static constexpr size_t kBufBytes = sizeof(double) * 4 * kBuf * kWave;
-  static constexpr size_t kBound = SPLIT > 1 ? sizeof(double) * 4 * kWave : 0;
+  static constexpr size_t kBound = SPLIT > 1 ? sizeof(double) * 2 * 4 * kWave : 0;
   static constexpr size_t kScan = kPlanes + kBufBytes + kBound;
   static constexpr size_t kMerge = SPLIT > 1 ? sizeof(double) * 2 * L * kWave : 0;
   static constexpr size_t bytes = kScan > kMerge ? kScan : kMerge;
@@ -214,7 +218,10 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
     reinterpret_cast<unsigned*>(hp + r * kPitch)[c / 4] = wh;
     reinterpret_cast<unsigned*>(lp + r * kPitch)[c / 4] = wl;
   }
-  if constexpr (SPLIT > 1) bound[threadIdx.x] = __double_as_longlong(kInf);
+  if constexpr (SPLIT > 1) {
+    bound[threadIdx.x] = __double_as_longlong(kInf);
+    bound[blockDim.x + threadIdx.x] = __double_as_longlong(kInf);
+  }
   __syncthreads();
 
   // this lane's reference (p0 + u, qt + v): operand rows 2g, 2g + 1, and norm
@@ -236,20 +243,30 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   double* mybuf = buf + wave * kBuf * kWave + lane;
   const int r_center = R * S + R;
 
-  // keys are unique: a key above any list's worst kept key for the same
-  // reference cannot be among its K-1 best
+  // the two bounds over the 4 SPLIT lists of this reference (a published
+  // value may be stale: lists only improve, so it stays a valid bound)
+  constexpr int M = (L + 4 * SPLIT - 1) / (4 * SPLIT);
   auto publish = [&]() {
-    double tb = fmin(list[L - 1], shfl_xor_double(list[L - 1], 16));
-    tb = fmin(tb, shfl_xor_double(tb, 32));
+    double b1 = fmin(list[L - 1], shfl_xor_double(list[L - 1], 16));
+    b1 = fmin(b1, shfl_xor_double(b1, 32));
+    double b2 = fmax(list[M - 1], shfl_xor_double(list[M - 1], 16));
+    b2 = fmax(b2, shfl_xor_double(b2, 32));
     if constexpr (SPLIT > 1) {
-      __hip_atomic_store(bound + wave * kWave + lane, static_cast<unsigned long long>(__double_as_longlong(tb)),
+      unsigned long long* bmax = bound + 4 * kWave;
+      __hip_atomic_store(bound + wave * kWave + lane, static_cast<unsigned long long>(__double_as_longlong(b1)),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(bmax + wave * kWave + lane, static_cast<unsigned long long>(__double_as_longlong(b2)),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
-      for (int s2 = 0; s2 < SPLIT; ++s2)
-        tb = fmin(tb, __longlong_as_double(static_cast<long long>(__hip_atomic_load(
-                          bound + (t * SPLIT + s2) * kWave + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))));
+      for (int s2 = 0; s2 < SPLIT; ++s2) {
+        const int o = (t * SPLIT + s2) * kWave + lane;
+        b1 = fmin(b1, __longlong_as_double(static_cast<long long>(
+                          __hip_atomic_load(bound + o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))));
+        b2 = fmax(b2, __longlong_as_double(static_cast<long long>(
+                          __hip_atomic_load(bmax + o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))));
+      }
     }
-    thr = tb;
+    thr = fmin(b1, b2);
   };
   auto flush = [&]() {
     merge_buffer<L, kBuf>(list, mybuf, kWave, cnt);
@@ -319,9 +336,10 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       }
     };
     // Warm start: the first kWarm blocks of this part give 16 candidates per
-    // block and reference (four per lane group); their L best form the first
-    // list (held by lane group 0, so the four quarters stay disjoint) and
-    // its worst key the first bound.
+    // block and reference (four per lane group); sorted, they are dealt round
+    // robin to the four quarters (each key to exactly one, so the quarters
+    // stay disjoint; a quarter's dropped keys have L better ones beside them)
+    // and give the first bounds.
     constexpr int kWarm = L < 16 ? 1 : 2;
     {
       double seed[16 * kWarm];
@@ -344,7 +362,14 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       }
       bitonic_sort<16 * kWarm>(seed);
 #pragma unroll
-      for (int i = 0; i < L && i < 16 * kWarm; ++i) list[i] = g == 0 ? seed[i] : kInf;
+      for (int i = 0; i < L && 4 * i < 16 * kWarm; ++i) {
+        // seed[4 i + g] with a register index known at compile time
+        double x = seed[4 * i];
+        if (g == 1) x = seed[4 * i + 1];
+        if (g == 2) x = seed[4 * i + 2];
+        if (g == 3) x = seed[4 * i + 3];
+        list[i] = x;
+      }
       publish();
     }
     double unused[4];
