@@ -39,7 +39,8 @@ def algorithmic_work(H, W, search, k1, k2, bm_method="shift"):
     FX = 3 * (TPX - 1) + 8 + 2 * R
     FXP = FX + ((8 - FX) % 32 + 32) % 32
     n_tiles = ((nRy + TPY - 1) // TPY) * ((nRx + TPX - 1) // TPX)
-    partial_bytes = n_tiles * 2 * FY * FXP * 8  # 64-bit fixed-point sums
+    partial_bytes = n_tiles * FY * FXP * 8  # 64-bit fixed-point numerator footprints
+    weight_bytes = H * W * 8  # 64-bit block-start weights
     S2 = search * search
     if bm_method == "corr":
         bm = ("mfma", nref * (S2 - 1) * 64 * 4 * 2.0, "OP")
@@ -49,11 +50,14 @@ def algorithmic_work(H, W, search, k1, k2, bm_method="shift"):
     return {
         "bm": bm,
         "bm_norm": ("hbm", H * W * 2 + (H + 64) * (W + 64) * 8, "B"),
-        "stack_bior": ("hbm", H * W * (2 + 256), "B"),
-        "stack_dct": ("hbm", H * W * (2 + 256), "B"),
-        "group_ht": ("hbm", nref * (k1 * 256 + 2 * k1) + partial_bytes, "B"),
-        "group_wiener": ("hbm", nref * (2 * k2 * 256 + 2 * k2) + partial_bytes, "B"),
-        "reduce": ("hbm", partial_bytes + H * W * 6, "B"),
+        # the bior launch and the first of the two DCT launches clear the weights
+        "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes, "B"),
+        "stack_dct": ("hbm", H * W * (2 + 256) + weight_bytes / 2, "B"),
+        # spectra gathered, ranks read, numerator footprints written, one
+        # 8-byte weight added per block
+        "group_ht": ("hbm", nref * (k1 * 256 + 2 * k1 + 8 * k1) + partial_bytes, "B"),
+        "group_wiener": ("hbm", nref * (2 * k2 * 256 + 2 * k2 + 8 * k2) + partial_bytes, "B"),
+        "reduce": ("hbm", partial_bytes + weight_bytes + H * W * 6, "B"),
     }
 
 

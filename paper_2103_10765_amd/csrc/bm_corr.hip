@@ -335,14 +335,12 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
         if (wave_any(cnt > kFlushAt)) flush();
       }
     };
-    // Warm start: the first kWarm blocks of this part give 16 candidates per
-    // block and reference (four per lane group); sorted, they are dealt round
-    // robin to the four quarters (each key to exactly one, so the quarters
-    // stay disjoint; a quarter's dropped keys have L better ones beside them)
-    // and give the first bounds.
+    // Warm start: the first kWarm blocks of this part give each lane four
+    // candidates per block; sorted, they are its first list, and the lists
+    // hold enough keys for a finite m-th-best bound at once.
     constexpr int kWarm = L < 16 ? 1 : 2;
     {
-      double seed[16 * kWarm];
+      double seed[4 * kWarm];
 #pragma unroll
       for (int w = 0; w < kWarm; ++w) {
         double k4[4] = {kInf, kInf, kInf, kInf};
@@ -353,23 +351,11 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
           block(jw, nvw, std::true_type{}, k4);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          seed[4 * w + i] = k4[i];
-          seed[4 * kWarm + 4 * w + i] = shfl_xor_double(k4[i], 16);
-          seed[8 * kWarm + 4 * w + i] = shfl_xor_double(k4[i], 32);
-          seed[12 * kWarm + 4 * w + i] = shfl_xor_double(k4[i], 48);
-        }
+        for (int i = 0; i < 4; ++i) seed[4 * w + i] = k4[i];
       }
-      bitonic_sort<16 * kWarm>(seed);
+      bitonic_sort<4 * kWarm>(seed);
 #pragma unroll
-      for (int i = 0; i < L && 4 * i < 16 * kWarm; ++i) {
-        // seed[4 i + g] with a register index known at compile time
-        double x = seed[4 * i];
-        if (g == 1) x = seed[4 * i + 1];
-        if (g == 2) x = seed[4 * i + 2];
-        if (g == 3) x = seed[4 * i + 3];
-        list[i] = x;
-      }
+      for (int i = 0; i < L && i < 4 * kWarm; ++i) list[i] = seed[i];
       publish();
     }
     double unused[4];

@@ -246,7 +246,9 @@ struct ImgRec {
   float* stack_a;                  // f32 [H*W][64]
   float* stack_b;                  // f32 [H*W][64]
   int16_t* idx;                    // i16 [n_ref][K]
-  unsigned long long* partials;    // 64-bit fixed-point tile sums
+  unsigned long long* partials;    // 64-bit fixed-point aggregation sums: H*W block-start
+                                   // weights (cleared by the stack launch into stack_a),
+                                   // then the tiles' numerator footprints
   double* norm;                    // block norms with a periodic border (correlation matching)
   int H, W;
   float sigma, eps;

@@ -1,21 +1,26 @@
 // Collaborative filtering of matched groups and their aggregation.
 //
-// A workgroup of sixteen (eight for K = 32) waves owns a tile of 8 x 8 references; each wave
+// A workgroup of sixteen waves owns a tile of 8 x 8 references; each wave
 // filters one group at a time with lane = 2-D coefficient index (64 lanes =
 // 8x8 coefficients) and the group axis in registers:
 //   decode the K block positions (lane k decodes slot k, the values are
 //   broadcast as scalars), gather the K spectra from the patch stack (one
 //   coalesced 256 B load per block), 1-D Haar along the group, shrink,
 //   inverse Haar, inverse 2-D transform of the K blocks through a per-wave LDS
-//   scratch (separable rows then columns, level by level), group weight, and
-//   accumulation of w*U and w into an LDS image of the tile's footprint
-//   (every block a reference of the tile can match lies in it: rows
-//   3p-R .. 3p+7+R).
-// The sums are 64-bit fixed point (2^-40), so their value does not depend on
+//   scratch (separable rows then columns, level by level, at most 16 blocks
+//   at a time), group weight, and accumulation of w*U into an LDS image of
+//   the tile's footprint (every block a reference of the tile can match lies
+//   in it: rows 3p-R .. 3p+7+R).
+// The denominator sum of w over the blocks covering a pixel is not spread
+// over 64 pixels per block: w is added once per block at the block's
+// top-left pixel of an image-sized array (global integer atomics, one
+// instruction per group), and the pixel's denominator is the 8 x 8 box sum
+// of that array (periodic).
+// All sums are 64-bit fixed point (2^-40), so their value does not depend on
 // the order in which waves add: results are bit-reproducible.  The footprint
 // is written once per tile to a partial-sum buffer; a second kernel adds the
-// overlapping footprints of every pixel (periodic), divides and optionally
-// quantises.  No global atomics are used.
+// overlapping footprints of every pixel (periodic), forms the box sum,
+// divides and optionally quantises.
 //
 // Stage 1 (Sec. 3.1, Sec. 5): bior1.5 stack, hard threshold |C| >= tau_l with
 //   tau_l = sigma (a - b l) by Mallat level, 3-D DC kept, weight 1/(TV+eps)
@@ -43,19 +48,34 @@ struct Foot {
   static constexpr int FYmax = kStep * (kTPY - 1) + kPatch + 2 * kMaxR;
   static constexpr int FXmax = kStep * (kTPX - 1) + kPatch + 2 * kMaxR;
   static constexpr int FXPmax = FXmax + ((8 - FXmax) % 32 + 32) % 32;
-  static constexpr int entries = 2 * FYmax * FXPmax;
+  static constexpr int entries = FYmax * FXPmax;
 };
 
-// Waves per tile: sixteen (four per SIMD, the groups' LDS round trips hide
-// each other) where the per-wave transform scratch of K blocks still fits
-// beside the footprint accumulator, else eight.
+// blocks per inverse-transform pass through a wave's scratch
 template <int K>
+constexpr int kChunk = K > 16 ? 16 : K;
+
+// Waves per tile: sixteen (four per SIMD, the groups' LDS round trips hide
+// each other) where the per-wave scratch fits beside the footprint
+// accumulator and the filter's registers within a quarter of the register
+// file; else eight.  The hard-threshold filter holds all K inverse blocks
+// until its weight is known, which does not fit for K = 32.
+template <int K, bool HT>
 constexpr int group_waves() {
-  return Foot::entries * static_cast<int>(sizeof(acc_t)) + 16 * K * kBlockFloats * static_cast<int>(sizeof(float)) <=
-                 kLdsBytes
+  return Foot::entries * static_cast<int>(sizeof(acc_t)) +
+                         16 * kChunk<K> * kBlockFloats * static_cast<int>(sizeof(float)) <=
+                     kLdsBytes &&
+                 !(HT && K > 16)
              ? 16
              : 8;
 }
+
+// Layout of an image's aggregation buffer (ImgRec::partials): the H*W
+// block-start weights, then one footprint plane of numerator sums per tile.
+__host__ __device__ inline size_t block_weight_entries(int H, int W) {
+  return (static_cast<size_t>(H) * W + 31) / 32 * 32;
+}
+__device__ __forceinline__ acc_t* tile_sums(const ImgRec& r) { return r.partials + block_weight_entries(r.H, r.W); }
 
 struct GroupArgs {
   int H, W, R, S, nRy, nRx, nTx, nTy;
@@ -138,19 +158,24 @@ __device__ __forceinline__ void slot_pos(const GroupArgs& g, int r, int p, int q
   }
 }
 
-template <int K>
-__device__ __forceinline__ void accumulate(acc_t* acc, const GroupArgs& g, int fo_v, const float (&u)[K], float w,
-                                           int lane) {
+// w * u[k] into the footprint for blocks k0 .. k0 + N - 1 (u holds their values)
+template <int N>
+__device__ __forceinline__ void accumulate(acc_t* acc, const GroupArgs& g, int fo_v, int k0, const float (&u)[N],
+                                           float w, int lane) {
   const int ab = (lane >> 3) * g.FXP + (lane & 7);
-  acc_t* num = acc;
-  acc_t* den = acc + g.FY * g.FXP;
-  const acc_t wf = static_cast<acc_t>(to_fixed(w));
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int o = __builtin_amdgcn_readlane(fo_v, k) + ab;
-    atomicAdd(num + o, static_cast<acc_t>(to_fixed(w * u[k])));
-    atomicAdd(den + o, wf);
+  for (int k = 0; k < N; ++k) {
+    const int o = __builtin_amdgcn_readlane(fo_v, k0 + k) + ab;
+    atomicAdd(acc + o, static_cast<acc_t>(to_fixed(w * u[k])));
   }
+}
+
+// w at the top-left pixel pos of each of the K blocks (lane k holds slot k's);
+// integer addition, so the order of the atomics does not matter
+template <int K>
+__device__ __forceinline__ void add_block_weights(acc_t* bw, int pos_v, float w, int lane) {
+  if (lane < K)
+    __hip_atomic_fetch_add(bw + pos_v, static_cast<acc_t>(to_fixed(w)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void zero_acc(acc_t* acc, int n) {
@@ -165,9 +190,7 @@ __device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __rest
 }
 
 // The groups a wave filters in a tile: reference t = wave + j * WAVES,
-// j < kGroups.  Loads run ahead of the filtering: the ranks of group
-// j + 2 and the spectra of group j + 1 are in flight while group j is
-// filtered.
+// j < kGroups.
 template <int WAVES>
 struct GroupWalk {
   static constexpr int kGroups = kTPY * kTPX / WAVES;
@@ -188,13 +211,13 @@ struct GroupWalk {
     if (!ref_of(j, p, q) || lane >= K) return 0;
     return idx[(static_cast<size_t>(p) * g.nRx + q) * K + lane];
   }
-  // stack rows of group j from its ranks: v[k] = stack[pos_k * 64 + lane]
+  // stack rows of group j from its ranks: v[k] = stack[pos_k * 64 + lane];
+  // lane k < K returns slot k's pixel index and footprint offset
   template <int K, int NS>
-  __device__ __forceinline__ bool gather(int j, int r, const float* const (&stacks)[NS], float (&v)[NS][K],
-                                         int& fo) const {
+  __device__ __forceinline__ bool gather(int j, int r, const float* const (&stacks)[NS], float (&v)[NS][K], int& fo,
+                                         int& pos_v) const {
     int p, q;
     if (!ref_of(j, p, q)) return false;
-    int pos_v;
     slot_pos<K>(g, r, p, q, fy0, fx0, lane, pos_v, fo);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -208,16 +231,54 @@ struct GroupWalk {
   }
 };
 
+// Runs filter(v, fo_v, pos_v) on every group of this wave in the tile, v the
+// gathered spectra.  Small groups also keep the next group's spectra in
+// flight; large ones leave the registers to the filter (sixteen waves per
+// tile hide the loads instead).
+template <int K, int NS, int WAVES, typename F>
+__device__ __forceinline__ void for_each_group(const GroupWalk<WAVES>& walk, const float* const (&stacks)[NS],
+                                               F&& filter) {
+  if constexpr (NS * K <= 16) {
+    int r1 = walk.template rank<K>(1);
+    float cur[NS][K];
+    int fo_c = 0, pos_c = 0;
+    bool ok_c = walk.template gather<K, NS>(0, walk.template rank<K>(0), stacks, cur, fo_c, pos_c);
+    for (int j = 0; j < walk.kGroups; ++j) {
+      const int r2 = walk.template rank<K>(j + 2);
+      float nxt[NS][K];
+      int fo_n = 0, pos_n = 0;
+      const bool ok_n = walk.template gather<K, NS>(j + 1, r1, stacks, nxt, fo_n, pos_n);
+      if (ok_c) filter(cur, fo_c, pos_c);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int k = 0; k < K; ++k) cur[s][k] = nxt[s][k];
+      fo_c = fo_n;
+      pos_c = pos_n;
+      ok_c = ok_n;
+      r1 = r2;
+    }
+  } else {
+    int r0 = walk.template rank<K>(0);
+    for (int j = 0; j < walk.kGroups; ++j) {
+      const int r1 = walk.template rank<K>(j + 1);
+      float cur[NS][K];
+      int fo = 0, pos = 0;
+      if (walk.template gather<K, NS>(j, r0, stacks, cur, fo, pos)) filter(cur, fo, pos);
+      r0 = r1;
+    }
+  }
+}
+
 // One work item = one tile of references: stage-1 groups.
 template <int K>
-__device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * kBlockFloats], const ImgRec& r, int R,
-                                              const HtParams& hp, int item) {
+__device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[kChunk<K> * kBlockFloats],
+                                              const ImgRec& r, int R, const HtParams& hp, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
-  const float* __restrict__ stack = r.stack_a;
   const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = wave_id();
-  const int n_acc = 2 * g.FY * g.FXP;
+  const int n_acc = g.FY * g.FXP;
   zero_acc(acc, n_acc);
   const int fy0 = kStep * tyi * kTPY - g.R;
   const int fx0 = kStep * txi * kTPX - g.R;
@@ -225,20 +286,11 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
   const int a = lane >> 3, b = lane & 7;
   const float tau = r.sigma * (hp.ht_a - hp.ht_b * static_cast<float>(bior_level(lane)));
   const bool dc_lane = hp.keep_dc && lane == 0;
+  acc_t* bw = r.partials;  // block-start weights
 
-  const GroupWalk<group_waves<K>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
-  const float* const stacks[1] = {stack};
-  int r1 = walk.template rank<K>(1);
-  float cur[1][K];
-  int fo_c = 0;
-  bool ok_c = walk.template gather<K, 1>(0, walk.template rank<K>(0), stacks, cur, fo_c);
-  for (int j = 0; j < walk.kGroups; ++j) {
-    const int r2 = walk.template rank<K>(j + 2);
-    float nxt[1][K];
-    int fo_n = 0;
-    const bool ok_n = walk.template gather<K, 1>(j + 1, r1, stacks, nxt, fo_n);
-    if (ok_c) {
-    const int fo_v = fo_c;
+  const GroupWalk<group_waves<K, true>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  const float* const stacks[1] = {r.stack_a};
+  for_each_group<K, 1>(walk, stacks, [&](const float (&cur)[1][K], int fo_v, int pos_v) {
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = cur[0][k];
@@ -254,133 +306,129 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[K * k
       nnz += keep ? 1 : 0;
     }
     haar_inv_raw<K>(v);
-    wave_lds_sync();  // the previous group's reads of the scratch are done
-#pragma unroll
-    for (int k = 0; k < K; ++k) xw[k * kBlockFloats + a * kScratchPitch + b] = v[k];
-    wave_lds_sync();
-    {
-      constexpr Mat8 S2 = bior_synthesis(2);
-      constexpr Mat8 S4 = bior_synthesis(4);
-      constexpr Mat8 S8 = bior_synthesis(8);
-      inverse_level<K, 2>(xw, lane, [&](const float* x, float* y) { apply_mat<2>(S2, x, y); });
-      inverse_level<K, 4>(xw, lane, [&](const float* x, float* y) { apply_mat<4>(S4, x, y); });
-      inverse_level<K, 8>(xw, lane, [&](const float* x, float* y) { apply_mat<8>(S8, x, y); });
-    }
+    // inverse 2-D transform, kChunk blocks at a time through the scratch; the
+    // spatial total-variation terms are read while a chunk is parked there
+    constexpr int CH = kChunk<K>;
+    constexpr Mat8 S2 = bior_synthesis(2);
+    constexpr Mat8 S4 = bior_synthesis(4);
+    constexpr Mat8 S8 = bior_synthesis(8);
     float u[K];
+    float tv = 0.0f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = xw[k * kBlockFloats + a * kScratchPitch + b];
+    for (int c0 = 0; c0 < K; c0 += CH) {
+      wave_lds_sync();  // earlier reads of the scratch are done
+#pragma unroll
+      for (int k = 0; k < CH; ++k) xw[k * kBlockFloats + a * kScratchPitch + b] = v[c0 + k];
+      wave_lds_sync();
+      inverse_level<CH, 2>(xw, lane, [&](const float* x, float* y) { apply_mat<2>(S2, x, y); });
+      inverse_level<CH, 4>(xw, lane, [&](const float* x, float* y) { apply_mat<4>(S4, x, y); });
+      inverse_level<CH, 8>(xw, lane, [&](const float* x, float* y) { apply_mat<8>(S8, x, y); });
+#pragma unroll
+      for (int k = 0; k < CH; ++k) u[c0 + k] = xw[k * kBlockFloats + a * kScratchPitch + b];
+      if (hp.weight_mode == 0) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (b < 7) tv += fabsf(xw[k * kBlockFloats + a * kScratchPitch + b + 1] - u[c0 + k]);
+          if (a < 7) tv += fabsf(xw[k * kBlockFloats + (a + 1) * kScratchPitch + b] - u[c0 + k]);
+        }
+      }
+    }
     float w;
     if (hp.weight_mode == 0) {
-      float tv = 0.0f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (k + 1 < K) tv += fabsf(u[k + 1] - u[k]);
-        if (b < 7) tv += fabsf(xw[k * kBlockFloats + a * kScratchPitch + b + 1] - u[k]);
-        if (a < 7) tv += fabsf(xw[k * kBlockFloats + (a + 1) * kScratchPitch + b] - u[k]);
-      }
+      for (int k = 0; k + 1 < K; ++k) tv += fabsf(u[k + 1] - u[k]);
       w = r.eps / (wave_sum(tv) + r.eps);
     } else if (hp.weight_mode == 1) {
       w = 1.0f / static_cast<float>(max(wave_sum_int(nnz), 1));
     } else {
       w = 1.0f;
     }
-    accumulate<K>(acc, g, fo_v, u, w, lane);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) cur[0][k] = nxt[0][k];
-    fo_c = fo_n;
-    ok_c = ok_n;
-    r1 = r2;
-  }
-  flush_acc(acc, n_acc, r.partials + static_cast<size_t>(item) * n_acc);
+    accumulate<K>(acc, g, fo_v, 0, u, w, lane);
+    add_block_weights<K>(bw, pos_v, w, lane);
+  });
+  flush_acc(acc, n_acc, tile_sums(r) + static_cast<size_t>(item) * n_acc);
 }
 
 // One work item = one tile of references: stage-2 groups.
 template <int K>
-__device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[K * kBlockFloats], const ImgRec& r,
-                                                  int R, int item) {
+__device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[kChunk<K> * kBlockFloats],
+                                                  const ImgRec& r, int R, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
-  const float* __restrict__ stack_n = r.stack_a;
-  const float* __restrict__ stack_p = r.stack_b;
   const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = wave_id();
-  const int n_acc = 2 * g.FY * g.FXP;
+  const int n_acc = g.FY * g.FXP;
   zero_acc(acc, n_acc);
   const int fy0 = kStep * tyi * kTPY - g.R;
   const int fx0 = kStep * txi * kTPX - g.R;
   float* xw = scratch[wave];
   const int a = lane >> 3, b = lane & 7;
   const float s2 = r.sigma * r.sigma;
+  acc_t* bw = r.partials;  // block-start weights
 
-  const GroupWalk<group_waves<K>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
-  const float* const stacks[2] = {stack_n, stack_p};
-  int r1 = walk.template rank<K>(1);
-  float cur[2][K];
-  int fo_c = 0;
-  bool ok_c = walk.template gather<K, 2>(0, walk.template rank<K>(0), stacks, cur, fo_c);
-  for (int j = 0; j < walk.kGroups; ++j) {
-    const int r2 = walk.template rank<K>(j + 2);
-    float nxt[2][K];
-    int fo_n = 0;
-    const bool ok_n = walk.template gather<K, 2>(j + 1, r1, stacks, nxt, fo_n);
-    if (ok_c) {
-    const int fo_v = fo_c;
-    float vn[K], vp[K];
+  const GroupWalk<group_waves<K, false>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  // the walk gathers the pilot's spectra; the noisy ones are loaded once the
+  // gains are known, so the two groups are never in registers together
+  const float* const stacks[1] = {r.stack_b};
+  const float* __restrict__ stack_n = r.stack_a;
+  for_each_group<K, 1>(walk, stacks, [&](const float (&cur)[1][K], int fo_v, int pos_v) {
+    float vp[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      vn[k] = cur[0][k];
-      vp[k] = cur[1][k];
-    }
+    for (int k = 0; k < K; ++k) vp[k] = cur[0][k];
     // unnormalised Haar (orthonormal coefficient k = haar_gain(k) * raw);
     // haar_gain^2 is a power of two, so b^2 and the rescaling are exact
     haar_fwd_raw<K>(vp);
-    haar_fwd_raw<K>(vn);
+    float wt[K];
     float sw2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const float b2 = vp[k] * vp[k] * haar_gain2<K>(k);
-      float wt = b2 * __builtin_amdgcn_rcpf(b2 + s2);
-      if (k == 0 && lane == 0) wt = 1.0f;
-      vn[k] *= wt * haar_gain2<K>(k);
-      sw2 = fmaf(wt, wt, sw2);
+      wt[k] = b2 * __builtin_amdgcn_rcpf(b2 + s2);
+      if (k == 0 && lane == 0) wt[k] = 1.0f;
+      sw2 = fmaf(wt[k], wt[k], sw2);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    float vn[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      vn[k] = load_block_lane(stack_n + static_cast<size_t>(__builtin_amdgcn_readlane(pos_v, k)) * 64, lane);
+    haar_fwd_raw<K>(vn);
+#pragma unroll
+    for (int k = 0; k < K; ++k) vn[k] *= wt[k] * haar_gain2<K>(k);
     const float w = 1.0f / wave_sum(sw2);
     haar_inv_raw<K>(vn);
-    wave_lds_sync();
+    // the weight is known: each chunk is aggregated as soon as it is back
+    constexpr int CH = kChunk<K>;
 #pragma unroll
-    for (int k = 0; k < K; ++k) xw[k * kBlockFloats + a * kScratchPitch + b] = vn[k];
-    wave_lds_sync();
-    inverse_level<K, 8>(xw, lane, [&](const float* x, float* y) { dct8_inv(x, y); });
-    float u[K];
+    for (int c0 = 0; c0 < K; c0 += CH) {
+      wave_lds_sync();  // earlier reads of the scratch are done
 #pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = xw[k * kBlockFloats + a * kScratchPitch + b];
-    accumulate<K>(acc, g, fo_v, u, w, lane);
+      for (int k = 0; k < CH; ++k) xw[k * kBlockFloats + a * kScratchPitch + b] = vn[c0 + k];
+      wave_lds_sync();
+      inverse_level<CH, 8>(xw, lane, [&](const float* x, float* y) { dct8_inv(x, y); });
+      float u[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) u[k] = xw[k * kBlockFloats + a * kScratchPitch + b];
+      accumulate<CH>(acc, g, fo_v, c0, u, w, lane);
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      cur[0][k] = nxt[0][k];
-      cur[1][k] = nxt[1][k];
-    }
-    fo_c = fo_n;
-    ok_c = ok_n;
-    r1 = r2;
-  }
-  flush_acc(acc, n_acc, r.partials + static_cast<size_t>(item) * n_acc);
+    add_block_weights<K>(bw, pos_v, w, lane);
+  });
+  flush_acc(acc, n_acc, tile_sums(r) + static_cast<size_t>(item) * n_acc);
 }
 
 template <int K, bool BATCH>
-__global__ __launch_bounds__(group_waves<K>() * kWave) void group_ht_kernel(ImgRec one, WorkList wl, int R,
+__global__ __launch_bounds__((group_waves<K, true>() * kWave)) void group_ht_kernel(ImgRec one, WorkList wl, int R,
                                                                             HtParams hp) {
   __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[group_waves<K>()][K * kBlockFloats];
+  __shared__ float scratch[group_waves<K, true>()][kChunk<K> * kBlockFloats];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_ht_body<K>(acc, scratch, r, R, hp, item); });
 }
 
 template <int K, bool BATCH>
-__global__ __launch_bounds__(group_waves<K>() * kWave) void group_wiener_kernel(ImgRec one, WorkList wl, int R) {
+__global__ __launch_bounds__((group_waves<K, false>() * kWave)) void group_wiener_kernel(ImgRec one, WorkList wl,
+                                                                                      int R) {
   __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[group_waves<K>()][K * kBlockFloats];
+  __shared__ float scratch[group_waves<K, false>()][kChunk<K> * kBlockFloats];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_wiener_body<K>(acc, scratch, r, R, item); });
 }
 
@@ -388,94 +436,103 @@ __global__ __launch_bounds__(group_waves<K>() * kWave) void group_wiener_kernel(
 __device__ __forceinline__ int fdiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
 // One work item = 256 pixels of one row: sum of the partial footprints
-// covering each pixel (periodic), then normalise.
-__device__ __forceinline__ void reduce_body(const ImgRec& r, int R, int final_stage, int item) {
+// covering each pixel (periodic), the 8 x 8 box sum of the block-start
+// weights, then normalise.
+__device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int R, int final_stage, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
-  const acc_t* __restrict__ partials = r.partials;
+  const acc_t* __restrict__ bw = r.partials;
+  const acc_t* __restrict__ partials = tile_sums(r);
   float* __restrict__ out = final_stage ? r.out : r.basic;
   uint16_t* __restrict__ q = final_stage ? nullptr : r.q;
   const int TY = kStep * kTPY, TX = kStep * kTPX;
   const int xb = (g.W + kReduceThreads - 1) / kReduceThreads;
   const int y = item / xb;
-  const int x = (item % xb) * kReduceThreads + static_cast<int>(threadIdx.x);
-  if (x >= g.W) return;
+  const int xs = (item % xb) * kReduceThreads;
+  const int x = xs + static_cast<int>(threadIdx.x);
+  const bool active = x < g.W;
   // candidate (tile row, local row) pairs for y; the footprint of tile row t
   // covers unwrapped rows [t*TY - R, t*TY - R + FY)
   int cty[16], cly[16], ny = 0;
-  {
-    const int lo = -R, hi = (g.nTy - 1) * TY - R + g.FY;
-    for (int yy = y + fdiv(lo - y + g.H - 1, g.H) * g.H; yy < hi; yy += g.H) {
-      const int t0 = max(0, fdiv(yy + R - g.FY, TY) + 1), t1 = min(g.nTy - 1, fdiv(yy + R, TY));
-      for (int t = t0; t <= t1 && ny < 16; ++t) {
-        cty[ny] = t;
-        cly[ny] = yy - (t * TY - R);
-        ++ny;
+  int ctx[16], clx[16], nx = 0;
+  if (active) {
+    {
+      const int lo = -R, hi = (g.nTy - 1) * TY - R + g.FY;
+      for (int yy = y + fdiv(lo - y + g.H - 1, g.H) * g.H; yy < hi; yy += g.H) {
+        const int t0 = max(0, fdiv(yy + R - g.FY, TY) + 1), t1 = min(g.nTy - 1, fdiv(yy + R, TY));
+        for (int t = t0; t <= t1 && ny < 16; ++t) {
+          cty[ny] = t;
+          cly[ny] = yy - (t * TY - R);
+          ++ny;
+        }
       }
     }
-  }
-  int ctx[16], clx[16], nx = 0;
-  {
-    const int lo = -R, hi = (g.nTx - 1) * TX - R + g.FX;
-    for (int xx = x + fdiv(lo - x + g.W - 1, g.W) * g.W; xx < hi; xx += g.W) {
-      const int t0 = max(0, fdiv(xx + R - g.FX, TX) + 1), t1 = min(g.nTx - 1, fdiv(xx + R, TX));
-      for (int t = t0; t <= t1 && nx < 16; ++t) {
-        ctx[nx] = t;
-        clx[nx] = xx - (t * TX - R);
-        ++nx;
+    {
+      const int lo = -R, hi = (g.nTx - 1) * TX - R + g.FX;
+      for (int xx = x + fdiv(lo - x + g.W - 1, g.W) * g.W; xx < hi; xx += g.W) {
+        const int t0 = max(0, fdiv(xx + R - g.FX, TX) + 1), t1 = min(g.nTx - 1, fdiv(xx + R, TX));
+        for (int t = t0; t <= t1 && nx < 16; ++t) {
+          ctx[nx] = t;
+          clx[nx] = xx - (t * TX - R);
+          ++nx;
+        }
       }
     }
   }
   const size_t plane = static_cast<size_t>(g.FY) * g.FXP;
   auto at = [&](int i, int j) -> const acc_t* {
-    return partials + (static_cast<size_t>(cty[i]) * g.nTx + ctx[j]) * 2 * plane +
-           static_cast<size_t>(cly[i]) * g.FXP + clx[j];
+    return partials + (static_cast<size_t>(cty[i]) * g.nTx + ctx[j]) * plane + static_cast<size_t>(cly[i]) * g.FXP +
+           clx[j];
   };
-  acc_t num = 0, den = 0;
-  if (ny <= 3 && nx <= 3) {
-    // the usual case: at most 3 x 3 footprints; every load is issued before
-    // the sums so their latencies overlap
-    acc_t vn[3][3], vd[3][3];
+  // The usual case, at most 3 x 3 footprints: their loads are issued before
+  // the weights' column sums below, so the two round trips overlap.
+  const bool few = ny <= 3 && nx <= 3;
+  acc_t vn[3][3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        vn[i][j] = 0;
-        vd[i][j] = 0;
-        if (i < ny && j < nx) {
-          const acc_t* t = at(i, j);
-          vn[i][j] = t[0];
-          vd[i][j] = t[plane];
-        }
-      }
+    for (int j = 0; j < 3; ++j) vn[i][j] = (few && i < ny && j < nx) ? *at(i, j) : 0;
+  // colsum[c] = sum over rows y-7..y of the weights at column xs - 7 + c
+  for (int c = threadIdx.x; c < kReduceThreads + 7; c += blockDim.x) {
+    const size_t xx = static_cast<size_t>(pmod(xs - 7 + c, g.W));
+    acc_t v[8];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int dy = 0; dy < 8; ++dy) v[dy] = bw[static_cast<size_t>(pmod(y - dy, g.H)) * g.W + xx];
+    acc_t sum = 0;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        num += vn[i][j];
-        den += vd[i][j];
-      }
-  } else {
-    // small images whose footprints wrap around more than once
-    for (int i = 0; i < ny; ++i)
-      for (int j = 0; j < nx; ++j) {
-        const acc_t* t = at(i, j);
-        num += t[0];
-        den += t[plane];
-      }
+    for (int dy = 0; dy < 8; ++dy) sum += v[dy];
+    colsum[c] = sum;
   }
-  const float v = static_cast<float>(static_cast<double>(static_cast<long long>(num)) /
-                                     static_cast<double>(static_cast<long long>(den)));
-  const size_t o = static_cast<size_t>(y) * g.W + x;
-  out[o] = v;
-  if (q) {
-    const double d = static_cast<double>(fminf(fmaxf(v, 0.0f), 1.0f));
-    q[o] = static_cast<uint16_t>(floor(d * 65535.0 + 0.5));
+  __syncthreads();
+  if (active) {
+    acc_t num = 0;
+    if (few) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) num += vn[i][j];
+    } else {
+      // small images whose footprints wrap around more than once
+      for (int i = 0; i < ny; ++i)
+        for (int j = 0; j < nx; ++j) num += *at(i, j);
+    }
+    acc_t den = 0;
+#pragma unroll
+    for (int dx = 0; dx < 8; ++dx) den += colsum[threadIdx.x + 7 - dx];
+    const float v = static_cast<float>(static_cast<double>(static_cast<long long>(num)) /
+                                       static_cast<double>(static_cast<long long>(den)));
+    const size_t o = static_cast<size_t>(y) * g.W + x;
+    out[o] = v;
+    if (q) {
+      const double d = static_cast<double>(fminf(fmaxf(v, 0.0f), 1.0f));
+      q[o] = static_cast<uint16_t>(floor(d * 65535.0 + 0.5));
+    }
   }
 }
 
 template <bool BATCH>
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ImgRec one, WorkList wl, int R, int final_stage) {
-  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { reduce_body(r, R, final_stage, item); });
+  __shared__ acc_t colsum[kReduceThreads + 8];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { reduce_body(colsum, r, R, final_stage, item); });
 }
 
 __global__ void quantize_kernel(const float* __restrict__ in, uint16_t* __restrict__ out, size_t n) {
@@ -490,7 +547,7 @@ __global__ void quantize_kernel(const float* __restrict__ in, uint16_t* __restri
 
 size_t partials_bytes(int H, int W, int R) {
   const GroupArgs g = make_args(H, W, R);
-  return static_cast<size_t>(g.nTy) * g.nTx * 2 * g.FY * g.FXP * sizeof(acc_t);
+  return (block_weight_entries(H, W) + static_cast<size_t>(g.nTy) * g.nTx * g.FY * g.FXP) * sizeof(acc_t);
 }
 
 int group_items_for(int H, int W, int R) {
@@ -503,13 +560,14 @@ int reduce_items_for(int H, int W) { return reduce_items(H, W); }
 template <int K>
 static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int grid_cap,
                               hipStream_t st) {
+  constexpr int threads = group_waves<K, true>() * kWave;
   if (!wl) {
-    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(group_waves<K>() * kWave), 0, st,
-                       one, WorkList{}, R, hp);
+    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(threads), 0, st, one,
+                       WorkList{}, R, hp);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(group_waves<K>() * kWave), 0, st, one,
-                       *wl, R, hp);
+    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(threads), 0, st, one, *wl,
+                       R, hp);
   }
   return hipGetLastError();
 }
@@ -529,13 +587,14 @@ hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, 
 
 template <int K>
 static hipError_t launch_wiener_k(const ImgRec& one, const WorkList* wl, int R, int grid_cap, hipStream_t st) {
+  constexpr int threads = group_waves<K, false>() * kWave;
   if (!wl) {
-    hipLaunchKernelGGL((group_wiener_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(group_waves<K>() * kWave), 0,
-                       st, one, WorkList{}, R);
+    hipLaunchKernelGGL((group_wiener_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(threads), 0, st,
+                       one, WorkList{}, R);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_wiener_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(group_waves<K>() * kWave), 0, st,
-                       one, *wl, R);
+    hipLaunchKernelGGL((group_wiener_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(threads), 0, st, one,
+                       *wl, R);
   }
   return hipGetLastError();
 }

@@ -43,7 +43,8 @@ hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src
                         hipStream_t st);
 int stack_items_for(int H, int W);
 
-// bytes of the per-tile partial-sum buffer (64-bit fixed point) of the group kernels
+// bytes of the aggregation buffer (64-bit fixed point) of the group kernels:
+// block-start weights of the image, then one numerator footprint per tile
 size_t partials_bytes(int H, int W, int R);
 int group_items_for(int H, int W, int R);
 
@@ -54,7 +55,8 @@ hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, 
 // stage-2 groups: stack_a (noisy DCT) + stack_b (pilot DCT) + idx -> partials
 hipError_t launch_group_wiener(const ImgRec& one, const WorkList* wl, int R, int K, int grid_cap, hipStream_t st);
 
-// sum(num) / sum(den) over the overlapping tile footprints into rec.basic
+// sum(num) over the overlapping tile footprints / 8 x 8 box sum of the
+// block-start weights into rec.basic
 // (+ its quantisation into rec.q when set) or, with final_stage, rec.out
 hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int R, int final_stage, int grid_cap,
                          hipStream_t st);

@@ -61,8 +61,8 @@ __host__ __device__ constexpr int stack_items(int H, int W) {
 
 template <int KIND>
 __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*stage)[kWave * kStagePitch],
-                                           const uint16_t* __restrict__ img, float* __restrict__ out, int H, int W,
-                                           int item) {
+                                           const uint16_t* __restrict__ img, float* __restrict__ out,
+                                           unsigned long long* __restrict__ block_weights, int H, int W, int item) {
   const int xt = (W + kWave - 1) / kWave;
   const int y0 = (item / xt) * kRowsPerWg;
   const int x0 = (item % xt) * kWave;
@@ -92,6 +92,8 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
   const int y = y0 + w;
   if (y < H) {
     const int n_pos = min(kWave, W - x0);  // positions of this row in the tile
+    // the aggregation that follows adds into the block-start weights
+    if (block_weights && lane < n_pos) block_weights[static_cast<size_t>(y) * W + x0 + lane] = 0;
     float4* dst = reinterpret_cast<float4*>(out + (static_cast<size_t>(y) * W + x0) * 64);
     // 16 rounds; in round i lane l stores float4 g = i*64 + l of the run
 #pragma unroll
@@ -113,7 +115,8 @@ __global__ __launch_bounds__(256) void stack_kernel(ImgRec one, WorkList wl, int
   __shared__ float pix[kPixRows][kPixCols + 1];
   __shared__ float stage[kRowsPerWg][kWave * kStagePitch];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    stack_body<KIND>(pix, stage, src_sel ? r.pilot : r.noisy, dst_sel ? r.stack_b : r.stack_a, r.H, r.W, item);
+    stack_body<KIND>(pix, stage, src_sel ? r.pilot : r.noisy, dst_sel ? r.stack_b : r.stack_a,
+                     dst_sel ? nullptr : r.partials, r.H, r.W, item);
   });
 }
 
