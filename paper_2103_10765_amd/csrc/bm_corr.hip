@@ -41,8 +41,14 @@ constexpr int kNormPad = 32;                       // periodic border of the nor
 constexpr int kPitch = 96;                         // bytes per LDS plane row
 constexpr int kMaxNb = (2 * kMaxR + 10 + 3) / 4;   // candidate blocks per axis
 constexpr int kRows = 4 * kMaxNb + 7;              // LDS plane rows
-constexpr int kBuf = 8;                            // buffered candidates per lane
-constexpr int kFlushAt = kBuf - 4;                 // a block appends at most 4
+// Buffered candidates per lane before a merge into the list.  A merge runs
+// when any lane of the wave might overflow, so a deeper buffer makes merges
+// rarer; the depth is what the LDS allows at the occupancy the registers
+// already set (four waves per SIMD for K <= 16, three for K = 32).
+template <int K>
+constexpr int kBuf = K >= 32 ? 16 : K >= 16 ? 12 : 8;
+template <int K>
+constexpr int kFlushAt = kBuf<K> - 4;  // a block appends at most 4
 constexpr int kZShift = 32896;
 constexpr double kInf = __builtin_huge_val();
 
@@ -135,7 +141,7 @@ template <int K, int TPW, int SPLIT>
 struct CorrSmem {
   static constexpr int L = K - 1;
   static constexpr size_t kPlanes = 2 * kRows * kPitch;
-  static constexpr size_t kBufBytes = sizeof(double) * 4 * kBuf * kWave;
+  static constexpr size_t kBufBytes = sizeof(double) * 4 * kBuf<K> * kWave;
   static constexpr size_t kBound = SPLIT > 1 ? sizeof(double) * 2 * 4 * kWave : 0;
   static constexpr size_t kScan = kPlanes + kBufBytes + kBound;
   static constexpr size_t kMerge = SPLIT > 1 ? sizeof(double) * 2 * L * kWave : 0;
@@ -240,7 +246,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   double thr = kInf;  // no key at or above it can enter the list
   const double key_base = 2048.0 * nr;
   int cnt = 0;
-  double* mybuf = buf + wave * kBuf * kWave + lane;
+  double* mybuf = buf + wave * kBuf<K> * kWave + lane;
   const int r_center = R * S + R;
 
   // the two bounds over the 4 SPLIT lists of this reference (a published
@@ -269,7 +275,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
     thr = fmin(b1, b2);
   };
   auto flush = [&]() {
-    merge_buffer<L, kBuf>(list, mybuf, kWave, cnt);
+    merge_buffer<L, kBuf<K>>(list, mybuf, kWave, cnt);
     cnt = 0;
     publish();
   };
@@ -332,7 +338,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       else
         pairs(std::false_type{});
       if constexpr (!decltype(warm)::value) {
-        if (wave_any(cnt > kFlushAt)) flush();
+        if (wave_any(cnt > kFlushAt<K>)) flush();
       }
     };
     // Warm start: the first kWarm blocks of this part give each lane four

@@ -1012,8 +1012,9 @@ int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target,
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t ab = act_bytes(B, H, W);
   const size_t npix = static_cast<size_t>(B) * H * W;
-  // layout: acts x0..x5 | grad ping-pong g0, g1 | pilot f32
-  CHECK(ensure(ctx, ctx->pilot_act, 8 * ab + align256(npix * sizeof(float)), "pilot training activations"));
+  // layout: layer inputs x0 .. x(L-1) | grad ping-pong g0, g1 | pilot f32
+  constexpr int L = gbm3d::kPilotLayers;
+  CHECK(ensure(ctx, ctx->pilot_act, (L + 2) * ab + align256(npix * sizeof(float)), "pilot training activations"));
   const int wg_grid = 2 * ctx->n_cu;
   const int loss_blocks = 1024;
   CHECK(ensure(ctx, ctx->pilot_part,
@@ -1021,8 +1022,8 @@ int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target,
                "pilot partial sums"));
   char* act = static_cast<char*>(ctx->pilot_act.p);
   auto x = [&](int l) { return reinterpret_cast<uint16_t*>(act + l * ab); };
-  uint16_t* gbuf[2] = {reinterpret_cast<uint16_t*>(act + 6 * ab), reinterpret_cast<uint16_t*>(act + 7 * ab)};
-  float* pil = reinterpret_cast<float*>(act + 8 * ab);
+  uint16_t* gbuf[2] = {reinterpret_cast<uint16_t*>(act + L * ab), reinterpret_cast<uint16_t*>(act + (L + 1) * ab)};
+  float* pil = reinterpret_cast<float*>(act + (L + 2) * ab);
   float* wpart = static_cast<float*>(ctx->pilot_part.p);
   double* lpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->pilot_part.p) +
                                             gbm3d::pilot_wgrad_partial_floats(wg_grid) * sizeof(float));

@@ -59,15 +59,18 @@ __device__ __forceinline__ void merge_sorted(double (&list)[L], Bf b) {
       }
 }
 
+constexpr int pow2_ceil(int n) { return n <= 1 ? 1 : 2 * pow2_ceil((n + 1) / 2); }
+
 // Merges this lane's first cnt buffered keys (buf[j * stride], cnt <= B) into
-// list: the batch is padded with inf, sorted, then merged.
+// list: the batch is padded with inf to a power of two, sorted, then merged.
 template <int L, int B>
 __device__ __forceinline__ void merge_buffer(double (&list)[L], const double* buf, int stride, int cnt) {
-  double b[B];
+  constexpr int P = pow2_ceil(B);
+  double b[P];
 #pragma unroll
-  for (int j = 0; j < B; ++j) b[j] = j < cnt ? buf[j * stride] : kKeyInf;
-  bitonic_sort<B>(b);
-  merge_sorted<L>(list, [&](int j) { return j < B ? b[j] : kKeyInf; });
+  for (int j = 0; j < P; ++j) b[j] = (j < B && j < cnt) ? buf[j * stride] : kKeyInf;
+  bitonic_sort<P>(b);
+  merge_sorted<L>(list, [&](int j) { return j < P ? b[j] : kKeyInf; });
 }
 
 __device__ __forceinline__ double shfl_xor_double(double v, int mask) {

@@ -206,6 +206,25 @@ def test_basic_weight_variants(torch, G, ctx, weight):
     _check_stage1(Yg, Yo, idx, margin, p, clean)
 
 
+@pytest.mark.parametrize("k_ht,k_wiener", [(2, 4), (8, 8), (32, 16)])
+def test_group_sizes_parity(torch, G, ctx, k_ht, k_wiener):
+    """Both stages at the other group sizes (32 stage-1 blocks go through the
+    transform scratch in two passes; small groups keep the next group's
+    spectra in flight)."""
+    H, W, S = 52, 47, 15
+    say("group sizes", k_ht, k_wiener)
+    clean, Z = synth.make_case(H, W, SIG, 16)
+    gp = G.default_params(search=S, k_ht=k_ht, k_wiener=k_wiener)
+    p = oparams(G, gp)
+    Yg = ctx.basic(up(torch, Z), SIG, gp).cpu().numpy().astype(np.float64)
+    Yo, (idx, margin, _, _) = O.basic_estimate(Z, SIG, p, return_parts=True)
+    _check_stage1(Yg, Yo, idx, margin, p, clean)
+    pilot = O.quantize(Yo)
+    Yw = ctx.wiener(up(torch, Z), up(torch, pilot), SIG, gp).cpu().numpy().astype(np.float64)
+    Ywo = O.wiener_estimate(Z, pilot, SIG, p)
+    assert np.abs(Yw - Ywo).max() <= MAXABS
+
+
 def test_basic_zero_threshold_identity(torch, G, ctx):
     _, Z = synth.make_case(70, 80, SIG, 13)
     gp = G.default_params(search=21, ht_a=0.0, ht_b=0.0)
