@@ -82,9 +82,13 @@ __constant__ BlockOrder kOrder = make_block_order();
 __device__ __forceinline__ int norm_pitch(int W) { return W + 2 * kNormPad; }
 
 // ---------------------------------------------------------------------------
-// Norm table: N[ey][ex] = sum over the 8 x 8 block at image position
-// ((ey - pad) mod H, (ex - pad) mod W) of (Z - 32896)^2, for
-// ey < H + 2 pad, ex < W + 2 pad.  Items are 16 x 64 output tiles.
+// Norm table: T[ey][ex] = 2048 N + ((ex + R) mod 4), N the sum over the
+// 8 x 8 block at image position ((ey - pad) mod H, (ex - pad) mod W) of
+// (Z - 32896)^2, for ey < H + 2 pad, ex < W + 2 pad (exact: 2048 N < 2^50).
+// The matching kernel's candidate blocks start at table columns
+// congruent to -R mod 4, so (ex + R) mod 4 is the candidate's column in its
+// block, the part of its rank that varies inside a block: the key's
+// candidate term is one load.  Items are 16 x 64 output tiles.
 // ---------------------------------------------------------------------------
 constexpr int kNTy = 16, kNTx = 64;
 
@@ -93,7 +97,7 @@ __host__ __device__ constexpr int norm_items(int H, int W) {
 }
 
 __device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img, double* __restrict__ norm, int H, int W,
-                                          int item, int* zt, double* hs) {
+                                          int R, int item, int* zt, double* hs) {
   const int He = H + 2 * kNormPad, We = norm_pitch(W);
   const int tiles_x = (We + kNTx - 1) / kNTx;
   const int ty0 = (item / tiles_x) * kNTy, tx0 = (item % tiles_x) * kNTx;
@@ -120,16 +124,17 @@ __device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img, doub
     double s = 0.0;
 #pragma unroll
     for (int a = 0; a < 8; ++a) s += hs[(r + a) * kNTx + c];
-    if (ty0 + r < He && tx0 + c < We) norm[static_cast<size_t>(ty0 + r) * We + tx0 + c] = s;
+    if (ty0 + r < He && tx0 + c < We)
+      norm[static_cast<size_t>(ty0 + r) * We + tx0 + c] = fma(s, 2048.0, static_cast<double>((tx0 + c + R) & 3));
   }
 }
 
 template <bool BATCH>
-__global__ __launch_bounds__(256) void bm_norm_kernel(ImgRec one, WorkList wl, int use_pilot) {
+__global__ __launch_bounds__(256) void bm_norm_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
   __shared__ int zt[(kNTy + 7) * (kNTx + 7)];
   __shared__ double hs[(kNTy + 7) * kNTx];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    norm_body(use_pilot ? r.pilot : r.noisy, r.norm, r.H, r.W, item, zt, hs);
+    norm_body(use_pilot ? r.pilot : r.noisy, r.norm, r.H, r.W, R, item, zt, hs);
   });
 }
 
@@ -234,17 +239,20 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   i32x4 rh, rl;
   load_operand(hp, lp, R + 3 * u, R + 12 * t + 3 * v, g, rh, rl);
   const int We = norm_pitch(W);
-  // (a tile right of the last reference column only takes part in the merges)
-  const double nr =
-      qt < nRx ? norm[static_cast<size_t>(kStep * (p0 + u) + kNormPad) * We + kStep * (qt + v) + kNormPad] : 0.0;
-  // norms of this lane's result candidates: block (br, bc) row g, columns 0..3
+  // 2048 N of the reference: its table entry less the column term (a tile
+  // right of the last reference column only takes part in the merges)
+  const int cr = kStep * (qt + v) + kNormPad;
+  const double nr2048 =
+      qt < nRx ? norm[static_cast<size_t>(kStep * (p0 + u) + kNormPad) * We + cr] - static_cast<double>((cr + R) & 3)
+               : 0.0;
+  // table entries of this lane's result candidates: block (br, bc) row g, columns 0..3
   const double* ncand = norm + static_cast<size_t>(y0 + g + kNormPad) * We + (x0 + 12 * t + kNormPad);
 
   double list[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) list[i] = kInf;
   double thr = kInf;  // no key at or above it can enter the list
-  const double key_base = 2048.0 * nr;
+  const double key_base = nr2048;
   int cnt = 0;
   double* mybuf = buf + wave * kBuf<K> * kWave + lane;
   const int r_center = R * S + R;
@@ -319,7 +327,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int s = hh[i] * 256 + cc[i];  // 256 Phh + Phl + Plh, |s| < 2^29
-          const double c = fma(nv[i], 2048.0, kb + static_cast<double>(i));
+          const double c = nv[i] + kb;  // 2048 N(b) + i from the table
           const double key =
               fma(-1048576.0, static_cast<double>(s), fma(-4096.0, static_cast<double>(ll[i]), c));
           // (bitwise: no short-circuit branches)
@@ -476,13 +484,14 @@ long corr_tiles(int H, int W) { return static_cast<long>(corr_items<1>(H, W)); }
 
 int corr_auto_split(long tiles) { return tiles >= 4096 ? 1 : (tiles >= 2048 ? 2 : 4); }
 
-hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int use_pilot, int grid_cap, hipStream_t st) {
+hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int R, int use_pilot, int grid_cap,
+                          hipStream_t st) {
   if (!wl) {
-    hipLaunchKernelGGL((bm_norm_kernel<false>), dim3(norm_items(one.H, one.W)), dim3(256), 0, st, one, WorkList{},
+    hipLaunchKernelGGL((bm_norm_kernel<false>), dim3(norm_items(one.H, one.W)), dim3(256), 0, st, one, WorkList{}, R,
                        use_pilot);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((bm_norm_kernel<true>), dim3(std::min(wl->total, grid_cap)), dim3(256), 0, st, one, *wl,
+    hipLaunchKernelGGL((bm_norm_kernel<true>), dim3(std::min(wl->total, grid_cap)), dim3(256), 0, st, one, *wl, R,
                        use_pilot);
   }
   return hipGetLastError();

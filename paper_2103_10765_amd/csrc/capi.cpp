@@ -280,7 +280,7 @@ int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const BmChoice& c, int us
   if (c.method == GBM3D_BM_CORR) {
     CHECK(ensure(ctx, ctx->norm, gbm3d::norm_bytes(r.H, r.W), "norm table"));
     r.norm = static_cast<double*>(ctx->norm.p);
-    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(r, nullptr, use_pilot, 0, st); }),
+    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(r, nullptr, R, use_pilot, 0, st); }),
             "norm table launch");
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
               return gbm3d::launch_bm_corr(r, nullptr, R, K, c.split, use_pilot, 0, st);
@@ -483,7 +483,7 @@ int launch_batch_match(gbm3d_ctx* ctx, const WorkList& nm, const WorkList& bm, i
   const ImgRec none = blank_rec(0, 0, 0.0f);
   const int cu = ctx->n_cu;
   if (method == GBM3D_BM_CORR) {
-    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(none, &nm, use_pilot, 4 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(none, &nm, R, use_pilot, 4 * cu, st); }),
             "batch norm tables");
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
               return gbm3d::launch_bm_corr(none, &bm, R, K, split, use_pilot, 4 * cu, st);

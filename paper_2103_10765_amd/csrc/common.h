@@ -155,10 +155,6 @@ __device__ __forceinline__ void dct8_inv(const float* X, float* x) {
   }
 }
 
-// round(x * 2^40) as a 64-bit integer, exact for |x| < 2^11: the fixed-point
-// format of the aggregation sums (integer addition is order-independent).
-// Weights can be small (1/TV), so the format keeps 40 fractional bits.
-constexpr double kFixScale = 1099511627776.0;  // 2^40
 // Element `lane` of the 64 floats at `blk` (a wave-uniform address) by a raw
 // buffer load: the base lives in scalar registers, the offset lane * 4 in
 // the instruction, so a gather of whole blocks costs no vector address
@@ -170,10 +166,24 @@ __device__ __forceinline__ float load_block_lane(const float* blk, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, 0, 0));
 }
 
+// round(x * 2^40) as a 64-bit integer, exact for |x| < 2^11: the fixed-point
+// format of the aggregation sums (integer addition is order-independent).
+// Weights can be small (1/TV), so the format keeps 40 fractional bits.
+constexpr double kFixScale = 1099511627776.0;  // 2^40
+constexpr float kFixScaleF = 1099511627776.0f;
+constexpr double kFixMagic = 6755399441055744.0;  // 1.5 * 2^52: adding it rounds to an integer
+
 __device__ __forceinline__ long long to_fixed(float x) {
-  const double magic = 6755399441055744.0;  // 1.5 * 2^52
-  const double y = fma(static_cast<double>(x), kFixScale, magic);
-  return __double_as_longlong(y) - __double_as_longlong(magic);
+  const double y = fma(static_cast<double>(x), kFixScale, kFixMagic);
+  return __double_as_longlong(y) - __double_as_longlong(kFixMagic);
+}
+
+// The same for xs = x * 2^40 already formed in float (scaling by a power of
+// two is exact, so the result is identical); one add instead of an FMA with a
+// register copy of the magic constant.
+__device__ __forceinline__ long long to_fixed_scaled(float xs) {
+  const double y = static_cast<double>(xs) + kFixMagic;
+  return __double_as_longlong(y) - __double_as_longlong(kFixMagic);
 }
 
 // ---------------------------------------------------------------------------

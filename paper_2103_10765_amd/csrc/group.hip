@@ -163,10 +163,11 @@ template <int N>
 __device__ __forceinline__ void accumulate(acc_t* acc, const GroupArgs& g, int fo_v, int k0, const float (&u)[N],
                                            float w, int lane) {
   const int ab = (lane >> 3) * g.FXP + (lane & 7);
+  const float ws = w * kFixScaleF;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     const int o = __builtin_amdgcn_readlane(fo_v, k0 + k) + ab;
-    atomicAdd(acc + o, static_cast<acc_t>(to_fixed(w * u[k])));
+    atomicAdd(acc + o, static_cast<acc_t>(to_fixed_scaled(ws * u[k])));
   }
 }
 

@@ -26,9 +26,11 @@ int bm_items_for(int H, int W, int split);
 
 // Correlation-form matching (Theorem 1, int8 matrix cores): the same indices.
 // launch_bm_norm writes rec.norm (norm_bytes: the block norms of the noisy or
-// pilot image with a periodic border) and must precede launch_bm_corr on the
+// pilot image with a periodic border, times 2048, plus a column term that
+// depends on R) and must precede launch_bm_corr with the same R on the
 // stream.  split: waves sharing a 4x4 reference tile (1, 2, 4; 0 = by size).
-hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int use_pilot, int grid_cap, hipStream_t st);
+hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int R, int use_pilot, int grid_cap,
+                          hipStream_t st);
 hipError_t launch_bm_corr(const ImgRec& one, const WorkList* wl, int R, int K, int split, int use_pilot, int grid_cap,
                           hipStream_t st);
 size_t norm_bytes(int H, int W);

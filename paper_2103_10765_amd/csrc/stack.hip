@@ -5,9 +5,10 @@
 //            low-low block;
 //   DCT:     orthonormal separable 8x8 DCT-II (Sec. 4).
 // A workgroup covers 4 rows x 64 columns of positions.  Each thread
-// transforms one block read from an LDS pixel tile, parks its 64 coefficients
-// in LDS, and the wave then writes its 64 consecutive positions as one
-// contiguous 16 KB run with 16-byte stores.
+// transforms one block read from an LDS pixel tile; in two halves of 32
+// positions, the threads park their 64 coefficients in LDS and the wave
+// writes the half's consecutive positions as one contiguous 8 KB run with
+// 16-byte stores (half-size staging keeps four workgroups per CU).
 #include "common.h"
 #include "kernels.h"
 
@@ -19,6 +20,7 @@ constexpr int kRowsPerWg = 4;
 constexpr int kPixRows = kRowsPerWg + kPatch - 1;  // 11
 constexpr int kPixCols = kWave + kPatch - 1;       // 71
 constexpr int kStagePitch = 65;                    // floats per parked block (odd: conflict-free)
+constexpr int kHalf = kWave / 2;                   // positions parked at a time
 
 // one separable level on the leading L x L block: rows (x[a][0..L)), then columns
 template <int L, typename F>
@@ -60,7 +62,7 @@ __host__ __device__ constexpr int stack_items(int H, int W) {
 }
 
 template <int KIND>
-__device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*stage)[kWave * kStagePitch],
+__device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*stage)[kHalf * kStagePitch],
                                            const uint16_t* __restrict__ img, float* __restrict__ out,
                                            unsigned long long* __restrict__ block_weights, int H, int W, int item) {
   const int xt = (W + kWave - 1) / kWave;
@@ -82,27 +84,32 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
 #pragma unroll
     for (int b = 0; b < 8; ++b) x[a][b] = pix[w + a][lane + b];
   forward2d<KIND>(x);
-  float* st = stage[w] + lane * kStagePitch;
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) st[a * 8 + b] = x[a][b];
-  wave_lds_sync();
-
   const int y = y0 + w;
-  if (y < H) {
-    const int n_pos = min(kWave, W - x0);  // positions of this row in the tile
-    // the aggregation that follows adds into the block-start weights
-    if (block_weights && lane < n_pos) block_weights[static_cast<size_t>(y) * W + x0 + lane] = 0;
-    float4* dst = reinterpret_cast<float4*>(out + (static_cast<size_t>(y) * W + x0) * 64);
-    // 16 rounds; in round i lane l stores float4 g = i*64 + l of the run
+  const int n_pos = min(kWave, W - x0);  // positions of this row in the tile
+  // the aggregation that follows adds into the block-start weights
+  if (block_weights && y < H && lane < n_pos) block_weights[static_cast<size_t>(y) * W + x0 + lane] = 0;
+  float4* dst = reinterpret_cast<float4*>(out + (static_cast<size_t>(y) * W + x0) * 64);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int g = i * kWave + lane;
-      const int blk = g >> 4, c = (g & 15) * 4;
-      if (blk < n_pos) {
-        const float* s = stage[w] + blk * kStagePitch + c;
-        dst[g] = make_float4(s[0], s[1], s[2], s[3]);
+  for (int half = 0; half < 2; ++half) {
+    wave_lds_sync();  // the previous half's reads are done
+    if ((lane / kHalf) == half) {
+      float* st = stage[w] + (lane % kHalf) * kStagePitch;
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) st[a * 8 + b] = x[a][b];
+    }
+    wave_lds_sync();
+    if (y < H) {
+      // 8 rounds; in round i lane l stores float4 g = i*64 + l of the half's run
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int g = i * kWave + lane;
+        const int blk = g >> 4, c = (g & 15) * 4;
+        if (half * kHalf + blk < n_pos) {
+          const float* s = stage[w] + blk * kStagePitch + c;
+          dst[half * kHalf * 16 + g] = make_float4(s[0], s[1], s[2], s[3]);
+        }
       }
     }
   }
@@ -113,7 +120,7 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
 template <int KIND, bool BATCH>
 __global__ __launch_bounds__(256) void stack_kernel(ImgRec one, WorkList wl, int src_sel, int dst_sel) {
   __shared__ float pix[kPixRows][kPixCols + 1];
-  __shared__ float stage[kRowsPerWg][kWave * kStagePitch];
+  __shared__ float stage[kRowsPerWg][kHalf * kStagePitch];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
     stack_body<KIND>(pix, stage, src_sel ? r.pilot : r.noisy, dst_sel ? r.stack_b : r.stack_a,
                      dst_sel ? nullptr : r.partials, r.H, r.W, item);
