@@ -88,9 +88,10 @@ __device__ __forceinline__ int norm_pitch(int W) { return W + 2 * kNormPad; }
 // The matching kernel's candidate blocks start at table columns
 // congruent to -R mod 4, so (ex + R) mod 4 is the candidate's column in its
 // block, the part of its rank that varies inside a block: the key's
-// candidate term is one load.  Items are 16 x 64 output tiles.
+// candidate term is one load.  Items are 8 x 64 output tiles (small tiles:
+// many workgroups in flight for what is a short, latency-bound pass).
 // ---------------------------------------------------------------------------
-constexpr int kNTy = 16, kNTx = 64;
+constexpr int kNTy = 8, kNTx = 64;
 
 __host__ __device__ constexpr int norm_items(int H, int W) {
   return ((H + 2 * kNormPad + kNTy - 1) / kNTy) * ((W + 2 * kNormPad + kNTx - 1) / kNTx);
@@ -102,9 +103,19 @@ __device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img, doub
   const int tiles_x = (We + kNTx - 1) / kNTx;
   const int ty0 = (item / tiles_x) * kNTy, tx0 = (item % tiles_x) * kNTx;
   constexpr int ZR = kNTy + 7, ZC = kNTx + 7;
+  // table rows and columns lie within one period of the image when it is at
+  // least as large as the border plus a tile; else the general modulo
+  const bool near = H >= kNormPad + kNTy + 7 && W >= kNormPad + kNTx + 7;
   for (int i = threadIdx.x; i < ZR * ZC; i += blockDim.x) {
     const int r = i / ZC, c = i - r * ZC;
-    const int y = pmod(ty0 + r - kNormPad, H), x = pmod(tx0 + c - kNormPad, W);
+    int y = ty0 + r - kNormPad, x = tx0 + c - kNormPad;
+    if (near) {
+      y += y < 0 ? H : (y >= H ? -H : 0);
+      x += x < 0 ? W : (x >= W ? -W : 0);
+    } else {
+      y = pmod(y, H);
+      x = pmod(x, W);
+    }
     zt[i] = static_cast<int>(img[static_cast<size_t>(y) * W + x]) - kZShift;
   }
   __syncthreads();
