@@ -20,9 +20,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 lanes x 2 (FMA)
 INT8_MFMA_PEAK_TOPS = 5000.0   # dense int8 matrix cores
+BF16_MFMA_PEAK_TFLOPS = 2500.0 # dense bf16 matrix cores
 # bound -> (peak, unit, scale of the unit)
 PEAKS = {"hbm": (HBM_PEAK_GBS, "GB/s", 1e9), "alu": (FP64_VALU_PEAK_TFLOPS, "TFLOP/s", 1e12),
-         "mfma": (INT8_MFMA_PEAK_TOPS, "TOP/s", 1e12)}
+         "mfma": (INT8_MFMA_PEAK_TOPS, "TOP/s", 1e12), "mfma_bf16": (BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", 1e12)}
 
 
 def algorithmic_work(H, W, search, k1, k2, bm_method="shift"):
@@ -113,6 +114,81 @@ def copy_calibration(mib):
     y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n, "ok": bool(y[-1].item() == 1)}), flush=True)
+
+
+def copy_bandwidth(gib=2, reps=5):
+    """Measured HBM bandwidth: a device-to-device copy of `gib` GiB (far past
+    the 256 MB last-level cache), read + written bytes over event time."""
+    import torch
+    n = gib << 30
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_GBps": gbps, "bytes": 2 * n}
+
+
+def pilot_conv_rate(ctx, n=32, size=512):
+    """Matrix-core rate of the pilot network's convolutions on the evaluation
+    batch shape (library-recorded events around each layer's launch)."""
+    import numpy as np
+    import torch
+    from paper_2103_10765_amd import pilot
+    rng = np.random.default_rng(7)
+    Zt = torch.from_numpy(rng.integers(0, 65536, size=(n, size, size), dtype=np.uint16)).cuda()
+    sig = torch.full((n,), 25.0 / 255.0, dtype=torch.float32, device="cuda")
+    ctx.pilot_infer(Zt, sig)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    reps = 3
+    for _ in range(reps):
+        ctx.pilot_infer(Zt, sig)
+    torch.cuda.synchronize()
+    tot, launches = ctx.timing_read("pilot_conv")
+    ctx.timing(False)
+    flop_px = sum(2 * 9 * ci * co for ci, co in pilot.LAYERS)
+    tflops = n * size * size * flop_px * reps / (tot * 1e-3) / 1e12
+    return {"conv_ms_per_batch": tot / reps, "flop_per_pixel": flop_px, "achieved_TFLOPs": tflops,
+            "peak_TFLOPs": PEAKS["mfma_bf16"][0], "frac": tflops / PEAKS["mfma_bf16"][0]}
+
+
+def sigma_bench(ctx, p, Zt_shape, steps=50):
+    """The 512^2 image at sigma 15, 25 and 50 / 255: Mpixel/s and PSNR."""
+    import numpy as np
+    import torch
+    from oracle import gbm3d_oracle as O
+    from paper_2103_10765_amd import synth
+    H, W = Zt_shape
+    res = {}
+    for s255 in (15.0, 25.0, 50.0):
+        sigma = s255 / 255.0
+        clean, Z = synth.make_case(H, W, sigma, 2)
+        Zt = torch.from_numpy(Z).cuda()
+        out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            ctx.denoise(Zt, sigma, p, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ctx.denoise(Zt, sigma, p, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[f"{s255:g}"] = {"mpix_s": H * W / (ms * 1e-3) / 1e6,
+                            "psnr_db": O.psnr(out.cpu().numpy().astype(np.float64), clean),
+                            "psnr_noisy_db": O.psnr(Z / 65535.0, clean)}
+    return res
 
 
 def cpu_baseline(Z, sigma, size=320):
@@ -331,8 +407,16 @@ def main():
         rec["pilot"] = pb
         if "psnr_gap_db" in pb:
             rec["psnr_gap_db"] = pb["psnr_gap_db"]
+        if "skipped" not in pb:
+            rec["pilot"]["conv"] = pilot_conv_rate(ctx)
         rec["batch"] = batch_bench(ctx)
         rec["sizes"] = size_bench(ctx, p)
+        rec["sigmas"] = sigma_bench(ctx, p, (H, W))
+        mp = copy_bandwidth()
+        rec["measured_peaks"] = mp
+        for k in kernels.values():
+            if k["bound"] == "hbm":
+                k["frac_of_measured_copy"] = k["achieved"] / mp["copy_GBps"]
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(Z, sigma)
     print(json.dumps(rec), flush=True)
