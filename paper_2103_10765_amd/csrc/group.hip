@@ -80,6 +80,7 @@ __device__ __forceinline__ acc_t* tile_sums(const ImgRec& r) { return r.partials
 struct GroupArgs {
   int H, W, R, S, nRy, nRx, nTx, nTy;
   int FY, FX, FXP;
+  float invS;  // 1 / S for the rank decode
 };
 
 __host__ __device__ inline GroupArgs make_args(int H, int W, int R) {
@@ -95,6 +96,7 @@ __host__ __device__ inline GroupArgs make_args(int H, int W, int R) {
   g.FY = kStep * (kTPY - 1) + kPatch + 2 * R;
   g.FX = kStep * (kTPX - 1) + kPatch + 2 * R;
   g.FXP = g.FX + ((8 - g.FX) % 32 + 32) % 32;
+  g.invS = 1.0f / static_cast<float>(g.S);
   return g;
 }
 
@@ -151,9 +153,14 @@ __device__ __forceinline__ void slot_pos(const GroupArgs& g, int r, int p, int q
   pos = 0;
   fo = 0;
   if (lane < K) {
-    const int dyi = r / g.S, dxi = r - dyi * g.S;
+    // r / S in float: r + 1/2 lies at least 1/(2S) from a multiple of S and
+    // r < S^2 <= 1521, far inside float's exact range
+    const int dyi = static_cast<int>((static_cast<float>(r) + 0.5f) * g.invS), dxi = r - dyi * g.S;
     const int y = kStep * p + dyi - g.R, x = kStep * q + dxi - g.R;
-    pos = pmod(y, g.H) * g.W + pmod(x, g.W);
+    // -R <= y < H + R and H >= S > R + 1: at most one period away (same for x)
+    const int yw = y < 0 ? y + g.H : (y >= g.H ? y - g.H : y);
+    const int xw = x < 0 ? x + g.W : (x >= g.W ? x - g.W : x);
+    pos = yw * g.W + xw;
     fo = (y - fy0) * g.FXP + (x - fx0);
   }
 }
@@ -484,20 +491,33 @@ __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int 
     return partials + (static_cast<size_t>(cty[i]) * g.nTx + ctx[j]) * plane + static_cast<size_t>(cly[i]) * g.FXP +
            clx[j];
   };
-  // The usual case, at most 3 x 3 footprints: their loads are issued before
-  // the weights' column sums below, so the two round trips overlap.
-  const bool few = ny <= 3 && nx <= 3;
-  acc_t vn[3][3];
+  // The usual case, at most 4 x 4 footprints (3 per axis inside the image,
+  // 4 where the last tiles' footprints wrap over the first rows or columns):
+  // their loads are issued before the weights' column sums below, so the two
+  // round trips overlap.
+  constexpr int kFew = 4;
+  const bool few = ny <= kFew && nx <= kFew;
+  acc_t vn[kFew][kFew];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < kFew; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) vn[i][j] = (few && i < ny && j < nx) ? *at(i, j) : 0;
+    for (int j = 0; j < kFew; ++j) vn[i][j] = (few && i < ny && j < nx) ? *at(i, j) : 0;
   // colsum[c] = sum over rows y-7..y of the weights at column xs - 7 + c
+  // (H, W >= 8, so a row index wraps at most once; so does a column index
+  // when W covers a chunk and its 7-column margin)
+  const bool wide = g.W >= kReduceThreads + 7;
   for (int c = threadIdx.x; c < kReduceThreads + 7; c += blockDim.x) {
-    const size_t xx = static_cast<size_t>(pmod(xs - 7 + c, g.W));
+    int xi = xs - 7 + c;
+    if (wide)
+      xi += xi < 0 ? g.W : (xi >= g.W ? -g.W : 0);
+    else
+      xi = pmod(xi, g.W);
     acc_t v[8];
 #pragma unroll
-    for (int dy = 0; dy < 8; ++dy) v[dy] = bw[static_cast<size_t>(pmod(y - dy, g.H)) * g.W + xx];
+    for (int dy = 0; dy < 8; ++dy) {
+      const int yy = y - dy < 0 ? y - dy + g.H : y - dy;
+      v[dy] = bw[static_cast<size_t>(yy) * g.W + xi];
+    }
     acc_t sum = 0;
 #pragma unroll
     for (int dy = 0; dy < 8; ++dy) sum += v[dy];
@@ -508,9 +528,9 @@ __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int 
     acc_t num = 0;
     if (few) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < kFew; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) num += vn[i][j];
+        for (int j = 0; j < kFew; ++j) num += vn[i][j];
     } else {
       // small images whose footprints wrap around more than once
       for (int i = 0; i < ny; ++i)
