@@ -412,6 +412,8 @@ def main():
         rec["batch"] = batch_bench(ctx)
         rec["sizes"] = size_bench(ctx, p)
         rec["sigmas"] = sigma_bench(ctx, p, (H, W))
+        from paper_2103_10765_amd import pnp
+        rec["pnp"] = pnp.bench(ctx)
         mp = copy_bandwidth()
         rec["measured_peaks"] = mp
         for k in kernels.values():

@@ -137,3 +137,33 @@ def pilot_train_crop(i: int, sigma: float, size: int = 128):
 
 def pilot_eval_cases(n: int = 32, size: int = 512, sigma: float = SIGMA25):
     return [make_case(size, size, sigma, 6000 + i) for i in range(n)]
+
+
+# ---- plug-and-play deblurring workload -------------------------------------
+
+def blur_kernel(size: int = 9, std: float = 1.6) -> np.ndarray:
+    """Normalised isotropic Gaussian point-spread function (size x size)."""
+    a = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
+    g = np.exp(-0.5 * (a / std) ** 2)
+    k = np.outer(g, g)
+    return k / k.sum()
+
+
+def psf_spectrum(k: np.ndarray, H: int, W: int) -> np.ndarray:
+    """2-D DFT (H x W) of the point-spread function centred at pixel (0, 0),
+    so that multiplying spectra is a zero-phase periodic convolution."""
+    s = k.shape[0]
+    pad = np.zeros((H, W))
+    pad[:s, :s] = k
+    pad = np.roll(pad, (-(s // 2), -(s // 2)), axis=(0, 1))
+    return np.fft.fft2(pad)
+
+
+def pnp_case(H: int, W: int, seed: int, sigma_n: float = 0.01, ksize: int = 9, kstd: float = 1.6):
+    """(clean, observation y = k (*) clean + n as float64, psf k): periodic
+    blur by a Gaussian PSF and white Gaussian noise of deviation sigma_n."""
+    clean = clean_image(H, W, seed)
+    k = blur_kernel(ksize, kstd)
+    blurred = np.real(np.fft.ifft2(np.fft.fft2(clean) * psf_spectrum(k, H, W)))
+    rng = np.random.default_rng(seed + 2_000_000)
+    return clean, blurred + sigma_n * rng.standard_normal((H, W)), k

@@ -1,0 +1,61 @@
+"""Pins of the plug-and-play deblurring oracle (CPU only)."""
+import numpy as np
+
+from oracle import pnp_oracle as P
+from paper_2103_10765_amd import synth
+
+
+def _conv_periodic(x, k):
+    """k (*) x by explicit periodic shifts, the PSF centred at (0, 0)."""
+    s = k.shape[0]
+    c = s // 2
+    out = np.zeros_like(x)
+    for a in range(s):
+        for b in range(s):
+            out += k[a, b] * np.roll(x, (a - c, b - c), axis=(0, 1))
+    return out
+
+
+def test_psf_spectrum_is_the_periodic_convolution():
+    rng = np.random.default_rng(0)
+    x = rng.random((20, 23))
+    k = synth.blur_kernel(9, 1.6)
+    via_fft = np.real(np.fft.ifft2(np.fft.fft2(x) * synth.psf_spectrum(k, 20, 23)))
+    assert np.abs(via_fft - _conv_periodic(x, k)).max() < 1e-12
+
+
+def test_x_step_solves_the_normal_equations():
+    """(K'K + mu I) x = K'y + mu w, with K the periodic blur and K' its
+    adjoint (the flipped PSF; the Gaussian is symmetric)."""
+    rng = np.random.default_rng(1)
+    H, W = 24, 30
+    k = synth.blur_kernel(9, 1.6)
+    y, w = rng.random((H, W)), rng.random((H, W))
+    mu = 0.37
+    x = P.x_step(np.fft.fft2(y), synth.psf_spectrum(k, H, W), w, mu)
+    kf = k[::-1, ::-1]
+    lhs = _conv_periodic(_conv_periodic(x, k), kf) + mu * x
+    rhs = _conv_periodic(y, kf) + mu * w
+    assert np.abs(lhs - rhs).max() < 1e-10
+
+
+def test_x_step_without_blur_is_the_weighted_mean():
+    rng = np.random.default_rng(2)
+    y, w = rng.random((16, 16)), rng.random((16, 16))
+    delta = np.zeros((3, 3))
+    delta[1, 1] = 1.0
+    x = P.x_step(np.fft.fft2(y), synth.psf_spectrum(delta, 16, 16), w, 0.25)
+    assert np.abs(x - (y + 0.25 * w) / 1.25).max() < 1e-12
+
+
+def test_strength_schedule():
+    s = P.strengths(5, 0.08, 0.02)
+    assert abs(s[0] - 0.08) < 1e-15 and abs(s[-1] - 0.02) < 1e-15
+    assert np.allclose(s[1:] / s[:-1], (0.02 / 0.08) ** 0.25)
+
+
+def test_observation_model():
+    clean, y, k = synth.pnp_case(96, 96, 3, sigma_n=0.02)
+    assert abs(k.sum() - 1.0) < 1e-12 and np.allclose(k, k.T)
+    resid = y - np.real(np.fft.ifft2(np.fft.fft2(clean) * synth.psf_spectrum(k, 96, 96)))
+    assert abs(resid.std() - 0.02) < 0.002
