@@ -1,6 +1,6 @@
 // Collaborative filtering of matched groups and their aggregation.
 //
-// A workgroup of sixteen waves owns a tile of 8 x 8 references; each wave
+// A workgroup of 8 to 16 waves owns a tile of 8 x 8 references; each wave
 // filters one group at a time with lane = 2-D coefficient index (64 lanes =
 // 8x8 coefficients) and the group axis in registers:
 //   decode the K block positions (lane k decodes slot k, the values are
@@ -51,24 +51,37 @@ struct Foot {
   static constexpr int entries = FYmax * FXPmax;
 };
 
-// blocks per inverse-transform pass through a wave's scratch
-template <int K>
-constexpr int kChunk = K > 16 ? 16 : K;
-
-// Waves per tile: sixteen (four per SIMD, the groups' LDS round trips hide
-// each other) where the per-wave scratch fits beside the footprint
-// accumulator and the filter's registers within a quarter of the register
-// file; else eight.  The hard-threshold filter holds all K inverse blocks
-// until its weight is known, which does not fit for K = 32.
-template <int K, bool HT>
-constexpr int group_waves() {
-  return Foot::entries * static_cast<int>(sizeof(acc_t)) +
-                         16 * kChunk<K> * kBlockFloats * static_cast<int>(sizeof(float)) <=
-                     kLdsBytes &&
-                 !(HT && K > 16)
-             ? 16
-             : 8;
-}
+// Launch shape of a group kernel.  The hard-threshold kernel on one image
+// (K <= 16) runs two tiles per CU: 12 waves each (six per SIMD), inverse
+// transforms 8 blocks at a time through each wave's scratch, no prefetch of
+// the next group (the other waves hide the loads).  Otherwise one tile per
+// CU: sixteen waves (four per SIMD) where a 16-block scratch per wave fits
+// beside the footprint accumulator and the filter's registers fit a quarter
+// of the register file, else eight; small groups keep the next group's
+// spectra in flight.  The hard-threshold filter holds all K inverse blocks
+// until its weight is known, which does not fit sixteen waves for K = 32;
+// the batched variant carries more state per wave and keeps one tile per CU.
+template <int K, bool HT, bool BATCH>
+struct GroupCfg {
+  static constexpr bool two_tiles = HT && K <= 16 && !BATCH;
+  static constexpr int chunk = two_tiles ? (K > 8 ? 8 : K) : (K > 16 ? 16 : K);
+  static constexpr int waves =
+      two_tiles ? 12
+      : Foot::entries * static_cast<int>(sizeof(acc_t)) +
+                      16 * chunk * kBlockFloats * static_cast<int>(sizeof(float)) <=
+                  kLdsBytes &&
+              !(HT && K > 16)
+          ? 16
+          : 8;
+  static constexpr int tiles = two_tiles ? 2 : 1;
+  static constexpr bool prefetch = !two_tiles && K <= 16;
+  static constexpr int threads = waves * kWave;
+  static constexpr int min_waves_per_simd = waves * tiles / 4;
+  static_assert(tiles * (Foot::entries * static_cast<int>(sizeof(acc_t)) +
+                         waves * chunk * kBlockFloats * static_cast<int>(sizeof(float))) <=
+                    kLdsBytes,
+                "LDS of the tiles sharing a CU");
+};
 
 // Layout of an image's aggregation buffer (ImgRec::partials): the H*W
 // block-start weights, then one footprint plane of numerator sums per tile.
@@ -201,7 +214,7 @@ __device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __rest
 // j < kGroups.
 template <int WAVES>
 struct GroupWalk {
-  static constexpr int kGroups = kTPY * kTPX / WAVES;
+  static constexpr int kGroups = (kTPY * kTPX + WAVES - 1) / WAVES;
   const GroupArgs& g;
   const int16_t* __restrict__ idx;
   int tyi, txi, wave, lane, fy0, fx0;
@@ -210,7 +223,7 @@ struct GroupWalk {
     const int t = wave + j * WAVES;
     p = tyi * kTPY + t / kTPX;
     q = txi * kTPX + t % kTPX;
-    return j < kGroups && p < g.nRy && q < g.nRx;
+    return j < kGroups && t < kTPY * kTPX && p < g.nRy && q < g.nRx;
   }
   // rank of slot `lane` of group j (0 where there is none)
   template <int K>
@@ -243,10 +256,10 @@ struct GroupWalk {
 // gathered spectra.  Small groups also keep the next group's spectra in
 // flight; large ones leave the registers to the filter (sixteen waves per
 // tile hide the loads instead).
-template <int K, int NS, int WAVES, typename F>
+template <int K, int NS, bool PREFETCH, int WAVES, typename F>
 __device__ __forceinline__ void for_each_group(const GroupWalk<WAVES>& walk, const float* const (&stacks)[NS],
                                                F&& filter) {
-  if constexpr (NS * K <= 16) {
+  if constexpr (PREFETCH) {
     int r1 = walk.template rank<K>(1);
     float cur[NS][K];
     int fo_c = 0, pos_c = 0;
@@ -279,8 +292,8 @@ __device__ __forceinline__ void for_each_group(const GroupWalk<WAVES>& walk, con
 }
 
 // One work item = one tile of references: stage-1 groups.
-template <int K>
-__device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[kChunk<K> * kBlockFloats],
+template <int K, bool BATCH>
+__device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[GroupCfg<K, true, BATCH>::chunk * kBlockFloats],
                                               const ImgRec& r, int R, const HtParams& hp, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
   const int tyi = item / g.nTx, txi = item % g.nTx;
@@ -296,9 +309,10 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[kChun
   const bool dc_lane = hp.keep_dc && lane == 0;
   acc_t* bw = r.partials;  // block-start weights
 
-  const GroupWalk<group_waves<K, true>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  using Cfg = GroupCfg<K, true, BATCH>;
+  const GroupWalk<Cfg::waves> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
   const float* const stacks[1] = {r.stack_a};
-  for_each_group<K, 1>(walk, stacks, [&](const float (&cur)[1][K], int fo_v, int pos_v) {
+  for_each_group<K, 1, Cfg::prefetch>(walk, stacks, [&](const float (&cur)[1][K], int fo_v, int pos_v) {
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = cur[0][k];
@@ -316,7 +330,7 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[kChun
     haar_inv_raw<K>(v);
     // inverse 2-D transform, kChunk blocks at a time through the scratch; the
     // spatial total-variation terms are read while a chunk is parked there
-    constexpr int CH = kChunk<K>;
+    constexpr int CH = Cfg::chunk;
     constexpr Mat8 S2 = bior_synthesis(2);
     constexpr Mat8 S4 = bior_synthesis(4);
     constexpr Mat8 S8 = bior_synthesis(8);
@@ -358,8 +372,9 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[kChun
 }
 
 // One work item = one tile of references: stage-2 groups.
-template <int K>
-__device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[kChunk<K> * kBlockFloats],
+template <int K, bool BATCH>
+__device__ __forceinline__ void group_wiener_body(acc_t* acc,
+                                                  float (*scratch)[GroupCfg<K, false, BATCH>::chunk * kBlockFloats],
                                                   const ImgRec& r, int R, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
   const int tyi = item / g.nTx, txi = item % g.nTx;
@@ -374,12 +389,13 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[k
   const float s2 = r.sigma * r.sigma;
   acc_t* bw = r.partials;  // block-start weights
 
-  const GroupWalk<group_waves<K, false>()> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  using Cfg = GroupCfg<K, false, BATCH>;
+  const GroupWalk<Cfg::waves> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
   // the walk gathers the pilot's spectra; the noisy ones are loaded once the
   // gains are known, so the two groups are never in registers together
   const float* const stacks[1] = {r.stack_b};
   const float* __restrict__ stack_n = r.stack_a;
-  for_each_group<K, 1>(walk, stacks, [&](const float (&cur)[1][K], int fo_v, int pos_v) {
+  for_each_group<K, 1, Cfg::prefetch>(walk, stacks, [&](const float (&cur)[1][K], int fo_v, int pos_v) {
     float vp[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) vp[k] = cur[0][k];
@@ -406,7 +422,7 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[k
     const float w = 1.0f / wave_sum(sw2);
     haar_inv_raw<K>(vn);
     // the weight is known: each chunk is aggregated as soon as it is back
-    constexpr int CH = kChunk<K>;
+    constexpr int CH = Cfg::chunk;
 #pragma unroll
     for (int c0 = 0; c0 < K; c0 += CH) {
       wave_lds_sync();  // earlier reads of the scratch are done
@@ -424,20 +440,27 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc, float (*scratch)[k
   flush_acc(acc, n_acc, tile_sums(r) + static_cast<size_t>(item) * n_acc);
 }
 
+// (the second launch bound is the minimum number of waves per SIMD)
 template <int K, bool BATCH>
-__global__ __launch_bounds__((group_waves<K, true>() * kWave)) void group_ht_kernel(ImgRec one, WorkList wl, int R,
-                                                                            HtParams hp) {
+__global__ __launch_bounds__((GroupCfg<K, true, BATCH>::threads),
+                             (GroupCfg<K, true, BATCH>::min_waves_per_simd)) void group_ht_kernel(ImgRec one,
+                                                                                                   WorkList wl, int R,
+                                                                                                   HtParams hp) {
+  using Cfg = GroupCfg<K, true, BATCH>;
   __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[group_waves<K, true>()][kChunk<K> * kBlockFloats];
-  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_ht_body<K>(acc, scratch, r, R, hp, item); });
+  __shared__ float scratch[Cfg::waves][Cfg::chunk * kBlockFloats];
+  for_each_item<BATCH>(one, wl,
+                       [&](const ImgRec& r, int item) { group_ht_body<K, BATCH>(acc, scratch, r, R, hp, item); });
 }
 
 template <int K, bool BATCH>
-__global__ __launch_bounds__((group_waves<K, false>() * kWave)) void group_wiener_kernel(ImgRec one, WorkList wl,
-                                                                                      int R) {
+__global__ __launch_bounds__((GroupCfg<K, false, BATCH>::threads)) void group_wiener_kernel(ImgRec one, WorkList wl,
+                                                                                             int R) {
+  using Cfg = GroupCfg<K, false, BATCH>;
   __shared__ acc_t acc[Foot::entries];
-  __shared__ float scratch[group_waves<K, false>()][kChunk<K> * kBlockFloats];
-  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { group_wiener_body<K>(acc, scratch, r, R, item); });
+  __shared__ float scratch[Cfg::waves][Cfg::chunk * kBlockFloats];
+  for_each_item<BATCH>(one, wl,
+                       [&](const ImgRec& r, int item) { group_wiener_body<K, BATCH>(acc, scratch, r, R, item); });
 }
 
 // floor(a / b) for b > 0
@@ -581,14 +604,13 @@ int reduce_items_for(int H, int W) { return reduce_items(H, W); }
 template <int K>
 static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int grid_cap,
                               hipStream_t st) {
-  constexpr int threads = group_waves<K, true>() * kWave;
   if (!wl) {
-    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(threads), 0, st, one,
-                       WorkList{}, R, hp);
+    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)),
+                       dim3(GroupCfg<K, true, false>::threads), 0, st, one, WorkList{}, R, hp);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(threads), 0, st, one, *wl,
-                       R, hp);
+    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)),
+                       dim3(GroupCfg<K, true, true>::threads), 0, st, one, *wl, R, hp);
   }
   return hipGetLastError();
 }
@@ -608,14 +630,13 @@ hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, 
 
 template <int K>
 static hipError_t launch_wiener_k(const ImgRec& one, const WorkList* wl, int R, int grid_cap, hipStream_t st) {
-  constexpr int threads = group_waves<K, false>() * kWave;
   if (!wl) {
-    hipLaunchKernelGGL((group_wiener_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)), dim3(threads), 0, st,
-                       one, WorkList{}, R);
+    hipLaunchKernelGGL((group_wiener_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)),
+                       dim3(GroupCfg<K, false, false>::threads), 0, st, one, WorkList{}, R);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_wiener_kernel<K, true>), dim3(std::min(wl->total, grid_cap)), dim3(threads), 0, st, one,
-                       *wl, R);
+    hipLaunchKernelGGL((group_wiener_kernel<K, true>), dim3(std::min(wl->total, grid_cap)),
+                       dim3(GroupCfg<K, false, true>::threads), 0, st, one, *wl, R);
   }
   return hipGetLastError();
 }
