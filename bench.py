@@ -191,6 +191,37 @@ def sigma_bench(ctx, p, Zt_shape, steps=50):
     return res
 
 
+def global_bench(ctx, Zt, clean, sigma, steps=20):
+    """The volume form of stage 1 (tiles of 16, one 3-D transform of the
+    whole volume, 2 cycle spins, 2 translations) against the grouped stage 1
+    on the same image: Mpixel/s and PSNR of each."""
+    import numpy as np
+    import torch
+    from oracle import gbm3d_oracle as O
+    H, W = Zt.shape
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_g = timed(lambda: ctx.global_basic(Zt, sigma, out=out))
+    p_g = O.psnr(out.cpu().numpy().astype(np.float64), clean)
+    ms_b = timed(lambda: ctx.basic(Zt, sigma, out=out))
+    p_b = O.psnr(out.cpu().numpy().astype(np.float64), clean)
+    mpx = H * W / 1e6
+    return {"global_ms": ms_g, "global_mpix_s": mpx / (ms_g * 1e-3), "global_psnr_db": p_g,
+            "grouped_ms": ms_b, "grouped_mpix_s": mpx / (ms_b * 1e-3), "grouped_psnr_db": p_b}
+
+
 def cpu_baseline(Z, sigma, size=320):
     """The CPU oracle (one thread) on a size x size crop of the same image."""
     import numpy as np
@@ -414,6 +445,7 @@ def main():
         rec["sigmas"] = sigma_bench(ctx, p, (H, W))
         from paper_2103_10765_amd import pnp
         rec["pnp"] = pnp.bench(ctx)
+        rec["global_stage1"] = global_bench(ctx, Zt, clean, sigma)
         mp = copy_bandwidth()
         rec["measured_peaks"] = mp
         for k in kernels.values():

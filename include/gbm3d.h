@@ -166,6 +166,50 @@ int gbm3d_denoise(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sig
                   const gbm3d_params* params, float* out, float* basic_out,
                   uint16_t* q_out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Global stage 1 (Sec. 3, the volume form; Sec. 5 parameters): reference
+ * blocks of side `patch` tile the image, each is matched to its `k` nearest
+ * blocks in the search window (same key and tie rule as gbm3d_match, slot 0
+ * the reference), the k-th matches are stacked behind the references into a
+ * volume with the noisy image as its first slice, the whole volume is
+ * transformed (periodic separable 3-D Mallat decomposition, `levels` levels:
+ * bior1.5 along both image axes, orthonormal Haar along the match axis),
+ * hard-thresholded with tau_l = sigma (ht_a - ht_b l) per detail level (the
+ * final approximation kept) and inverted, averaged over `cycles` cycle spins
+ * (circular shifts by h = 0 .. cycles-1 along all three axes); the blocks
+ * return to their sources with weight 1 / (TV + eps) of their reference's
+ * block (3-D total variation, eps = tv_eps_rel sigma patch^2 k), and the
+ * normalised estimate is averaged over the `n_shifts` image translations
+ * `shifts` (eq. firstEst).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t struct_size; /* = sizeof(gbm3d_global_params) */
+  int32_t patch;        /* 8 or 16 (16 in Sec. 5); H and W multiples of it */
+  int32_t search;       /* odd, 3 .. 39 (Sec. 5 states 32; default 33) */
+  int32_t k;            /* 8, 16 (default) or 32; k >= 2^levels */
+  int32_t levels;       /* 1 .. 3 (default 3) */
+  int32_t cycles;       /* 1 .. 4 (default 2) */
+  int32_t n_shifts;     /* 1 .. 4 (default 2) */
+  int32_t shifts[4];    /* translations, each in [0, patch) (default 0, patch/4) */
+  float ht_a, ht_b;     /* 3.6, 0.3 */
+  float tv_eps_rel;     /* 1e-3 */
+} gbm3d_global_params;
+
+void gbm3d_global_default_params(gbm3d_global_params* p);
+
+/* noisy: device u16 [H][W]; out: device float [H][W].  H, W: multiples of
+ * patch, at least max(search, patch).  The context keeps three float volumes
+ * of k H W entries and 2 H W 64-bit sums as workspace. */
+int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
+                       const gbm3d_global_params* params, float* out, void* stream);
+
+/* The tile matching of gbm3d_global_basic alone (S^K_pq of Sec. 3.1 for the
+ * reference tiles): idx device int16 [(H/patch)(W/patch)][k], tiles in raster
+ * order, displacement ranks r = (dy+R)*search + (dx+R), slot 0 the tile
+ * itself, then ascending (distance, rank). */
+int gbm3d_global_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W,
+                       const gbm3d_global_params* params, int16_t* idx, void* stream);
+
 /* A batch of images of any sizes (the plug-and-play use case of Sec. 1: one
  * denoiser call per iteration, many images).  imgs: HOST array of n
  * descriptors (device pointers inside).  For each image: if pilot == NULL,

@@ -65,6 +65,8 @@ struct gbm3d_ctx {
   int n_cu = 256;
   std::string err;
   Buffer stack_a, stack_b, idx, partials, basic, q, norm;
+  // global stage 1
+  Buffer gl_a, gl_b, gl_u, gl_num, gl_idx, gl_shift;
   // block-matching choices per (K, shape class)
   std::map<std::pair<int, int>, TuneEntry> tuned;
   // batches
@@ -636,7 +638,8 @@ void gbm3d_destroy(gbm3d_ctx* ctx) {
     (void)hipDeviceSynchronize();
     drop_graph(ctx);
     for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->norm, &ctx->batch_ws,
-                      &ctx->batch_table, &ctx->pilot_w, &ctx->pilot_act, &ctx->pilot_part})
+                      &ctx->batch_table, &ctx->pilot_w, &ctx->pilot_act, &ctx->pilot_part, &ctx->gl_a, &ctx->gl_b,
+                      &ctx->gl_u, &ctx->gl_num, &ctx->gl_idx, &ctx->gl_shift})
       if (b->p) (void)hipFree(b->p);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
@@ -808,6 +811,114 @@ int gbm3d_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
   return run_basic(ctx, noisy, H, W, sigma, p, basic, nullptr, static_cast<hipStream_t>(stream));
+}
+
+void gbm3d_global_default_params(gbm3d_global_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(gbm3d_global_params);
+  p->patch = 16;
+  p->search = 33;
+  p->k = 16;
+  p->levels = 3;
+  p->cycles = 2;
+  p->n_shifts = 2;
+  p->shifts[0] = 0;
+  p->shifts[1] = 4;
+  p->ht_a = 3.6f;
+  p->ht_b = 0.3f;
+  p->tv_eps_rel = 1e-3f;
+}
+
+namespace {
+
+int resolve_global(gbm3d_ctx* ctx, const gbm3d_global_params* params, int H, int W, gbm3d_global_params& p) {
+  gbm3d_global_default_params(&p);
+  if (params) {
+    if (params->struct_size != sizeof(gbm3d_global_params))
+      return fail(ctx, GBM3D_EINVAL, "gbm3d_global_params.struct_size %u != %zu", params->struct_size,
+                  sizeof(gbm3d_global_params));
+    p = *params;
+  }
+  if (p.patch != 8 && p.patch != 16) return fail(ctx, GBM3D_EINVAL, "global patch %d must be 8 or 16", p.patch);
+  if (p.search < 3 || p.search > 39 || !(p.search & 1))
+    return fail(ctx, GBM3D_EINVAL, "global search %d must be odd in [3, 39]", p.search);
+  if (p.k != 8 && p.k != 16 && p.k != 32) return fail(ctx, GBM3D_EINVAL, "global k %d must be 8, 16 or 32", p.k);
+  if (p.k > p.search * p.search) return fail(ctx, GBM3D_EINVAL, "global k %d exceeds search^2", p.k);
+  if (p.levels < 1 || p.levels > 3 || (p.k >> p.levels) < 1)
+    return fail(ctx, GBM3D_EINVAL, "global levels %d must be in [1, 3] with k >= 2^levels", p.levels);
+  if (p.cycles < 1 || p.cycles > 4) return fail(ctx, GBM3D_EINVAL, "global cycles %d must be in [1, 4]", p.cycles);
+  if (p.n_shifts < 1 || p.n_shifts > 4)
+    return fail(ctx, GBM3D_EINVAL, "global n_shifts %d must be in [1, 4]", p.n_shifts);
+  for (int i = 0; i < p.n_shifts; ++i)
+    if (p.shifts[i] < 0 || p.shifts[i] >= p.patch)
+      return fail(ctx, GBM3D_EINVAL, "global shift %d must be in [0, patch)", p.shifts[i]);
+  if (!(p.ht_a >= 0.0f) || !(p.ht_b >= 0.0f) || !(p.tv_eps_rel > 0.0f))
+    return fail(ctx, GBM3D_EINVAL, "global thresholds and eps must be non-negative (eps > 0)");
+  const int lo = p.search > p.patch ? p.search : p.patch;
+  if (H < lo || W < lo || H > 32768 || W > 32768 || H % p.patch || W % p.patch)
+    return fail(ctx, GBM3D_EINVAL, "image %dx%d must be multiples of %d in [%d, 32768]", H, W, p.patch, lo);
+  return GBM3D_OK;
+}
+
+}  // namespace
+
+int gbm3d_global_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, const gbm3d_global_params* params,
+                       int16_t* idx, void* stream) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!img || !idx) return fail(ctx, GBM3D_EINVAL, "NULL image or index pointer");
+  gbm3d_global_params p;
+  CHECK(resolve_global(ctx, params, H, W, p));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  HIP_TRY(ctx, gbm3d::launch_global_match(img, H, W, p.patch, p.search, p.k, idx, static_cast<hipStream_t>(stream)),
+          "global matching launch");
+  return GBM3D_OK;
+}
+
+int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
+                       const gbm3d_global_params* params, float* out, void* stream) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!noisy || !out) return fail(ctx, GBM3D_EINVAL, "NULL image or output pointer");
+  CHECK(check_sigma(ctx, sigma));
+  gbm3d_global_params p;
+  CHECK(resolve_global(ctx, params, H, W, p));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  const size_t hw = static_cast<size_t>(H) * W;
+  const size_t vb = gbm3d::global_volume_bytes(H, W, p.k);
+  CHECK(ensure(ctx, ctx->gl_a, vb, "global volume"));
+  CHECK(ensure(ctx, ctx->gl_b, vb, "global volume"));
+  CHECK(ensure(ctx, ctx->gl_u, vb, "global volume"));
+  CHECK(ensure(ctx, ctx->gl_num, 2 * hw * sizeof(unsigned long long), "global sums"));
+  CHECK(ensure(ctx, ctx->gl_idx, (hw / (p.patch * p.patch)) * p.k * sizeof(int16_t), "global matches"));
+  CHECK(ensure(ctx, ctx->gl_shift, hw * sizeof(uint16_t), "translated image"));
+  gbm3d::GlobalJob j{};
+  j.noisy = noisy;
+  j.out = out;
+  j.H = H;
+  j.W = W;
+  j.sigma = sigma;
+  j.patch = p.patch;
+  j.search = p.search;
+  j.k = p.k;
+  j.levels = p.levels;
+  j.cycles = p.cycles;
+  j.n_shifts = p.n_shifts;
+  for (int i = 0; i < 4; ++i) j.shifts[i] = p.shifts[i];
+  j.ht_a = p.ht_a;
+  j.ht_b = p.ht_b;
+  j.tv_eps_rel = p.tv_eps_rel;
+  j.vol_a = static_cast<float*>(ctx->gl_a.p);
+  j.vol_b = static_cast<float*>(ctx->gl_b.p);
+  j.vol_u = static_cast<float*>(ctx->gl_u.p);
+  j.num = static_cast<unsigned long long*>(ctx->gl_num.p);
+  j.idx = static_cast<int16_t*>(ctx->gl_idx.p);
+  j.shifted = static_cast<uint16_t*>(ctx->gl_shift.p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, timed(ctx, "global_basic", st, [&] { return gbm3d::launch_global_basic(j, st); }),
+          "global stage 1 launch");
+  return GBM3D_OK;
 }
 
 int gbm3d_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int H, int W, float sigma,

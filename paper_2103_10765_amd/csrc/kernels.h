@@ -66,4 +66,27 @@ int reduce_items_for(int H, int W);
 
 hipError_t launch_quantize(const float* in, uint16_t* out, size_t n, hipStream_t st);
 
+// Global stage 1 (the volume form of Sec. 3): one image, every buffer on the
+// device.  vol_a, vol_b, vol_u: global_volume_bytes each; num: 2 H W
+// 64-bit words (numerators, then denominators); idx: (H/patch)(W/patch) k
+// int16; shifted: H W uint16 (used when a translation is not 0).
+struct GlobalJob {
+  const uint16_t* noisy;
+  float* out;
+  int H, W;
+  float sigma;
+  int patch, search, k, levels, cycles, n_shifts;
+  int shifts[4];
+  float ht_a, ht_b, tv_eps_rel;
+  float *vol_a, *vol_b, *vol_u;
+  unsigned long long* num;
+  int16_t* idx;
+  uint16_t* shifted;
+};
+size_t global_volume_bytes(int H, int W, int K);
+// the tile matching alone: idx [(H/patch)(W/patch)][k] displacement ranks
+hipError_t launch_global_match(const uint16_t* img, int H, int W, int patch, int search, int k, int16_t* idx,
+                               hipStream_t st);
+hipError_t launch_global_basic(const GlobalJob& job, hipStream_t st);
+
 }  // namespace gbm3d

@@ -51,6 +51,22 @@ class Image(ctypes.Structure):
     ]
 
 
+class GlobalParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("patch", ctypes.c_int32),
+        ("search", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("cycles", ctypes.c_int32),
+        ("n_shifts", ctypes.c_int32),
+        ("shifts", ctypes.c_int32 * 4),
+        ("ht_a", ctypes.c_float),
+        ("ht_b", ctypes.c_float),
+        ("tv_eps_rel", ctypes.c_float),
+    ]
+
+
 class GBM3DError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"gbm3d status {status}: {msg}")
@@ -92,6 +108,9 @@ _SIGNATURES = {
                             ctypes.POINTER(_F), _P]),
     "gbm3d_tune_save": (_I, [_P, ctypes.c_char_p]),
     "gbm3d_tune_load": (_I, [_P, ctypes.c_char_p]),
+    "gbm3d_global_default_params": (None, [ctypes.POINTER(GlobalParams)]),
+    "gbm3d_global_basic": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(GlobalParams), _P, _P]),
+    "gbm3d_global_match": (_I, [_P, _P, _I, _I, ctypes.POINTER(GlobalParams), _P, _P]),
 }
 
 
@@ -115,6 +134,23 @@ def default_params(**overrides) -> Params:
     p = Params()
     lib().gbm3d_default_params(ctypes.byref(p))
     for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def global_default_params(**overrides) -> GlobalParams:
+    """Global stage-1 parameters; `shifts` may be given as a sequence."""
+    p = GlobalParams()
+    lib().gbm3d_global_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k == "shifts":
+            v = list(v)
+            p.n_shifts = len(v)
+            for i in range(4):
+                p.shifts[i] = int(v[i]) if i < len(v) else 0
+            continue
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, v)
@@ -274,6 +310,26 @@ class Context:
         flags = (BATCH_GRAPH if graph else 0) | (BATCH_BASIC_ONLY if basic_only else 0)
         self._check(lib().gbm3d_denoise_batch(self._h, arr, n, self._params(params), flags, _stream(stream)))
         return outs
+
+    def global_basic(self, noisy: torch.Tensor, sigma: float, params: GlobalParams | None = None, out=None,
+                     stream=None):
+        """Global stage 1 (volume form) of a uint16 CUDA image."""
+        H, W = _hw(noisy)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=noisy.device)
+        p = params if params is not None else global_default_params()
+        self._check(lib().gbm3d_global_basic(self._h, _dev(noisy, torch.uint16, "noisy"), H, W, float(sigma),
+                                             ctypes.byref(p), _dev(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def global_match(self, img: torch.Tensor, params: GlobalParams | None = None, stream=None):
+        """Tile matching of the global stage 1: int16 [(H/patch)(W/patch), k]."""
+        H, W = _hw(img)
+        p = params if params is not None else global_default_params()
+        out = torch.empty(((H // p.patch) * (W // p.patch), p.k), dtype=torch.int16, device=img.device)
+        self._check(lib().gbm3d_global_match(self._h, _dev(img, torch.uint16, "img"), H, W, ctypes.byref(p),
+                                             _dev(out, torch.int16, "idx"), _stream(stream)))
+        return out
 
     # -- learned pilot -----------------------------------------------------
     def pilot_load(self, master: torch.Tensor, stream=None):
