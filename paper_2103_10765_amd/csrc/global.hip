@@ -59,25 +59,40 @@ __global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __
   }
   __syncthreads();
   const int S2 = S * S;
-  // exact squared distances: every difference squared and summed in float64
-  // (each term < 2^32, the sum < 2^42)
-  for (int r = threadIdx.x; r < 2048; r += blockDim.x) {
-    double key = kKeyInfG;
-    if (r < S2 && r != S2 / 2) {
-      const int dy = r / S, dx = r - dy * S;
-      double d = 0.0;
-      for (int a = 0; a < N; ++a) {
-        const int* rr = sm.reg + (R + a) * side + R;
-        const int* cr = sm.reg + (dy + a) * side + dx;
+  for (int r = S2 + threadIdx.x; r < 2048; r += blockDim.x) sm.keys[r] = kKeyInfG;
+  // exact squared distances, every difference squared and summed in float64
+  // (each term < 2^32, the sum < 2^42); a work item is one displacement row
+  // dy and four consecutive dx, so each reference pixel read from LDS serves
+  // four candidates
+  constexpr int kDx = 4;
+  const int groups = (S + kDx - 1) / kDx;
+  for (int item = threadIdx.x; item < S * groups; item += blockDim.x) {
+    const int dy = item / groups, dx0 = (item - dy * groups) * kDx;
+    double d[kDx] = {0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < N; ++a) {
+      const int* rr = sm.reg + (R + a) * side + R;
+      const int* cr = sm.reg + (dy + a) * side + dx0;
+      int seg[N + kDx - 1];
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-          const double t = static_cast<double>(rr[b] - cr[b]);
-          d = fma(t, t, d);
+      for (int b = 0; b < N + kDx - 1; ++b) seg[b] = dx0 + b < side ? cr[b] : 0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const int ref = rr[b];
+#pragma unroll
+        for (int c = 0; c < kDx; ++c) {
+          const double t = static_cast<double>(ref - seg[b + c]);
+          d[c] = fma(t, t, d[c]);
         }
       }
-      key = fma(d, 2048.0, static_cast<double>(r));
     }
-    sm.keys[r] = key;
+#pragma unroll
+    for (int c = 0; c < kDx; ++c) {
+      const int dx = dx0 + c;
+      if (dx < S) {
+        const int r = dy * S + dx;
+        sm.keys[r] = r == S2 / 2 ? kKeyInfG : fma(d[c], 2048.0, static_cast<double>(r));
+      }
+    }
   }
   __syncthreads();
   // ascending bitonic sort of the 2048 keys
@@ -113,6 +128,13 @@ __global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __
 // Elementwise kernels over the image and the volume V[k][y][x].
 // ---------------------------------------------------------------------------
 
+// index j (possibly a few periods out of range) folded into [0, L)
+__device__ __forceinline__ int wrap(int j, int L) {
+  while (j < 0) j += L;
+  while (j >= L) j -= L;
+  return j;
+}
+
 // out[y][x] = img[(y - t) mod H][(x - t) mod W]  (S_t of the image)
 __global__ void gl_roll_kernel(const uint16_t* __restrict__ img, int H, int W, int t, uint16_t* __restrict__ out) {
   const size_t n = static_cast<size_t>(H) * W;
@@ -126,22 +148,23 @@ __global__ void gl_roll_kernel(const uint16_t* __restrict__ img, int H, int W, i
 // V_h[k][y][x] = V[(k - h) mod K][(y - h) mod H][(x - h) mod W] with
 // V[k'][y'][x'] = z at the k'-th match of the tile holding (y', x'), offset
 // by (y', x') inside the tile.
+// grid of the volume kernels: (ceil(W / 256), H, K), thread = element (k, y, x)
 template <int N, int K>
-__global__ void gl_volume_kernel(const uint16_t* __restrict__ img, const int16_t* __restrict__ idx, int H, int W,
-                                 int S, int h, float* __restrict__ vol) {
-  const size_t hw = static_cast<size_t>(H) * W;
+__global__ __launch_bounds__(kGlThreads) void gl_volume_kernel(const uint16_t* __restrict__ img,
+                                                               const int16_t* __restrict__ idx, int H, int W, int S,
+                                                               int h, float* __restrict__ vol) {
+  const int x = blockIdx.x * kGlThreads + threadIdx.x;
+  if (x >= W) return;
+  const int y = blockIdx.y, k = blockIdx.z;
+  const size_t i = (static_cast<size_t>(k) * H + y) * W + x;
   const int R = S / 2;
   const int tiles_x = W / N;
-  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < K * hw;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int k = static_cast<int>(i / hw);
-    const size_t p = i - static_cast<size_t>(k) * hw;
-    const int y = static_cast<int>(p / W), x = static_cast<int>(p - static_cast<size_t>(y) * W);
-    const int ks = pmod(k - h, K), ys = pmod(y - h, H), xs = pmod(x - h, W);
+  {
+    const int ks = wrap(k - h, K), ys = wrap(y - h, H), xs = wrap(x - h, W);
     const int g = (ys / N) * tiles_x + xs / N;
     const int r = idx[static_cast<size_t>(g) * K + ks];
     const int dy = r / S - R, dx = r % S - R;
-    const uint16_t v = img[static_cast<size_t>(pmod(ys + dy, H)) * W + pmod(xs + dx, W)];
+    const uint16_t v = img[static_cast<size_t>(wrap(ys + dy, H)) * W + wrap(xs + dx, W)];
     vol[i] = static_cast<float>(v) * (1.0f / 65535.0f);
   }
 }
@@ -162,60 +185,58 @@ __device__ __forceinline__ float bior_hi_syn(int m) {
   return t[m + 4];
 }
 
-__global__ void gl_axis_kernel(const float* __restrict__ in, float* __restrict__ out, int H, int W, int Lk, int Ly,
-                               int Lx, int axis, int inverse) {
-  const size_t region = static_cast<size_t>(Lk) * Ly * Lx;
+// grid: (ceil(Lx / 256), Ly, Lk); thread = one output element (k, y, x)
+__global__ __launch_bounds__(kGlThreads) void gl_axis_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                                             int H, int W, int Lk, int Ly, int Lx, int axis,
+                                                             int inverse) {
+  const int x = blockIdx.x * kGlThreads + threadIdx.x;
+  if (x >= Lx) return;
+  const int y = blockIdx.y, k = blockIdx.z;
   const size_t hw = static_cast<size_t>(H) * W;
+  const size_t base = static_cast<size_t>(k) * hw + static_cast<size_t>(y) * W + x;
   const float c = 0.70710678118654752f;
-  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < region;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int k = static_cast<int>(i / (static_cast<size_t>(Ly) * Lx));
-    const int rem = static_cast<int>(i - static_cast<size_t>(k) * Ly * Lx);
-    const int y = rem / Lx, x = rem - (rem / Lx) * Lx;
-    const size_t base = static_cast<size_t>(k) * hw + static_cast<size_t>(y) * W + x;
-    int n, L;
-    size_t stride;
-    if (axis == 0) {
-      n = k, L = Lk, stride = hw;
-    } else if (axis == 1) {
-      n = y, L = Ly, stride = W;
-    } else {
-      n = x, L = Lx, stride = 1;
-    }
-    const float* line = in + (base - static_cast<size_t>(n) * stride);  // element 0 of this line
-    auto at = [&](int j) { return line[static_cast<size_t>(pmod(j, L)) * stride]; };
-    const int half = L / 2;
-    float v;
-    if (!inverse) {
-      if (axis == 0) {
-        const int m = n < half ? n : n - half;
-        const float e = at(2 * m), o = at(2 * m + 1);
-        v = n < half ? (e + o) * c : (e - o) * c;
-      } else if (n < half) {
-        v = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 10; ++t) v = fmaf(bior_lo_tap(t), at(2 * n + t - 4), v);
-      } else {
-        const int m = n - half;
-        v = (at(2 * m + 1) - at(2 * m)) * c;
-      }
-    } else {
-      // input: a[0 .. half) then d[0 .. half)
-      if (axis == 0) {
-        const int m = n >> 1;
-        const float a = at(m), d = at(half + m);
-        v = (n & 1) ? (a - d) * c : (a + d) * c;
-      } else {
-        v = c * at(n >> 1);
-        // details d[q] with 2q + m = n (mod L), m = -4 .. 5 of the parity of n
-#pragma unroll
-        for (int m = -4; m <= 5; ++m) {
-          if (((n - m) & 1) == 0) v = fmaf(bior_hi_syn(m), at(half + pmod((n - m) / 2, half)), v);
-        }
-      }
-    }
-    out[base] = v;
+  int n, L;
+  size_t stride;
+  if (axis == 0) {
+    n = k, L = Lk, stride = hw;
+  } else if (axis == 1) {
+    n = y, L = Ly, stride = W;
+  } else {
+    n = x, L = Lx, stride = 1;
   }
+  const float* line = in + (base - static_cast<size_t>(n) * stride);  // element 0 of this line
+  auto at = [&](int j) { return line[static_cast<size_t>(wrap(j, L)) * stride]; };
+  const int half = L / 2;
+  float v;
+  if (!inverse) {
+    if (axis == 0) {
+      const int m = n < half ? n : n - half;
+      const float e = at(2 * m), o = at(2 * m + 1);
+      v = n < half ? (e + o) * c : (e - o) * c;
+    } else if (n < half) {
+      v = 0.0f;
+#pragma unroll
+      for (int t = 0; t < 10; ++t) v = fmaf(bior_lo_tap(t), at(2 * n + t - 4), v);
+    } else {
+      const int m = n - half;
+      v = (at(2 * m + 1) - at(2 * m)) * c;
+    }
+  } else {
+    // input: a[0 .. half) then d[0 .. half)
+    if (axis == 0) {
+      const int m = n >> 1;
+      const float a = at(m), d = at(half + m);
+      v = (n & 1) ? (a - d) * c : (a + d) * c;
+    } else {
+      v = c * at(n >> 1);
+      // details d[q] with 2q + m = n (mod L), m = -4 .. 5 of the parity of n
+#pragma unroll
+      for (int m = -4; m <= 5; ++m) {
+        if (((n - m) & 1) == 0) v = fmaf(bior_hi_syn(m), at(half + wrap((n - m) / 2, half)), v);
+      }
+    }
+  }
+  out[base] = v;
 }
 
 __global__ void gl_copy_region_kernel(const float* __restrict__ from, float* __restrict__ to, int H, int W, int Lk,
@@ -234,14 +255,13 @@ __global__ void gl_copy_region_kernel(const float* __restrict__ from, float* __r
 // hard threshold by band level: level l >= 1 of a detail band is the first
 // level whose low-low-low region excludes the coefficient; the final
 // approximation (inside the region of every level) is kept
-__global__ void gl_threshold_kernel(float* __restrict__ vol, int K, int H, int W, int levels, float sigma, float a,
-                                    float b) {
-  const size_t hw = static_cast<size_t>(H) * W;
-  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < K * hw;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int k = static_cast<int>(i / hw);
-    const size_t p = i - static_cast<size_t>(k) * hw;
-    const int y = static_cast<int>(p / W), x = static_cast<int>(p - static_cast<size_t>(y) * W);
+__global__ __launch_bounds__(kGlThreads) void gl_threshold_kernel(float* __restrict__ vol, int K, int H, int W,
+                                                                  int levels, float sigma, float a, float b) {
+  const int x = blockIdx.x * kGlThreads + threadIdx.x;
+  if (x >= W) return;
+  const int y = blockIdx.y, k = blockIdx.z;
+  const size_t i = (static_cast<size_t>(k) * H + y) * W + x;
+  {
     int lev = 0;
     for (int j = 1; j <= levels; ++j)
       if (k >= (K >> j) || y >= (H >> j) || x >= (W >> j)) {
@@ -256,16 +276,17 @@ __global__ void gl_threshold_kernel(float* __restrict__ vol, int K, int H, int W
 }
 
 // acc (=|+=) scale * src[(k + h) mod K][(y + h) mod H][(x + h) mod W]  (S_{-h})
-__global__ void gl_unspin_kernel(const float* __restrict__ src, float* __restrict__ acc, int K, int H, int W, int h,
-                                 int first, float scale) {
-  const size_t hw = static_cast<size_t>(H) * W;
-  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < K * hw;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int k = static_cast<int>(i / hw);
-    const size_t p = i - static_cast<size_t>(k) * hw;
-    const int y = static_cast<int>(p / W), x = static_cast<int>(p - static_cast<size_t>(y) * W);
-    const float v = scale * src[static_cast<size_t>(pmod(k + h, K)) * hw + static_cast<size_t>(pmod(y + h, H)) * W +
-                                pmod(x + h, W)];
+__global__ __launch_bounds__(kGlThreads) void gl_unspin_kernel(const float* __restrict__ src,
+                                                               float* __restrict__ acc, int K, int H, int W, int h,
+                                                               int first, float scale) {
+  const int x = blockIdx.x * kGlThreads + threadIdx.x;
+  if (x >= W) return;
+  const int y = blockIdx.y, k = blockIdx.z;
+  const size_t i = (static_cast<size_t>(k) * H + y) * W + x;
+  {
+    const size_t hw = static_cast<size_t>(H) * W;
+    const float v = scale * src[static_cast<size_t>(wrap(k + h, K)) * hw + static_cast<size_t>(wrap(y + h, H)) * W +
+                                wrap(x + h, W)];
     acc[i] = first ? v : acc[i] + v;
   }
 }
@@ -350,7 +371,7 @@ template <int N, int K>
 hipError_t global_nk(const GlobalJob& j, hipStream_t st) {
   const int H = j.H, W = j.W;
   const size_t hw = static_cast<size_t>(H) * W;
-  const size_t vol_n = static_cast<size_t>(K) * hw;
+  const dim3 vol_grid((W + kGlThreads - 1) / kGlThreads, H, K);
   const int tiles = (H / N) * (W / N);
   const float eps = j.tv_eps_rel * j.sigma * static_cast<float>(N * N * K);
   for (int ti = 0; ti < j.n_shifts; ++ti) {
@@ -364,38 +385,40 @@ hipError_t global_nk(const GlobalJob& j, hipStream_t st) {
     for (int h = 0; h < j.cycles; ++h) {
       float* A = j.vol_a;
       float* B = j.vol_b;
-      hipLaunchKernelGGL((gl_volume_kernel<N, K>), dim3(grid_for(vol_n)), dim3(kGlThreads), 0, st, img, j.idx, H, W,
-                         j.search, h, A);
+      hipLaunchKernelGGL((gl_volume_kernel<N, K>), vol_grid, dim3(kGlThreads), 0, st, img, j.idx, H, W, j.search, h,
+                         A);
       // forward: level 0 ends in B; every coarser level ends in A and its
       // region is copied back into B
       for (int l = 0; l < j.levels; ++l) {
         const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
         const size_t rn = static_cast<size_t>(Lk) * Ly * Lx;
+        const dim3 axis_grid((Lx + kGlThreads - 1) / kGlThreads, Ly, Lk);
         float* s0 = l == 0 ? A : B;
         float* s1 = l == 0 ? B : A;
-        hipLaunchKernelGGL(gl_axis_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, s0, s1, H, W, Lk, Ly, Lx, 1, 0);
-        hipLaunchKernelGGL(gl_axis_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, s1, s0, H, W, Lk, Ly, Lx, 2, 0);
-        hipLaunchKernelGGL(gl_axis_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, s0, s1, H, W, Lk, Ly, Lx, 0, 0);
+        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, s0, s1, H, W, Lk, Ly, Lx, 1, 0);
+        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, s1, s0, H, W, Lk, Ly, Lx, 2, 0);
+        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, s0, s1, H, W, Lk, Ly, Lx, 0, 0);
         if (l > 0)
           hipLaunchKernelGGL(gl_copy_region_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, A, B, H, W, Lk, Ly,
                              Lx);
       }
-      hipLaunchKernelGGL(gl_threshold_kernel, dim3(grid_for(vol_n)), dim3(kGlThreads), 0, st, B, K, H, W, j.levels,
-                         j.sigma, j.ht_a, j.ht_b);
+      hipLaunchKernelGGL(gl_threshold_kernel, vol_grid, dim3(kGlThreads), 0, st, B, K, H, W, j.levels, j.sigma, j.ht_a,
+                         j.ht_b);
       // inverse, coarsest level first: each level reads B and ends in A; all
       // but the finest copy their region back into B
       for (int l = j.levels - 1; l >= 0; --l) {
         const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
         const size_t rn = static_cast<size_t>(Lk) * Ly * Lx;
-        hipLaunchKernelGGL(gl_axis_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, B, A, H, W, Lk, Ly, Lx, 0, 1);
-        hipLaunchKernelGGL(gl_axis_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, A, B, H, W, Lk, Ly, Lx, 2, 1);
-        hipLaunchKernelGGL(gl_axis_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, B, A, H, W, Lk, Ly, Lx, 1, 1);
+        const dim3 axis_grid((Lx + kGlThreads - 1) / kGlThreads, Ly, Lk);
+        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, B, A, H, W, Lk, Ly, Lx, 0, 1);
+        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, A, B, H, W, Lk, Ly, Lx, 2, 1);
+        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, B, A, H, W, Lk, Ly, Lx, 1, 1);
         if (l > 0)
           hipLaunchKernelGGL(gl_copy_region_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, A, B, H, W, Lk, Ly,
                              Lx);
       }
-      hipLaunchKernelGGL(gl_unspin_kernel, dim3(grid_for(vol_n)), dim3(kGlThreads), 0, st, A, j.vol_u, K, H, W, h,
-                         h == 0 ? 1 : 0, 1.0f / static_cast<float>(j.cycles));
+      hipLaunchKernelGGL(gl_unspin_kernel, vol_grid, dim3(kGlThreads), 0, st, A, j.vol_u, K, H, W, h, h == 0 ? 1 : 0,
+                         1.0f / static_cast<float>(j.cycles));
     }
     hipLaunchKernelGGL(gl_zero_kernel, dim3(grid_for(2 * hw)), dim3(kGlThreads), 0, st, j.num, 2 * hw);
     hipLaunchKernelGGL((gl_aggregate_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, j.vol_u, j.idx, H, W,
