@@ -317,6 +317,8 @@ def main():
                     help="only run one plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="only time the 64-image batch under graph replay (for profiling the batch path)")
+    ap.add_argument("--global-only", action="store_true",
+                    help="only time the volume form of stage 1 beside the grouped stage 1 (for profiling it)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -325,6 +327,15 @@ def main():
         from paper_2103_10765_amd import gbm3d
         ctx = gbm3d.Context(0)
         print(json.dumps(batch_bench(ctx, reps=args.steps)), flush=True)
+        ctx.close()
+        return
+    if args.global_only:
+        import torch
+        from paper_2103_10765_amd import gbm3d, synth
+        sigma = args.sigma / 255.0
+        clean, Z = synth.make_case(args.size, args.size, sigma, 2)
+        ctx = gbm3d.Context(0)
+        print(json.dumps(global_bench(ctx, torch.from_numpy(Z).cuda(), clean, sigma, steps=args.steps)), flush=True)
         ctx.close()
         return
     if args.gpus != 1:

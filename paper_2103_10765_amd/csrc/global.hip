@@ -40,7 +40,7 @@ template <int N>
 struct TileSmem {
   static constexpr int kRegion = kMaxSearch + N - 1;
   int reg[kRegion * kRegion];  // search region, pixel values
-  double keys[2048];           // dist * 2048 + rank, padded with +inf
+  double keys[kMaxSearch * kMaxSearch];  // dist * 2048 + rank (+inf for the reference)
 };
 
 template <int N, int K>
@@ -59,7 +59,6 @@ __global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __
   }
   __syncthreads();
   const int S2 = S * S;
-  for (int r = S2 + threadIdx.x; r < 2048; r += blockDim.x) sm.keys[r] = kKeyInfG;
   // exact squared distances, every difference squared and summed in float64
   // (each term < 2^32, the sum < 2^42); a work item is one displacement row
   // dy and four consecutive dx, so each reference pixel read from LDS serves
@@ -95,32 +94,60 @@ __global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __
     }
   }
   __syncthreads();
-  // ascending bitonic sort of the 2048 keys
-  for (int k = 2; k <= 2048; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
-        const int l = i ^ j;
-        if (l > i) {
-          const double a = sm.keys[i], b = sm.keys[l];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            sm.keys[i] = b;
-            sm.keys[l] = a;
-          }
-        }
+  // the K-1 smallest keys (keys are unique): every wave takes its K-1
+  // smallest by repeated wave minima over its lanes' keys, then wave 0 does
+  // the same over the four waves' lists
+  constexpr int kPer = (kMaxSearch * kMaxSearch + kGlThreads - 1) / kGlThreads;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  double mine[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int r = threadIdx.x + m * kGlThreads;
+    mine[m] = r < S2 ? sm.keys[r] : kKeyInfG;
+  }
+  auto wave_min = [](double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const int lo = __shfl_xor(__double2loint(v), off, kWave), hi = __shfl_xor(__double2hiint(v), off, kWave);
+      v = fmin(v, __hiloint2double(hi, lo));
+    }
+    return v;
+  };
+  auto take_smallest = [&](double (&vals)[kPer], int count, double* dst) {
+    for (int s = 0; s < count; ++s) {
+      double cur = vals[0];
+#pragma unroll
+      for (int m = 1; m < kPer; ++m) cur = fmin(cur, vals[m]);
+      const double best = wave_min(cur);
+      if (lane == 0) dst[s] = best;
+#pragma unroll
+      for (int m = 0; m < kPer; ++m)
+        if (vals[m] == best) vals[m] = kKeyInfG;
+    }
+  };
+  __syncthreads();  // every key has been read; the key array is reused below
+  double* wtop = sm.keys;                  // [4][K - 1]
+  take_smallest(mine, K - 1, wtop + wave * (K - 1));
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int c = lane + m * kWave;
+      mine[m] = c < 4 * (K - 1) ? wtop[c] : kKeyInfG;
+    }
+    double* top = sm.keys + 4 * (K - 1);   // [K - 1], ascending
+    take_smallest(mine, K - 1, top);
+    wave_lds_sync();  // lane 0's writes of `top` are visible to the wave
+    if (lane < K) {
+      int16_t rank;
+      if (lane == 0) {
+        rank = static_cast<int16_t>(S2 / 2);
+      } else {
+        const double key = top[lane - 1];
+        rank = static_cast<int16_t>(key - 2048.0 * floor(key * (1.0 / 2048.0)));
       }
-      __syncthreads();
+      idx[static_cast<size_t>(g) * K + lane] = rank;
     }
-  if (threadIdx.x < K) {
-    const int s = threadIdx.x;
-    int16_t rank;
-    if (s == 0) {
-      rank = static_cast<int16_t>(S2 / 2);
-    } else {
-      const double key = sm.keys[s - 1];
-      rank = static_cast<int16_t>(key - 2048.0 * floor(key * (1.0 / 2048.0)));
-    }
-    idx[static_cast<size_t>(g) * K + s] = rank;
   }
 }
 
@@ -300,18 +327,29 @@ __global__ void gl_zero_kernel(unsigned long long* __restrict__ p, size_t n) {
 // One workgroup per tile: w = eps / (TV(u) + eps) (the 1 / (TV + eps) weight
 // scaled by eps, which cancels in the average), then every filtered block is
 // added at its source position: num += w u, den += w (64-bit fixed point).
+// The K blocks all lie in the tile's (S + N - 1)^2 search footprint, which
+// is summed in LDS first; only its covered cells go to the image with global
+// integer atomics.
 template <int N, int K>
-__global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* __restrict__ u, const int16_t* __restrict__ idx,
-                                                               int H, int W, int S, float eps,
-                                                               unsigned long long* __restrict__ num,
-                                                               unsigned long long* __restrict__ den) {
+__global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* __restrict__ u,
+                                                                   const int16_t* __restrict__ idx, int H, int W,
+                                                                   int S, float eps,
+                                                                   unsigned long long* __restrict__ num,
+                                                                   unsigned long long* __restrict__ den) {
   constexpr int kVals = N * N * K;
+  constexpr int kFoot = (kMaxSearch + N - 1) * (kMaxSearch + N - 1);
   __shared__ float blk[kVals];
   __shared__ double part[kGlThreads];
+  __shared__ unsigned long long fnum[kFoot], fden[kFoot];
   const size_t hw = static_cast<size_t>(H) * W;
   const int tiles_x = W / N;
   const int g = blockIdx.x;
   const int y0 = (g / tiles_x) * N, x0 = (g % tiles_x) * N;
+  const int side = S + N - 1;
+  for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
+    fnum[i] = 0;
+    fden[i] = 0;
+  }
   for (int i = threadIdx.x; i < kVals; i += blockDim.x) {
     const int k = i / (N * N), a = (i / N) % N, b = i % N;
     blk[i] = u[static_cast<size_t>(k) * hw + static_cast<size_t>(y0 + a) * W + x0 + b];
@@ -335,15 +373,21 @@ __global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* _
   }
   const float w = eps / (static_cast<float>(part[0]) + eps);
   const unsigned long long wf = static_cast<unsigned long long>(to_fixed(w));
-  const int R = S / 2;
   for (int i = threadIdx.x; i < kVals; i += blockDim.x) {
     const int k = i / (N * N), a = (i / N) % N, b = i % N;
     const int r = idx[static_cast<size_t>(g) * K + k];
-    const int y = pmod(y0 + r / S - R + a, H), x = pmod(x0 + r % S - R + b, W);
-    const size_t o = static_cast<size_t>(y) * W + x;
-    __hip_atomic_fetch_add(num + o, static_cast<unsigned long long>(to_fixed(w * blk[i])), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(den + o, wf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int f = (r / S + a) * side + r % S + b;  // footprint cell of (dy + R + a, dx + R + b)
+    atomicAdd(fnum + f, static_cast<unsigned long long>(to_fixed(w * blk[i])));
+    atomicAdd(fden + f, wf);
+  }
+  __syncthreads();
+  const int R = S / 2;
+  for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
+    if (fden[i] == 0) continue;
+    const int fy = i / side, fx = i - fy * side;
+    const size_t o = static_cast<size_t>(wrap(y0 - R + fy, H)) * W + wrap(x0 - R + fx, W);
+    __hip_atomic_fetch_add(num + o, fnum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(den + o, fden[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
