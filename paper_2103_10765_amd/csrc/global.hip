@@ -14,12 +14,12 @@
 // normalised estimate is averaged over translations of the image
 // (eq. firstEst).
 //
-// The transform runs as one kernel per axis and level over the active
-// sub-volume, out of place between two volume buffers (each output element
-// reads its <= 10 periodic inputs along the axis; consecutive threads take
-// consecutive x, so every axis is read and written coalesced).  Three passes
-// per level change buffers, so after each coarser level the level's region is
-// copied back next to the finer bands.
+// The transform runs one kernel per level: a workgroup loads a window of
+// two k-slices into LDS and does the Haar pair along k and the bior1.5
+// filters along x and y there, writing the eight bands of its coefficient
+// tile (thresholded, but for the low-low-low band).  Level 0 gathers the
+// spun volume straight from the image, and the finest inverse level writes
+// the average over the cycle spins, so the volume itself is never stored.
 #include <cstdint>
 
 #include "common.h"
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __
 }
 
 // ---------------------------------------------------------------------------
-// Elementwise kernels over the image and the volume V[k][y][x].
+// The volume V[k][y][x] and its periodic 3-D Mallat levels.
 // ---------------------------------------------------------------------------
 
 // index j (possibly a few periods out of range) folded into [0, L)
@@ -172,149 +172,283 @@ __global__ void gl_roll_kernel(const uint16_t* __restrict__ img, int H, int W, i
   }
 }
 
-// V_h[k][y][x] = V[(k - h) mod K][(y - h) mod H][(x - h) mod W] with
-// V[k'][y'][x'] = z at the k'-th match of the tile holding (y', x'), offset
-// by (y', x') inside the tile.
-// grid of the volume kernels: (ceil(W / 256), H, K), thread = element (k, y, x)
-template <int N, int K>
-__global__ __launch_bounds__(kGlThreads) void gl_volume_kernel(const uint16_t* __restrict__ img,
-                                                               const int16_t* __restrict__ idx, int H, int W, int S,
-                                                               int h, float* __restrict__ vol) {
-  const int x = blockIdx.x * kGlThreads + threadIdx.x;
-  if (x >= W) return;
-  const int y = blockIdx.y, k = blockIdx.z;
-  const size_t i = (static_cast<size_t>(k) * H + y) * W + x;
-  const int R = S / 2;
-  const int tiles_x = W / N;
-  {
-    const int ks = wrap(k - h, K), ys = wrap(y - h, H), xs = wrap(x - h, W);
-    const int g = (ys / N) * tiles_x + xs / N;
-    const int r = idx[static_cast<size_t>(g) * K + ks];
-    const int dy = r / S - R, dx = r % S - R;
-    const uint16_t v = img[static_cast<size_t>(wrap(ys + dy, H)) * W + wrap(xs + dx, W)];
-    vol[i] = static_cast<float>(v) * (1.0f / 65535.0f);
-  }
-}
-
-// One periodic level along one axis of the region [0, Lk) x [0, Ly) x [0, Lx)
-// of a K x H x W volume: analysis (bior1.5 on y / x: low-pass a[n] = sum_i
-// h_i x[2n + i - 4], details (x[2n+1] - x[2n]) / sqrt2; Haar on k: sums and
-// differences over sqrt2) or its inverse.  Axis 0 = k, 1 = y, 2 = x.
+// bior1.5 analysis low-pass: a[n] = sum_i h_i x[2n + i - 4]; the analysis
+// high-pass is the Haar difference d[n] = (x[2n+1] - x[2n]) / sqrt2
 __device__ __forceinline__ float bior_lo_tap(int i) {
   constexpr float s = 1.41421356237309505f / 256.0f;
   constexpr float t[10] = {3 * s, -3 * s, -22 * s, 22 * s, 128 * s, 128 * s, 22 * s, -22 * s, -3 * s, 3 * s};
   return t[i];
 }
-// coefficient of detail d[n] in x[2n + m], m = -4 .. 5
-__device__ __forceinline__ float bior_hi_syn(int m) {
+// synthesis: x[n] = a[n >> 1] / sqrt2 + sum_m g_m d[(n - m) / 2] over
+// m = -4 .. 5 with n - m even; syn_even(i) = g_{4 - 2i} multiplies
+// d[n/2 - 2 + i] for even n, syn_odd(i) = g_{5 - 2i} multiplies
+// d[(n-1)/2 - 2 + i] for odd n (i = 0 .. 4)
+__device__ __forceinline__ float bior_syn_even(int i) {
   constexpr float s = 1.41421356237309505f / 256.0f;
-  constexpr float t[10] = {-3 * s, -3 * s, 22 * s, 22 * s, -128 * s, 128 * s, -22 * s, -22 * s, 3 * s, 3 * s};
-  return t[m + 4];
+  constexpr float t[5] = {3 * s, -22 * s, -128 * s, 22 * s, -3 * s};
+  return t[i];
+}
+__device__ __forceinline__ float bior_syn_odd(int i) {
+  constexpr float s = 1.41421356237309505f / 256.0f;
+  constexpr float t[5] = {3 * s, -22 * s, 128 * s, 22 * s, -3 * s};
+  return t[i];
 }
 
-// grid: (ceil(Lx / 256), Ly, Lk); thread = one output element (k, y, x)
-__global__ __launch_bounds__(kGlThreads) void gl_axis_kernel(const float* __restrict__ in, float* __restrict__ out,
-                                                             int H, int W, int Lk, int Ly, int Lx, int axis,
-                                                             int inverse) {
-  const int x = blockIdx.x * kGlThreads + threadIdx.x;
-  if (x >= Lx) return;
-  const int y = blockIdx.y, k = blockIdx.z;
+__device__ __forceinline__ float hard_threshold(float v, float tau) { return fabsf(v) >= tau ? v : 0.0f; }
+
+// j folded into [0, L) when it lies within one period of it
+__device__ __forceinline__ int wrap1(int j, int L) { return j < 0 ? j + L : (j >= L ? j - L : j); }
+
+// Coefficient tiles of a workgroup: TY x TX per band of y and x, one pair of
+// slices along k.  The finest level takes 16 x 32; the coarser levels, whose
+// regions are 8 and 64 times smaller, take 8 x 16 to keep enough workgroups.
+template <int TY, int TX>
+struct LevelTile {
+  static constexpr int kFwdRows = 2 * TY + 8, kFwdCols = 2 * TX + 8;  // forward input window
+  static constexpr int kInvRows = 2 * TY + 4, kInvCols = 2 * TX + 4;  // inverse input window
+  static constexpr int kFwdIters = (kFwdRows * kFwdCols + kGlThreads - 1) / kGlThreads;
+  static constexpr int kInvIters = (kInvRows * kInvCols + kGlThreads - 1) / kGlThreads;
+};
+
+// One forward level over the region [0, Lk) x [0, Ly) x [0, Lx) of a
+// K x H x W volume, all three axes in one pass: Haar along k (sums and
+// differences over sqrt2), then bior1.5 along x and along y, all periodic
+// within the region.  Output bands go to their Mallat positions (low half /
+// high half of each axis) in dst; every band but low-low-low is hard
+// thresholded with tau.  With GATHER the input is the spun volume V_h,
+// gathered from the image through the matches, instead of src.
+// grid: (ceil(Lx / 2 / TX), ceil(Ly / 2 / TY), Lk / 2)
+template <int N, int K, bool GATHER, int TY, int TX>
+__global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __restrict__ src,
+                                                                 const uint16_t* __restrict__ img,
+                                                                 const int16_t* __restrict__ idx, int S, int h,
+                                                                 float* __restrict__ dst, int H, int W, int Lk, int Ly,
+                                                                 int Lx, float tau) {
+  using T = LevelTile<TY, TX>;
+  // input window: rows 2 cy0 - 4 .. 2 cy0 + 2 TY + 3, the same for columns;
+  // columns stored split by parity so the strided filter taps read
+  // consecutive LDS words
+  constexpr int kRows = T::kFwdRows, kCols = T::kFwdCols, kHalfCols = kCols / 2;
+  __shared__ float in_s[2][kRows][2][kHalfCols];
+  __shared__ float xs[2][kRows][2 * TX];
+  // per window row / column: the (unspun) volume coordinate, and with GATHER
+  // the tile offset of the spun coordinate
+  __shared__ int row_at[kRows], col_at[kCols], row_tile[GATHER ? kRows : 1], col_tile[GATHER ? kCols : 1];
+  const int hy = Ly >> 1, hx = Lx >> 1, hk = Lk >> 1;
+  const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY, kp = blockIdx.z;
   const size_t hw = static_cast<size_t>(H) * W;
-  const size_t base = static_cast<size_t>(k) * hw + static_cast<size_t>(y) * W + x;
   const float c = 0.70710678118654752f;
-  int n, L;
-  size_t stride;
-  if (axis == 0) {
-    n = k, L = Lk, stride = hw;
-  } else if (axis == 1) {
-    n = y, L = Ly, stride = W;
-  } else {
-    n = x, L = Lx, stride = 1;
-  }
-  const float* line = in + (base - static_cast<size_t>(n) * stride);  // element 0 of this line
-  auto at = [&](int j) { return line[static_cast<size_t>(wrap(j, L)) * stride]; };
-  const int half = L / 2;
-  float v;
-  if (!inverse) {
-    if (axis == 0) {
-      const int m = n < half ? n : n - half;
-      const float e = at(2 * m), o = at(2 * m + 1);
-      v = n < half ? (e + o) * c : (e - o) * c;
-    } else if (n < half) {
-      v = 0.0f;
-#pragma unroll
-      for (int t = 0; t < 10; ++t) v = fmaf(bior_lo_tap(t), at(2 * n + t - 4), v);
+  const int tid = threadIdx.x;
+  if (tid < kRows) {
+    const int y = wrap(2 * cy0 - 4 + tid, Ly);
+    if constexpr (GATHER) {
+      const int ys = wrap1(y - h, H);
+      row_at[tid] = ys;
+      row_tile[tid] = (ys / N) * (W / N);
     } else {
-      const int m = n - half;
-      v = (at(2 * m + 1) - at(2 * m)) * c;
+      row_at[tid] = y;
+    }
+  } else if (tid < kRows + kCols) {
+    const int x = wrap(2 * cx0 - 4 + tid - kRows, Lx);
+    if constexpr (GATHER) {
+      const int xs = wrap1(x - h, W);
+      col_at[tid - kRows] = xs;
+      col_tile[tid - kRows] = xs / N;
+    } else {
+      col_at[tid - kRows] = x;
+    }
+  }
+  __syncthreads();
+  float v0[T::kFwdIters], v1[T::kFwdIters];
+  if constexpr (GATHER) {
+    // V[k'][ys][xs] = z at (ys, xs) + the k'-th match displacement of its tile
+    const int R = S / 2;
+    const float inv_s = 1.0f / static_cast<float>(S);
+    const int16_t* idx0 = idx + wrap1(2 * kp - h, K);
+    const int16_t* idx1 = idx + wrap1(2 * kp + 1 - h, K);
+    int r0[T::kFwdIters], r1[T::kFwdIters];
+#pragma unroll
+    for (int it = 0; it < T::kFwdIters; ++it) {
+      const int e = tid + it * kGlThreads;
+      if (e < kRows * kCols) {
+        const int r = e / kCols, col = e - r * kCols;
+        const size_t g = static_cast<size_t>(row_tile[r] + col_tile[col]) * K;
+        r0[it] = idx0[g];
+        r1[it] = idx1[g];
+      }
+    }
+    auto pixel = [&](int rank, int ys, int xs) {
+      const int q = static_cast<int>((static_cast<float>(rank) + 0.5f) * inv_s);  // rank / S, exact for rank < S^2
+      const int y = wrap1(ys + q - R, H), x = wrap1(xs + (rank - q * S) - R, W);
+      return static_cast<float>(img[static_cast<size_t>(y) * W + x]) * (1.0f / 65535.0f);
+    };
+#pragma unroll
+    for (int it = 0; it < T::kFwdIters; ++it) {
+      const int e = tid + it * kGlThreads;
+      if (e < kRows * kCols) {
+        const int r = e / kCols, col = e - r * kCols;
+        v0[it] = pixel(r0[it], row_at[r], col_at[col]);
+        v1[it] = pixel(r1[it], row_at[r], col_at[col]);
+      }
     }
   } else {
-    // input: a[0 .. half) then d[0 .. half)
-    if (axis == 0) {
-      const int m = n >> 1;
-      const float a = at(m), d = at(half + m);
-      v = (n & 1) ? (a - d) * c : (a + d) * c;
-    } else {
-      v = c * at(n >> 1);
-      // details d[q] with 2q + m = n (mod L), m = -4 .. 5 of the parity of n
+    const float* s0 = src + static_cast<size_t>(2 * kp) * hw;
+    const float* s1 = s0 + hw;
 #pragma unroll
-      for (int m = -4; m <= 5; ++m) {
-        if (((n - m) & 1) == 0) v = fmaf(bior_hi_syn(m), at(half + wrap((n - m) / 2, half)), v);
+    for (int it = 0; it < T::kFwdIters; ++it) {
+      const int e = tid + it * kGlThreads;
+      if (e < kRows * kCols) {
+        const int r = e / kCols, col = e - r * kCols;
+        const size_t o = static_cast<size_t>(row_at[r]) * W + col_at[col];
+        v0[it] = s0[o];
+        v1[it] = s1[o];
       }
     }
   }
-  out[base] = v;
+#pragma unroll
+  for (int it = 0; it < T::kFwdIters; ++it) {
+    const int e = tid + it * kGlThreads;
+    if (e < kRows * kCols) {
+      const int r = e / kCols, col = e - r * kCols;
+      in_s[0][r][col & 1][col >> 1] = (v0[it] + v1[it]) * c;
+      in_s[1][r][col & 1][col >> 1] = (v0[it] - v1[it]) * c;
+    }
+  }
+  __syncthreads();
+  // along x: window column 2 j + i is even[j + i/2] or odd[j + (i-1)/2]
+  for (int e = tid; e < 2 * kRows * TX; e += kGlThreads) {
+    const int j = e % TX, r = (e / TX) % kRows, kb = e / (TX * kRows);
+    const float* ev = in_s[kb][r][0];
+    const float* od = in_s[kb][r][1];
+    float lo = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      lo = fmaf(bior_lo_tap(2 * u), ev[j + u], lo);
+      lo = fmaf(bior_lo_tap(2 * u + 1), od[j + u], lo);
+    }
+    xs[kb][r][j] = lo;
+    xs[kb][r][TX + j] = (od[j + 2] - ev[j + 2]) * c;
+  }
+  __syncthreads();
+  // along y, then out to the bands
+  for (int e = tid; e < 2 * TY * 2 * TX; e += kGlThreads) {
+    const int cc = e % (2 * TX), i = (e / (2 * TX)) % TY, kb = e / (2 * TX * TY);
+    const int xb = cc >= TX ? 1 : 0;
+    const int cy = cy0 + i, cx = cx0 + cc - xb * TX;
+    if (cy >= hy || cx >= hx) continue;
+    float lo = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 10; ++t) lo = fmaf(bior_lo_tap(t), xs[kb][2 * i + t][cc], lo);
+    const float hi = hard_threshold((xs[kb][2 * i + 5][cc] - xs[kb][2 * i + 4][cc]) * c, tau);
+    if (kb | xb) lo = hard_threshold(lo, tau);
+    float* o = dst + static_cast<size_t>(kb ? hk + kp : kp) * hw + (xb ? hx + cx : cx);
+    o[static_cast<size_t>(cy) * W] = lo;
+    o[static_cast<size_t>(hy + cy) * W] = hi;
+  }
 }
 
-__global__ void gl_copy_region_kernel(const float* __restrict__ from, float* __restrict__ to, int H, int W, int Lk,
-                                      int Ly, int Lx) {
-  const size_t region = static_cast<size_t>(Lk) * Ly * Lx;
+// The inverse of one level: src holds the level's eight bands at their
+// Mallat positions in the region; the workgroup rebuilds slices 2 kp, 2 kp + 1,
+// rows 2 cy0 .. 2 cy0 + 2 TY - 1 and columns 2 cx0 .. 2 cx0 + 2 TX - 1
+// (synthesis along x, then y, then the Haar pair along k).  Without UNSPIN the
+// result goes to the same positions of dst; with UNSPIN (the finest level,
+// region = volume) element (k, y, x) is scaled and stored (first) or added to
+// dst[(k - h) mod K][(y - h) mod H][(x - h) mod W], undoing the spin S_h.
+template <int K, bool UNSPIN, int TY, int TX>
+__global__ __launch_bounds__(kGlThreads) void gl_inverse_kernel(const float* __restrict__ src,
+                                                                 float* __restrict__ dst, int H, int W, int Lk, int Ly,
+                                                                 int Lx, int h, int first, float scale) {
+  using T = LevelTile<TY, TX>;
+  // window rows: low band cy0 .. cy0 + TY - 1, then high band cy0 - 2 ..
+  // cy0 + TY + 1 (the synthesis taps reach two coefficients either side);
+  // the same for columns
+  constexpr int kRows = T::kInvRows, kCols = T::kInvCols;
+  __shared__ float in_s[2][kRows][kCols];
+  __shared__ float xs[2][kRows][2 * TX];
+  __shared__ int row_at[kRows], col_at[kCols];
+  const int hy = Ly >> 1, hx = Lx >> 1, hk = Lk >> 1;
+  const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY, kp = blockIdx.z;
   const size_t hw = static_cast<size_t>(H) * W;
-  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < region;
-       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int k = static_cast<int>(i / (static_cast<size_t>(Ly) * Lx));
-    const int rem = static_cast<int>(i - static_cast<size_t>(k) * Ly * Lx);
-    const size_t o = static_cast<size_t>(k) * hw + static_cast<size_t>(rem / Lx) * W + rem % Lx;
-    to[o] = from[o];
+  const float c = 0.70710678118654752f;
+  const int tid = threadIdx.x;
+  if (tid < kRows) {
+    row_at[tid] = tid < TY ? wrap(cy0 + tid, hy) : hy + wrap(cy0 - 2 + tid - TY, hy);
+  } else if (tid < kRows + kCols) {
+    const int col = tid - kRows;
+    col_at[col] = col < TX ? wrap(cx0 + col, hx) : hx + wrap(cx0 - 2 + col - TX, hx);
   }
-}
-
-// hard threshold by band level: level l >= 1 of a detail band is the first
-// level whose low-low-low region excludes the coefficient; the final
-// approximation (inside the region of every level) is kept
-__global__ __launch_bounds__(kGlThreads) void gl_threshold_kernel(float* __restrict__ vol, int K, int H, int W,
-                                                                  int levels, float sigma, float a, float b) {
-  const int x = blockIdx.x * kGlThreads + threadIdx.x;
-  if (x >= W) return;
-  const int y = blockIdx.y, k = blockIdx.z;
-  const size_t i = (static_cast<size_t>(k) * H + y) * W + x;
+  __syncthreads();
   {
-    int lev = 0;
-    for (int j = 1; j <= levels; ++j)
-      if (k >= (K >> j) || y >= (H >> j) || x >= (W >> j)) {
-        lev = j;
-        break;
+    const float* s0 = src + static_cast<size_t>(kp) * hw;
+    const float* s1 = src + static_cast<size_t>(hk + kp) * hw;
+    float v0[T::kInvIters], v1[T::kInvIters];
+#pragma unroll
+    for (int it = 0; it < T::kInvIters; ++it) {
+      const int e = tid + it * kGlThreads;
+      if (e < kRows * kCols) {
+        const int r = e / kCols, col = e - r * kCols;
+        const size_t o = static_cast<size_t>(row_at[r]) * W + col_at[col];
+        v0[it] = s0[o];
+        v1[it] = s1[o];
       }
-    if (lev > 0) {
-      const float tau = sigma * (a - b * static_cast<float>(lev));
-      if (!(fabsf(vol[i]) >= tau)) vol[i] = 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < T::kInvIters; ++it) {
+      const int e = tid + it * kGlThreads;
+      if (e < kRows * kCols) {
+        const int r = e / kCols, col = e - r * kCols;
+        in_s[0][r][col] = v0[it];
+        in_s[1][r][col] = v1[it];
+      }
     }
   }
-}
-
-// acc (=|+=) scale * src[(k + h) mod K][(y + h) mod H][(x + h) mod W]  (S_{-h})
-__global__ __launch_bounds__(kGlThreads) void gl_unspin_kernel(const float* __restrict__ src,
-                                                               float* __restrict__ acc, int K, int H, int W, int h,
-                                                               int first, float scale) {
-  const int x = blockIdx.x * kGlThreads + threadIdx.x;
-  if (x >= W) return;
-  const int y = blockIdx.y, k = blockIdx.z;
-  const size_t i = (static_cast<size_t>(k) * H + y) * W + x;
-  {
-    const size_t hw = static_cast<size_t>(H) * W;
-    const float v = scale * src[static_cast<size_t>(wrap(k + h, K)) * hw + static_cast<size_t>(wrap(y + h, H)) * W +
-                                wrap(x + h, W)];
-    acc[i] = first ? v : acc[i] + v;
+  __syncthreads();
+  for (int e = tid; e < 2 * kRows * TX; e += kGlThreads) {
+    const int j = e % TX, r = (e / TX) % kRows, kb = e / (TX * kRows);
+    const float* row = in_s[kb][r];
+    const float a = c * row[j];
+    float ev = a, od = a;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const float d = row[TX + j + i];
+      ev = fmaf(bior_syn_even(i), d, ev);
+      od = fmaf(bior_syn_odd(i), d, od);
+    }
+    xs[kb][r][2 * j] = ev;
+    xs[kb][r][2 * j + 1] = od;
+  }
+  __syncthreads();
+  for (int e = tid; e < TY * 2 * TX; e += kGlThreads) {
+    const int cc = e % (2 * TX), i = e / (2 * TX);
+    const int y = 2 * (cy0 + i), x = 2 * cx0 + cc;
+    if (y >= Ly || x >= Lx) continue;
+    float ev[2], od[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const float a = c * xs[kb][i][cc];
+      ev[kb] = a;
+      od[kb] = a;
+#pragma unroll
+      for (int u = 0; u < 5; ++u) {
+        const float d = xs[kb][TY + i + u][cc];
+        ev[kb] = fmaf(bior_syn_even(u), d, ev[kb]);
+        od[kb] = fmaf(bior_syn_odd(u), d, od[kb]);
+      }
+    }
+    const float v[2][2] = {{(ev[0] + ev[1]) * c, (od[0] + od[1]) * c}, {(ev[0] - ev[1]) * c, (od[0] - od[1]) * c}};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if constexpr (UNSPIN) {
+          float* o = dst + static_cast<size_t>(wrap1(2 * kp + s - h, K)) * hw +
+                     static_cast<size_t>(wrap1(y + p - h, H)) * W + wrap1(x - h, W);
+          *o = first ? scale * v[s][p] : *o + scale * v[s][p];
+        } else {
+          dst[static_cast<size_t>(2 * kp + s) * hw + static_cast<size_t>(y + p) * W + x] = v[s][p];
+        }
+      }
+    }
   }
 }
 
@@ -406,6 +540,10 @@ __global__ void gl_normalize_kernel(const unsigned long long* __restrict__ num,
   }
 }
 
+dim3 level_grid(int Lk, int Ly, int Lx, int ty, int tx) {
+  return dim3((Lx / 2 + tx - 1) / tx, (Ly / 2 + ty - 1) / ty, Lk / 2);
+}
+
 unsigned grid_for(size_t n) {
   const size_t b = (n + kGlThreads - 1) / kGlThreads;
   return static_cast<unsigned>(b < 8192 ? (b > 0 ? b : 1) : 8192);
@@ -415,7 +553,6 @@ template <int N, int K>
 hipError_t global_nk(const GlobalJob& j, hipStream_t st) {
   const int H = j.H, W = j.W;
   const size_t hw = static_cast<size_t>(H) * W;
-  const dim3 vol_grid((W + kGlThreads - 1) / kGlThreads, H, K);
   const int tiles = (H / N) * (W / N);
   const float eps = j.tv_eps_rel * j.sigma * static_cast<float>(N * N * K);
   for (int ti = 0; ti < j.n_shifts; ++ti) {
@@ -427,42 +564,32 @@ hipError_t global_nk(const GlobalJob& j, hipStream_t st) {
     }
     hipLaunchKernelGGL((gl_match_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, img, H, W, j.search, j.idx);
     for (int h = 0; h < j.cycles; ++h) {
-      float* A = j.vol_a;
-      float* B = j.vol_b;
-      hipLaunchKernelGGL((gl_volume_kernel<N, K>), vol_grid, dim3(kGlThreads), 0, st, img, j.idx, H, W, j.search, h,
-                         A);
-      // forward: level 0 ends in B; every coarser level ends in A and its
-      // region is copied back into B
+      // forward level l writes buf[l & 1]; the next level reads only the
+      // low-low-low region of it, so every level's detail bands stay where
+      // they were written.  The inverse retraces the same buffers, and the
+      // finest level writes the spin average.
+      float* buf[2] = {j.vol_b, j.vol_a};
       for (int l = 0; l < j.levels; ++l) {
         const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
-        const size_t rn = static_cast<size_t>(Lk) * Ly * Lx;
-        const dim3 axis_grid((Lx + kGlThreads - 1) / kGlThreads, Ly, Lk);
-        float* s0 = l == 0 ? A : B;
-        float* s1 = l == 0 ? B : A;
-        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, s0, s1, H, W, Lk, Ly, Lx, 1, 0);
-        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, s1, s0, H, W, Lk, Ly, Lx, 2, 0);
-        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, s0, s1, H, W, Lk, Ly, Lx, 0, 0);
-        if (l > 0)
-          hipLaunchKernelGGL(gl_copy_region_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, A, B, H, W, Lk, Ly,
-                             Lx);
+        const float tau = j.sigma * (j.ht_a - j.ht_b * static_cast<float>(l + 1));
+        if (l == 0)
+          hipLaunchKernelGGL((gl_forward_kernel<N, K, true, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32),
+                             dim3(kGlThreads), 0, st, nullptr, img, j.idx, j.search, h, buf[0], H, W, Lk, Ly, Lx, tau);
+        else
+          hipLaunchKernelGGL((gl_forward_kernel<N, K, false, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16),
+                             dim3(kGlThreads), 0, st, buf[(l - 1) & 1], nullptr, nullptr, j.search, h, buf[l & 1], H, W,
+                             Lk, Ly, Lx, tau);
       }
-      hipLaunchKernelGGL(gl_threshold_kernel, vol_grid, dim3(kGlThreads), 0, st, B, K, H, W, j.levels, j.sigma, j.ht_a,
-                         j.ht_b);
-      // inverse, coarsest level first: each level reads B and ends in A; all
-      // but the finest copy their region back into B
       for (int l = j.levels - 1; l >= 0; --l) {
         const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
-        const size_t rn = static_cast<size_t>(Lk) * Ly * Lx;
-        const dim3 axis_grid((Lx + kGlThreads - 1) / kGlThreads, Ly, Lk);
-        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, B, A, H, W, Lk, Ly, Lx, 0, 1);
-        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, A, B, H, W, Lk, Ly, Lx, 2, 1);
-        hipLaunchKernelGGL(gl_axis_kernel, axis_grid, dim3(kGlThreads), 0, st, B, A, H, W, Lk, Ly, Lx, 1, 1);
-        if (l > 0)
-          hipLaunchKernelGGL(gl_copy_region_kernel, dim3(grid_for(rn)), dim3(kGlThreads), 0, st, A, B, H, W, Lk, Ly,
-                             Lx);
+        if (l == 0)
+          hipLaunchKernelGGL((gl_inverse_kernel<K, true, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32), dim3(kGlThreads),
+                             0, st, buf[0], j.vol_u, H, W, Lk, Ly, Lx, h, h == 0 ? 1 : 0,
+                             1.0f / static_cast<float>(j.cycles));
+        else
+          hipLaunchKernelGGL((gl_inverse_kernel<K, false, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16), dim3(kGlThreads),
+                             0, st, buf[l & 1], buf[(l - 1) & 1], H, W, Lk, Ly, Lx, h, 0, 1.0f);
       }
-      hipLaunchKernelGGL(gl_unspin_kernel, vol_grid, dim3(kGlThreads), 0, st, A, j.vol_u, K, H, W, h, h == 0 ? 1 : 0,
-                         1.0f / static_cast<float>(j.cycles));
     }
     hipLaunchKernelGGL(gl_zero_kernel, dim3(grid_for(2 * hw)), dim3(kGlThreads), 0, st, j.num, 2 * hw);
     hipLaunchKernelGGL((gl_aggregate_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, j.vol_u, j.idx, H, W,
