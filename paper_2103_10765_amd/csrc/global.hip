@@ -24,6 +24,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "topk.h"
 
 namespace gbm3d {
 
@@ -39,114 +40,161 @@ constexpr double kKeyInfG = __builtin_huge_val();
 template <int N>
 struct TileSmem {
   static constexpr int kRegion = kMaxSearch + N - 1;
-  int reg[kRegion * kRegion];  // search region, pixel values
+  // row pitch: the region plus the columns the last 8-wide displacement
+  // group reads past it, made odd so that lanes on consecutive rows fall on
+  // different LDS banks
+  static constexpr int kPitch = (kRegion + 2) | 1;
+  double reg[kRegion * kPitch];          // search region, pixel values
   double keys[kMaxSearch * kMaxSearch];  // dist * 2048 + rank (+inf for the reference)
+  double part[kGlThreads / kWave];       // per-wave partial sums of the reference norm
 };
 
 template <int N, int K>
 __global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __restrict__ img, int H, int W, int S,
                                                               int16_t* __restrict__ idx) {
-  __shared__ TileSmem<N> sm;
+  using Sm = TileSmem<N>;
+  constexpr int P = Sm::kPitch;
+  constexpr int L = K - 1;
+  __shared__ Sm sm;
   const int tiles_x = W / N;
   const int g = blockIdx.x;
   const int y0 = (g / tiles_x) * N, x0 = (g % tiles_x) * N;
   const int R = S / 2;
   const int side = S + N - 1;
-  for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
-    const int r = i / side, c = i - r * side;
-    const int y = pmod(y0 - R + r, H), x = pmod(x0 - R + c, W);
-    sm.reg[i] = img[static_cast<size_t>(y) * W + x];
-  }
-  __syncthreads();
-  const int S2 = S * S;
-  // exact squared distances, every difference squared and summed in float64
-  // (each term < 2^32, the sum < 2^42); a work item is one displacement row
-  // dy and four consecutive dx, so each reference pixel read from LDS serves
-  // four candidates
-  constexpr int kDx = 4;
-  const int groups = (S + kDx - 1) / kDx;
-  for (int item = threadIdx.x; item < S * groups; item += blockDim.x) {
-    const int dy = item / groups, dx0 = (item - dy * groups) * kDx;
-    double d[kDx] = {0.0, 0.0, 0.0, 0.0};
-    for (int a = 0; a < N; ++a) {
-      const int* rr = sm.reg + (R + a) * side + R;
-      const int* cr = sm.reg + (dy + a) * side + dx0;
-      int seg[N + kDx - 1];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  {
+    // the (S + N - 1)^2 search region (rows and columns wrap at most once:
+    // R < H, W), all loads issued before any store
+    constexpr int kIters = (Sm::kRegion * P + kGlThreads - 1) / kGlThreads;
+    uint16_t v[kIters];
 #pragma unroll
-      for (int b = 0; b < N + kDx - 1; ++b) seg[b] = dx0 + b < side ? cr[b] : 0;
-#pragma unroll
-      for (int b = 0; b < N; ++b) {
-        const int ref = rr[b];
-#pragma unroll
-        for (int c = 0; c < kDx; ++c) {
-          const double t = static_cast<double>(ref - seg[b + c]);
-          d[c] = fma(t, t, d[c]);
-        }
+    for (int it = 0; it < kIters; ++it) {
+      const int i = threadIdx.x + it * kGlThreads;
+      const int r = i / P, c = i - r * P;
+      v[it] = 0;
+      if (i < side * P && c < side) {
+        int y = y0 - R + r, x = x0 - R + c;
+        y = y < 0 ? y + H : (y >= H ? y - H : y);
+        x = x < 0 ? x + W : (x >= W ? x - W : x);
+        v[it] = img[static_cast<size_t>(y) * W + x];
       }
     }
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+      const int i = threadIdx.x + it * kGlThreads;
+      if (i < side * P) sm.reg[i] = v[it];
+    }
+  }
+  __syncthreads();
+  // the reference block's squared norm: one pixel per thread (N * N <= 256)
+  {
+    double v = 0.0;
+    if (threadIdx.x < N * N) {
+      v = sm.reg[(R + threadIdx.x / N) * P + R + threadIdx.x % N];
+      v *= v;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += shfl_xor_double(v, off);
+    if (lane == 0) sm.part[wave] = v;
+  }
+  __syncthreads();
+  double ref_norm = 0.0;
+#pragma unroll
+  for (int w = 0; w < kGlThreads / kWave; ++w) ref_norm += sm.part[w];
+  // exact squared distances as |a|^2 + |b|^2 - 2 <a, b>: every term an
+  // integer below 2^41, so float64 holds each step exactly and the keys equal
+  // those of summed squared differences.  A work item is one displacement
+  // row dy and eight consecutive dx: each reference pixel (one LDS word read
+  // by the whole wave) serves all eight; the candidates' norms are column
+  // sums of squares over the same rows, then sums of N columns.
+  const int S2 = S * S;
+  constexpr int kDx = 8;
+  constexpr int kSeg = N + kDx - 1;
+  const int groups = (S + kDx - 1) / kDx;
+  for (int item = threadIdx.x; item < S * groups; item += blockDim.x) {
+    // consecutive lanes take consecutive rows dy (an odd pitch apart: no
+    // two of 32 lanes on one LDS bank)
+    const int gi = item / S, dy = item - gi * S, dx0 = gi * kDx;
+    double d[kDx];
+#pragma unroll
+    for (int c = 0; c < kDx; ++c) d[c] = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < N; ++a) {
+      const double* cr = sm.reg + (dy + a) * P + dx0;
+      const double* rr = sm.reg + (R + a) * P + R;
+      double seg[kSeg];
+#pragma unroll
+      for (int b = 0; b < kSeg; ++b) seg[b] = cr[b];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const double rv = rr[b];
+#pragma unroll
+        for (int c = 0; c < kDx; ++c) d[c] = fma(rv, seg[b + c], d[c]);
+      }
+    }
+    // the candidates' norms: column sums of squares over the same rows
+    double col[kSeg];
+#pragma unroll
+    for (int b = 0; b < kSeg; ++b) col[b] = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < N; ++a) {
+      const double* cr = sm.reg + (dy + a) * P + dx0;
+#pragma unroll
+      for (int b = 0; b < kSeg; ++b) col[b] = fma(cr[b], cr[b], col[b]);
+    }
+    double cn = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) cn += col[b];
 #pragma unroll
     for (int c = 0; c < kDx; ++c) {
       const int dx = dx0 + c;
+      if (c > 0) cn += col[N - 1 + c] - col[c - 1];
       if (dx < S) {
         const int r = dy * S + dx;
-        sm.keys[r] = r == S2 / 2 ? kKeyInfG : fma(d[c], 2048.0, static_cast<double>(r));
+        const double dist = (ref_norm + cn) - 2.0 * d[c];
+        sm.keys[r] = r == S2 / 2 ? kKeyInfG : fma(dist, 2048.0, static_cast<double>(r));
       }
     }
   }
   __syncthreads();
-  // the K-1 smallest keys (keys are unique): every wave takes its K-1
-  // smallest by repeated wave minima over its lanes' keys, then wave 0 does
-  // the same over the four waves' lists
+  // the K-1 smallest keys (keys are unique): each lane sorts its own keys,
+  // the lanes of a wave merge their lists pairwise along a butterfly (every
+  // lane ends with the wave's K-1 smallest), and wave 0 merges the four
+  // waves' lists the same way
   constexpr int kPer = (kMaxSearch * kMaxSearch + kGlThreads - 1) / kGlThreads;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  double mine[kPer];
+  constexpr int kSort = pow2_ceil(kPer);
+  double list[L];
+  {
+    double mine[kSort];
 #pragma unroll
-  for (int m = 0; m < kPer; ++m) {
-    const int r = threadIdx.x + m * kGlThreads;
-    mine[m] = r < S2 ? sm.keys[r] : kKeyInfG;
+    for (int m = 0; m < kSort; ++m) {
+      const int r = threadIdx.x + m * kGlThreads;
+      mine[m] = (m < kPer && r < S2) ? sm.keys[r] : kKeyInfG;
+    }
+    bitonic_sort<kSort>(mine);
+#pragma unroll
+    for (int i = 0; i < L; ++i) list[i] = i < kSort ? mine[i] : kKeyInfG;
   }
-  auto wave_min = [](double v) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const int lo = __shfl_xor(__double2loint(v), off, kWave), hi = __shfl_xor(__double2hiint(v), off, kWave);
-      v = fmin(v, __hiloint2double(hi, lo));
-    }
-    return v;
-  };
-  auto take_smallest = [&](double (&vals)[kPer], int count, double* dst) {
-    for (int s = 0; s < count; ++s) {
-      double cur = vals[0];
-#pragma unroll
-      for (int m = 1; m < kPer; ++m) cur = fmin(cur, vals[m]);
-      const double best = wave_min(cur);
-      if (lane == 0) dst[s] = best;
-#pragma unroll
-      for (int m = 0; m < kPer; ++m)
-        if (vals[m] == best) vals[m] = kKeyInfG;
-    }
-  };
+  for (int off = 1; off < kWave; off <<= 1) merge_sorted<L>(list, [&](int j) { return shfl_xor_double(list[j], off); });
   __syncthreads();  // every key has been read; the key array is reused below
-  double* wtop = sm.keys;                  // [4][K - 1]
-  take_smallest(mine, K - 1, wtop + wave * (K - 1));
+  double* wl = sm.keys;  // [4][L]
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) wl[wave * L + i] = list[i];
+  }
   __syncthreads();
   if (wave == 0) {
 #pragma unroll
-    for (int m = 0; m < kPer; ++m) {
-      const int c = lane + m * kWave;
-      mine[m] = c < 4 * (K - 1) ? wtop[c] : kKeyInfG;
-    }
-    double* top = sm.keys + 4 * (K - 1);   // [K - 1], ascending
-    take_smallest(mine, K - 1, top);
-    wave_lds_sync();  // lane 0's writes of `top` are visible to the wave
-    if (lane < K) {
-      int16_t rank;
-      if (lane == 0) {
-        rank = static_cast<int16_t>(S2 / 2);
-      } else {
-        const double key = top[lane - 1];
-        rank = static_cast<int16_t>(key - 2048.0 * floor(key * (1.0 / 2048.0)));
-      }
-      idx[static_cast<size_t>(g) * K + lane] = rank;
+    for (int i = 0; i < L; ++i) list[i] = lane < kGlThreads / kWave ? wl[lane * L + i] : kKeyInfG;
+#pragma unroll
+    for (int off = 1; off < kGlThreads / kWave; off <<= 1)
+      merge_sorted<L>(list, [&](int j) { return shfl_xor_double(list[j], off); });
+    if (lane == 0) {
+      int16_t* out = idx + static_cast<size_t>(g) * K;
+      out[0] = static_cast<int16_t>(S2 / 2);
+#pragma unroll
+      for (int i = 0; i < L; ++i) out[i + 1] = key_rank(list[i]);
     }
   }
 }
