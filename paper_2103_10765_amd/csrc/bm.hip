@@ -107,9 +107,19 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
   const int y0 = kStep * p0 - R;
   const int x0 = kStep * q0 - R;
   const int nrows = kStep * (RPW - 1) + kPatch + 2 * R;
+  // y0 < H and x0 < W: rows and columns wrap at most once when the image
+  // is at least as tall as the tile and as wide as its columns
+  const bool near = H >= nrows && W >= 3 * kSubCols;
   for (int i = threadIdx.x; i < nrows * 3 * kSubCols; i += blockDim.x) {
     const int r = i / (3 * kSubCols), c = i - r * (3 * kSubCols);
-    const int y = pmod(y0 + r, H), x = pmod(x0 + c, W);
+    int y = y0 + r, x = x0 + c;
+    if (near) {
+      y += y < 0 ? H : (y >= H ? -H : 0);
+      x += x < 0 ? W : (x >= W ? -W : 0);
+    } else {
+      y = pmod(y, H);
+      x = pmod(x, W);
+    }
     sub[((c % 3) * rows + r) * kSubCols + c / 3] = img[static_cast<size_t>(y) * W + x];
   }
   if constexpr (SPLIT > 1) bound[threadIdx.x] = __double_as_longlong(kInf);

@@ -226,9 +226,19 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   // LDS planes of the image region rows 3 p0 - R + [0, 4 nb + 7), columns 3 q0 - R + [0, kPitch)
   const int y0 = kStep * p0 - R, x0 = kStep * q0 - R;
   const int rows = 4 * nb + 7;
+  // y0 < H and x0 < W: rows and columns wrap at most once when the image
+  // is at least as tall as the region and as wide as a plane row
+  const bool near = H >= rows && W >= kPitch;
   for (int i = threadIdx.x; i < rows * (kPitch / 4); i += blockDim.x) {
     const int r = i / (kPitch / 4), c = (i - r * (kPitch / 4)) * 4;
-    const int y = pmod(y0 + r, H), xb = pmod(x0 + c, W);
+    int y = y0 + r, xb = x0 + c;
+    if (near) {
+      y += y < 0 ? H : (y >= H ? -H : 0);
+      xb += xb < 0 ? W : (xb >= W ? -W : 0);
+    } else {
+      y = pmod(y, H);
+      xb = pmod(xb, W);
+    }
     unsigned wh = 0, wl = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
