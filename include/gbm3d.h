@@ -198,8 +198,9 @@ typedef struct {
 void gbm3d_global_default_params(gbm3d_global_params* p);
 
 /* noisy: device u16 [H][W]; out: device float [H][W].  H, W: multiples of
- * patch, at least max(search, patch).  The context keeps three float volumes
- * of k H W entries and 2 H W 64-bit sums as workspace. */
+ * patch, at least max(search, patch).  The context keeps 2 * cycles float
+ * volumes of k H W entries (all cycle spins are filtered together) and 2 H W
+ * 64-bit sums as workspace; GBM3D_ENOMEM when they cannot be allocated. */
 int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
                        const gbm3d_global_params* params, float* out, void* stream);
 

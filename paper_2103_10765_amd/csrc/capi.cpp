@@ -66,7 +66,7 @@ struct gbm3d_ctx {
   std::string err;
   Buffer stack_a, stack_b, idx, partials, basic, q, norm;
   // global stage 1
-  Buffer gl_a, gl_b, gl_u, gl_num, gl_idx, gl_shift;
+  Buffer gl_a, gl_b, gl_num, gl_idx, gl_shift;
   // block-matching choices per (K, shape class)
   std::map<std::pair<int, int>, TuneEntry> tuned;
   // batches
@@ -639,7 +639,7 @@ void gbm3d_destroy(gbm3d_ctx* ctx) {
     drop_graph(ctx);
     for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->norm, &ctx->batch_ws,
                       &ctx->batch_table, &ctx->pilot_w, &ctx->pilot_act, &ctx->pilot_part, &ctx->gl_a, &ctx->gl_b,
-                      &ctx->gl_u, &ctx->gl_num, &ctx->gl_idx, &ctx->gl_shift})
+                      &ctx->gl_num, &ctx->gl_idx, &ctx->gl_shift})
       if (b->p) (void)hipFree(b->p);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
@@ -887,9 +887,8 @@ int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, floa
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
   const size_t hw = static_cast<size_t>(H) * W;
   const size_t vb = gbm3d::global_volume_bytes(H, W, p.k);
-  CHECK(ensure(ctx, ctx->gl_a, vb, "global volume"));
-  CHECK(ensure(ctx, ctx->gl_b, vb, "global volume"));
-  CHECK(ensure(ctx, ctx->gl_u, vb, "global volume"));
+  CHECK(ensure(ctx, ctx->gl_a, p.cycles * vb, "global volumes"));
+  CHECK(ensure(ctx, ctx->gl_b, p.cycles * vb, "global volumes"));
   CHECK(ensure(ctx, ctx->gl_num, 2 * hw * sizeof(unsigned long long), "global sums"));
   CHECK(ensure(ctx, ctx->gl_idx, (hw / (p.patch * p.patch)) * p.k * sizeof(int16_t), "global matches"));
   CHECK(ensure(ctx, ctx->gl_shift, hw * sizeof(uint16_t), "translated image"));
@@ -911,7 +910,6 @@ int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, floa
   j.tv_eps_rel = p.tv_eps_rel;
   j.vol_a = static_cast<float*>(ctx->gl_a.p);
   j.vol_b = static_cast<float*>(ctx->gl_b.p);
-  j.vol_u = static_cast<float*>(ctx->gl_u.p);
   j.num = static_cast<unsigned long long*>(ctx->gl_num.p);
   j.idx = static_cast<int16_t*>(ctx->gl_idx.p);
   j.shifted = static_cast<uint16_t*>(ctx->gl_shift.p);

@@ -14,12 +14,13 @@
 // normalised estimate is averaged over translations of the image
 // (eq. firstEst).
 //
-// The transform runs one kernel per level: a workgroup loads a window of
-// two k-slices into LDS and does the Haar pair along k and the bior1.5
-// filters along x and y there, writing the eight bands of its coefficient
-// tile (thresholded, but for the low-low-low band).  Level 0 gathers the
-// spun volume straight from the image, and the finest inverse level writes
-// the average over the cycle spins, so the volume itself is never stored.
+// The transform runs one kernel per level for all cycle spins at once: a
+// workgroup loads a window of two k-slices of one spin into LDS and does the
+// Haar pair along k and the bior1.5 filters along x and y there, writing the
+// eight bands of its coefficient tile (thresholded, but for the
+// low-low-low band).  Level 0 gathers the spun volume straight from the
+// image, so the unfiltered volume is never stored; the aggregation undoes
+// the spins and averages them as it loads each tile's blocks.
 #include <cstdint>
 
 #include "common.h"
@@ -264,12 +265,13 @@ struct LevelTile {
 // within the region.  Output bands go to their Mallat positions (low half /
 // high half of each axis) in dst; every band but low-low-low is hard
 // thresholded with tau.  With GATHER the input is the spun volume V_h,
-// gathered from the image through the matches, instead of src.
-// grid: (ceil(Lx / 2 / TX), ceil(Ly / 2 / TY), Lk / 2)
+// gathered from the image through the matches, instead of src.  Every cycle
+// spin h has its own pair of volumes, K H W elements apart in src and dst.
+// grid: (ceil(Lx / 2 / TX), ceil(Ly / 2 / TY), Lk / 2 * spins), z = h Lk / 2 + kp
 template <int N, int K, bool GATHER, int TY, int TX>
 __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __restrict__ src,
                                                                  const uint16_t* __restrict__ img,
-                                                                 const int16_t* __restrict__ idx, int S, int h,
+                                                                 const int16_t* __restrict__ idx, int S,
                                                                  float* __restrict__ dst, int H, int W, int Lk, int Ly,
                                                                  int Lx, float tau) {
   using T = LevelTile<TY, TX>;
@@ -283,8 +285,11 @@ __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __r
   // the tile offset of the spun coordinate
   __shared__ int row_at[kRows], col_at[kCols], row_tile[GATHER ? kRows : 1], col_tile[GATHER ? kCols : 1];
   const int hy = Ly >> 1, hx = Lx >> 1, hk = Lk >> 1;
-  const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY, kp = blockIdx.z;
+  const int h = blockIdx.z / hk, kp = blockIdx.z - h * hk;
+  const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY;
   const size_t hw = static_cast<size_t>(H) * W;
+  if constexpr (!GATHER) src += static_cast<size_t>(h) * K * hw;
+  dst += static_cast<size_t>(h) * K * hw;
   const float c = 0.70710678118654752f;
   const int tid = threadIdx.x;
   if (tid < kRows) {
@@ -398,14 +403,12 @@ __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __r
 // The inverse of one level: src holds the level's eight bands at their
 // Mallat positions in the region; the workgroup rebuilds slices 2 kp, 2 kp + 1,
 // rows 2 cy0 .. 2 cy0 + 2 TY - 1 and columns 2 cx0 .. 2 cx0 + 2 TX - 1
-// (synthesis along x, then y, then the Haar pair along k).  Without UNSPIN the
-// result goes to the same positions of dst; with UNSPIN (the finest level,
-// region = volume) element (k, y, x) is scaled and stored (first) or added to
-// dst[(k - h) mod K][(y - h) mod H][(x - h) mod W], undoing the spin S_h.
-template <int K, bool UNSPIN, int TY, int TX>
+// (synthesis along x, then y, then the Haar pair along k) at the same
+// positions of dst.  Volumes and grid as in the forward kernel.
+template <int K, int TY, int TX>
 __global__ __launch_bounds__(kGlThreads) void gl_inverse_kernel(const float* __restrict__ src,
                                                                  float* __restrict__ dst, int H, int W, int Lk, int Ly,
-                                                                 int Lx, int h, int first, float scale) {
+                                                                 int Lx) {
   using T = LevelTile<TY, TX>;
   // window rows: low band cy0 .. cy0 + TY - 1, then high band cy0 - 2 ..
   // cy0 + TY + 1 (the synthesis taps reach two coefficients either side);
@@ -415,8 +418,11 @@ __global__ __launch_bounds__(kGlThreads) void gl_inverse_kernel(const float* __r
   __shared__ float xs[2][kRows][2 * TX];
   __shared__ int row_at[kRows], col_at[kCols];
   const int hy = Ly >> 1, hx = Lx >> 1, hk = Lk >> 1;
-  const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY, kp = blockIdx.z;
+  const int h = blockIdx.z / hk, kp = blockIdx.z - h * hk;
+  const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY;
   const size_t hw = static_cast<size_t>(H) * W;
+  src += static_cast<size_t>(h) * K * hw;
+  dst += static_cast<size_t>(h) * K * hw;
   const float c = 0.70710678118654752f;
   const int tid = threadIdx.x;
   if (tid < kRows) {
@@ -487,15 +493,7 @@ __global__ __launch_bounds__(kGlThreads) void gl_inverse_kernel(const float* __r
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        if constexpr (UNSPIN) {
-          float* o = dst + static_cast<size_t>(wrap1(2 * kp + s - h, K)) * hw +
-                     static_cast<size_t>(wrap1(y + p - h, H)) * W + wrap1(x - h, W);
-          *o = first ? scale * v[s][p] : *o + scale * v[s][p];
-        } else {
-          dst[static_cast<size_t>(2 * kp + s) * hw + static_cast<size_t>(y + p) * W + x] = v[s][p];
-        }
-      }
+      for (int p = 0; p < 2; ++p) dst[static_cast<size_t>(2 * kp + s) * hw + static_cast<size_t>(y + p) * W + x] = v[s][p];
     }
   }
 }
@@ -506,14 +504,17 @@ __global__ void gl_zero_kernel(unsigned long long* __restrict__ p, size_t n) {
     p[i] = 0;
 }
 
-// One workgroup per tile: w = eps / (TV(u) + eps) (the 1 / (TV + eps) weight
-// scaled by eps, which cancels in the average), then every filtered block is
-// added at its source position: num += w u, den += w (64-bit fixed point).
+// One workgroup per tile.  u is the average over the cycle spins h of the
+// filtered spun volumes (spin h at vol + h K H W) with each spin undone:
+// u[k][y][x] = (1 / spins) sum_h vol_h[(k + h) mod K][(y + h) mod H][(x + h) mod W].
+// w = eps / (TV(u) + eps) (the 1 / (TV + eps) weight scaled by eps, which
+// cancels in the average), then every filtered block is added at its source
+// position: num += w u, den += w (64-bit fixed point).
 // The K blocks all lie in the tile's (S + N - 1)^2 search footprint, which
 // is summed in LDS first; only its covered cells go to the image with global
 // integer atomics.
 template <int N, int K>
-__global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* __restrict__ u,
+__global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* __restrict__ vol, int spins,
                                                                    const int16_t* __restrict__ idx, int H, int W,
                                                                    int S, float eps,
                                                                    unsigned long long* __restrict__ num,
@@ -532,9 +533,18 @@ __global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* _
     fnum[i] = 0;
     fden[i] = 0;
   }
-  for (int i = threadIdx.x; i < kVals; i += blockDim.x) {
-    const int k = i / (N * N), a = (i / N) % N, b = i % N;
-    blk[i] = u[static_cast<size_t>(k) * hw + static_cast<size_t>(y0 + a) * W + x0 + b];
+  {
+    const float scale = 1.0f / static_cast<float>(spins);
+    for (int i = threadIdx.x; i < kVals; i += blockDim.x) {
+      const int k = i / (N * N), a = (i / N) % N, b = i % N;
+      float v = 0.0f;
+      for (int h = 0; h < spins; ++h) {
+        const float* vh = vol + static_cast<size_t>(h) * K * hw;
+        v += scale * vh[static_cast<size_t>(wrap1(k + h, K)) * hw + static_cast<size_t>(wrap1(y0 + a + h, H)) * W +
+                        wrap1(x0 + b + h, W)];
+      }
+      blk[i] = v;
+    }
   }
   __syncthreads();
   double tv = 0.0;
@@ -588,8 +598,8 @@ __global__ void gl_normalize_kernel(const unsigned long long* __restrict__ num,
   }
 }
 
-dim3 level_grid(int Lk, int Ly, int Lx, int ty, int tx) {
-  return dim3((Lx / 2 + tx - 1) / tx, (Ly / 2 + ty - 1) / ty, Lk / 2);
+dim3 level_grid(int Lk, int Ly, int Lx, int ty, int tx, int spins) {
+  return dim3((Lx / 2 + tx - 1) / tx, (Ly / 2 + ty - 1) / ty, Lk / 2 * spins);
 }
 
 unsigned grid_for(size_t n) {
@@ -611,36 +621,35 @@ hipError_t global_nk(const GlobalJob& j, hipStream_t st) {
       img = j.shifted;
     }
     hipLaunchKernelGGL((gl_match_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, img, H, W, j.search, j.idx);
-    for (int h = 0; h < j.cycles; ++h) {
-      // forward level l writes buf[l & 1]; the next level reads only the
-      // low-low-low region of it, so every level's detail bands stay where
-      // they were written.  The inverse retraces the same buffers, and the
-      // finest level writes the spin average.
-      float* buf[2] = {j.vol_b, j.vol_a};
-      for (int l = 0; l < j.levels; ++l) {
-        const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
-        const float tau = j.sigma * (j.ht_a - j.ht_b * static_cast<float>(l + 1));
-        if (l == 0)
-          hipLaunchKernelGGL((gl_forward_kernel<N, K, true, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32),
-                             dim3(kGlThreads), 0, st, nullptr, img, j.idx, j.search, h, buf[0], H, W, Lk, Ly, Lx, tau);
-        else
-          hipLaunchKernelGGL((gl_forward_kernel<N, K, false, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16),
-                             dim3(kGlThreads), 0, st, buf[(l - 1) & 1], nullptr, nullptr, j.search, h, buf[l & 1], H, W,
-                             Lk, Ly, Lx, tau);
-      }
-      for (int l = j.levels - 1; l >= 0; --l) {
-        const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
-        if (l == 0)
-          hipLaunchKernelGGL((gl_inverse_kernel<K, true, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32), dim3(kGlThreads),
-                             0, st, buf[0], j.vol_u, H, W, Lk, Ly, Lx, h, h == 0 ? 1 : 0,
-                             1.0f / static_cast<float>(j.cycles));
-        else
-          hipLaunchKernelGGL((gl_inverse_kernel<K, false, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16), dim3(kGlThreads),
-                             0, st, buf[l & 1], buf[(l - 1) & 1], H, W, Lk, Ly, Lx, h, 0, 1.0f);
-      }
+    // every cycle spin in the same launches: forward level l writes
+    // buf[l & 1]; the next level reads only the low-low-low region of it, so
+    // every level's detail bands stay where they were written.  The inverse
+    // retraces the same buffers and the finest level leaves the filtered spun
+    // volumes in vol_a.
+    float* buf[2] = {j.vol_b, j.vol_a};
+    const int C = j.cycles;
+    for (int l = 0; l < j.levels; ++l) {
+      const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
+      const float tau = j.sigma * (j.ht_a - j.ht_b * static_cast<float>(l + 1));
+      if (l == 0)
+        hipLaunchKernelGGL((gl_forward_kernel<N, K, true, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32, C),
+                           dim3(kGlThreads), 0, st, nullptr, img, j.idx, j.search, buf[0], H, W, Lk, Ly, Lx, tau);
+      else
+        hipLaunchKernelGGL((gl_forward_kernel<N, K, false, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16, C),
+                           dim3(kGlThreads), 0, st, buf[(l - 1) & 1], nullptr, nullptr, j.search, buf[l & 1], H, W, Lk,
+                           Ly, Lx, tau);
+    }
+    for (int l = j.levels - 1; l >= 0; --l) {
+      const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
+      if (l == 0)
+        hipLaunchKernelGGL((gl_inverse_kernel<K, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32, C), dim3(kGlThreads), 0, st,
+                           buf[0], j.vol_a, H, W, Lk, Ly, Lx);
+      else
+        hipLaunchKernelGGL((gl_inverse_kernel<K, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16, C), dim3(kGlThreads), 0, st,
+                           buf[l & 1], buf[(l - 1) & 1], H, W, Lk, Ly, Lx);
     }
     hipLaunchKernelGGL(gl_zero_kernel, dim3(grid_for(2 * hw)), dim3(kGlThreads), 0, st, j.num, 2 * hw);
-    hipLaunchKernelGGL((gl_aggregate_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, j.vol_u, j.idx, H, W,
+    hipLaunchKernelGGL((gl_aggregate_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, j.vol_a, C, j.idx, H, W,
                        j.search, eps, j.num, j.num + hw);
     hipLaunchKernelGGL(gl_normalize_kernel, dim3(grid_for(hw)), dim3(kGlThreads), 0, st, j.num, j.num + hw, H, W, t,
                        ti == 0 ? 1 : 0, 1.0f / static_cast<float>(j.n_shifts), j.out);

@@ -67,9 +67,10 @@ int reduce_items_for(int H, int W);
 hipError_t launch_quantize(const float* in, uint16_t* out, size_t n, hipStream_t st);
 
 // Global stage 1 (the volume form of Sec. 3): one image, every buffer on the
-// device.  vol_a, vol_b, vol_u: global_volume_bytes each; num: 2 H W
-// 64-bit words (numerators, then denominators); idx: (H/patch)(W/patch) k
-// int16; shifted: H W uint16 (used when a translation is not 0).
+// device.  vol_a, vol_b: cycles * global_volume_bytes each (one volume per
+// cycle spin); num: 2 H W 64-bit words (numerators, then denominators); idx:
+// (H/patch)(W/patch) k int16; shifted: H W uint16 (used when a translation is
+// not 0).
 struct GlobalJob {
   const uint16_t* noisy;
   float* out;
@@ -78,7 +79,7 @@ struct GlobalJob {
   int patch, search, k, levels, cycles, n_shifts;
   int shifts[4];
   float ht_a, ht_b, tv_eps_rel;
-  float *vol_a, *vol_b, *vol_u;
+  float *vol_a, *vol_b;
   unsigned long long* num;
   int16_t* idx;
   uint16_t* shifted;
