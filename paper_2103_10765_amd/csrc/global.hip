@@ -534,17 +534,29 @@ __global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* _
     fden[i] = 0;
   }
   {
+    // all of a spin's loads in flight at once (kVals is a multiple of the
+    // block size)
+    static_assert(kVals % kGlThreads == 0, "whole rounds of the block");
+    constexpr int kIt = kVals / kGlThreads;
     const float scale = 1.0f / static_cast<float>(spins);
-    for (int i = threadIdx.x; i < kVals; i += blockDim.x) {
-      const int k = i / (N * N), a = (i / N) % N, b = i % N;
-      float v = 0.0f;
-      for (int h = 0; h < spins; ++h) {
-        const float* vh = vol + static_cast<size_t>(h) * K * hw;
-        v += scale * vh[static_cast<size_t>(wrap1(k + h, K)) * hw + static_cast<size_t>(wrap1(y0 + a + h, H)) * W +
-                        wrap1(x0 + b + h, W)];
+    float acc[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) acc[it] = 0.0f;
+    for (int h = 0; h < spins; ++h) {
+      const float* vh = vol + static_cast<size_t>(h) * K * hw;
+      float v[kIt];
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) {
+        const int i = threadIdx.x + it * kGlThreads;
+        const int k = i / (N * N), a = (i / N) % N, b = i % N;
+        v[it] = vh[static_cast<size_t>(wrap1(k + h, K)) * hw + static_cast<size_t>(wrap1(y0 + a + h, H)) * W +
+                   wrap1(x0 + b + h, W)];
       }
-      blk[i] = v;
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) acc[it] += scale * v[it];
     }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) blk[threadIdx.x + it * kGlThreads] = acc[it];
   }
   __syncthreads();
   double tv = 0.0;
