@@ -213,13 +213,25 @@ def global_bench(ctx, Zt, clean, sigma, steps=20):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    from paper_2103_10765_amd import gbm3d
+    gp = gbm3d.global_default_params()
     ms_g = timed(lambda: ctx.global_basic(Zt, sigma, out=out))
     p_g = O.psnr(out.cpu().numpy().astype(np.float64), clean)
     ms_b = timed(lambda: ctx.basic(Zt, sigma, out=out))
     p_b = O.psnr(out.cpu().numpy().astype(np.float64), clean)
+    # its largest kernel, the tile matching (one launch per translation),
+    # alone through its own entry point: exact distances, 3 FLOP per (pixel,
+    # displacement) as for the grouped matcher, on the fp64 vector ALU
+    ms_m = timed(lambda: ctx.global_match(Zt, gp))
+    flop = 3.0 * H * W * (gp.search * gp.search - 1)
+    tflops = flop / (ms_m * 1e-3) / 1e12
     mpx = H * W / 1e6
     return {"global_ms": ms_g, "global_mpix_s": mpx / (ms_g * 1e-3), "global_psnr_db": p_g,
-            "grouped_ms": ms_b, "grouped_mpix_s": mpx / (ms_b * 1e-3), "grouped_psnr_db": p_b}
+            "grouped_ms": ms_b, "grouped_mpix_s": mpx / (ms_b * 1e-3), "grouped_psnr_db": p_b,
+            "roofline": {"kernel": "gl_match_kernel", "bound": "alu", "avg_us": 1e3 * ms_m,
+                         "launches_per_call": gp.n_shifts, "work_per_launch": flop, "work_unit": "FLOP",
+                         "achieved": tflops, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / FP64_VALU_PEAK_TFLOPS}}
 
 
 def cpu_baseline(Z, sigma, size=320):
