@@ -63,6 +63,9 @@ CASES = [
     (96, 112, 50, 23, {}),
     (48, 64, 25, 24, {"patch": 8, "search": 15, "k": 8, "levels": 2, "cycles": 1, "shifts": (0,)}),
     (64, 64, 25, 25, {"k": 32, "search": 39, "shifts": (0, 4, 8)}),
+    # several cycle spins filtered in the same launches
+    (64, 48, 25, 26, {"cycles": 4, "levels": 1, "shifts": (0, 2)}),
+    (48, 80, 35, 27, {"cycles": 3, "shifts": (0, 4, 8, 12)}),
 ]
 
 
