@@ -137,6 +137,28 @@ def copy_bandwidth(gib=2, reps=5):
     return {"copy_GBps": gbps, "bytes": 2 * n}
 
 
+def unit_peaks(ctx, reps=5):
+    """Measured ceilings of the arithmetic units the kernels are read against:
+    the library's peak-rate probes (fp64 vector FMA, int8 and bf16 matrix
+    cores), 2048 workgroups of 256 threads with no memory traffic."""
+    import torch
+    from paper_2103_10765_amd import gbm3d
+    res = {}
+    for name, kind, iters in (("fp64_fma_TFLOPs", gbm3d.PROBE_FP64, 4096),
+                              ("int8_mfma_TOPs", gbm3d.PROBE_MFMA_I8, 1024),
+                              ("bf16_mfma_TFLOPs", gbm3d.PROBE_MFMA_BF16, 1024)):
+        sink, ops = ctx.probe(kind, 2048, iters)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.probe(kind, 2048, iters, sink=sink)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = ops * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    return res
+
+
 def pilot_conv_rate(ctx, n=32, size=512):
     """Matrix-core rate of the pilot network's convolutions on the evaluation
     batch shape (library-recorded events around each layer's launch)."""
@@ -470,10 +492,19 @@ def main():
         rec["pnp"] = pnp.bench(ctx)
         rec["global_stage1"] = global_bench(ctx, Zt, clean, sigma)
         mp = copy_bandwidth()
+        mp.update(unit_peaks(ctx))
         rec["measured_peaks"] = mp
+        measured = {"hbm": mp["copy_GBps"], "alu": mp["fp64_fma_TFLOPs"], "mfma": mp["int8_mfma_TOPs"]}
         for k in kernels.values():
             if k["bound"] == "hbm":
                 k["frac_of_measured_copy"] = k["achieved"] / mp["copy_GBps"]
+            k["frac_of_measured_peak"] = k["achieved"] / measured[k["bound"]]
+        roof["frac_of_measured_peak"] = roof["achieved"] / measured[roof["bound"]]
+        gr = rec["global_stage1"]["roofline"]
+        gr["frac_of_measured_peak"] = gr["achieved"] / mp["fp64_fma_TFLOPs"]
+        if "conv" in rec.get("pilot", {}):
+            c = rec["pilot"]["conv"]
+            c["frac_of_measured_peak"] = c["achieved_TFLOPs"] / mp["bf16_mfma_TFLOPs"]
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(Z, sigma)
     print(json.dumps(rec), flush=True)

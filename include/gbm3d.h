@@ -229,6 +229,23 @@ int gbm3d_denoise_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n,
  * evaluated in double from the float input; NaN -> 0.  Device pointers. */
 int gbm3d_quantize(gbm3d_ctx* ctx, const float* in, uint16_t* out, size_t n, void* stream);
 
+/* Peak-rate probes, for reading the kernels' achieved rates against measured
+ * ceilings: `blocks` workgroups of 256 threads run `iters` rounds of eight
+ * independent chains of one operation with no memory traffic, then write one
+ * float per thread to the device buffer sink (blocks * 256 floats, owned by
+ * the caller; the values carry no meaning).  kind GBM3D_PROBE_FP64: fp64
+ * vector FMA (the shift-wise and global matchers' unit); GBM3D_PROBE_MFMA_I8:
+ * v_mfma_i32_16x16x64_i8 (the correlation matcher's); GBM3D_PROBE_MFMA_BF16:
+ * v_mfma_f32_16x16x32_bf16 (the pilot's).  Asynchronous on stream; time it
+ * with events.  blocks and iters in [1, 2^20].  gbm3d_probe_ops returns the
+ * arithmetic operations of such a launch (a fused multiply-add counts 2), or
+ * 0 for an unknown kind. */
+#define GBM3D_PROBE_FP64 0
+#define GBM3D_PROBE_MFMA_I8 1
+#define GBM3D_PROBE_MFMA_BF16 2
+int gbm3d_probe(gbm3d_ctx* ctx, int kind, int blocks, int iters, float* sink, void* stream);
+double gbm3d_probe_ops(int kind, int blocks, int iters);
+
 /* ---------------------------------------------------------------------------
  * Learned pilot: a six-layer 3x3 convolutional network (2 -> 32 -> 32 -> 32 ->
  * 32 -> 32 -> 1 channels, ReLU after the first five, zero "same" padding,

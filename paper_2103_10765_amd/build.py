@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgbm3d.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["bm.hip", "bm_corr.hip", "stack.hip", "group.hip", "global.hip", "pilot.hip", "capi.cpp"]
+SOURCES = ["bm.hip", "bm_corr.hip", "stack.hip", "group.hip", "global.hip", "pilot.hip", "microbench.hip", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -49,7 +49,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

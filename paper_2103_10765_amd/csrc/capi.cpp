@@ -1024,6 +1024,20 @@ int gbm3d_quantize(gbm3d_ctx* ctx, const float* in, uint16_t* out, size_t n, voi
   return GBM3D_OK;
 }
 
+int gbm3d_probe(gbm3d_ctx* ctx, int kind, int blocks, int iters, float* sink, void* stream) {
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (kind < GBM3D_PROBE_FP64 || kind > GBM3D_PROBE_MFMA_BF16) return fail(ctx, GBM3D_EINVAL, "probe kind %d", kind);
+  if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
+    return fail(ctx, GBM3D_EINVAL, "probe blocks %d / iters %d out of [1, 2^20]", blocks, iters);
+  if (!sink) return fail(ctx, GBM3D_EINVAL, "NULL sink");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  HIP_TRY(ctx, gbm3d::launch_microbench(kind, blocks, iters, sink, static_cast<hipStream_t>(stream)), "probe launch");
+  return GBM3D_OK;
+}
+
+double gbm3d_probe_ops(int kind, int blocks, int iters) { return gbm3d::microbench_ops(kind, blocks, iters); }
+
 // ---------------------------------------------------------------------------
 // learned pilot
 // ---------------------------------------------------------------------------

@@ -90,4 +90,11 @@ hipError_t launch_global_match(const uint16_t* img, int H, int W, int patch, int
                                hipStream_t st);
 hipError_t launch_global_basic(const GlobalJob& job, hipStream_t st);
 
+// Peak-rate probes (kind 0 = fp64 vector FMA, 1 = int8 MFMA, 2 = bf16 MFMA):
+// blocks of 256 threads, iters rounds each, one float per thread to sink.
+// microbench_ops gives the arithmetic operations of such a launch (an FMA or
+// multiply-accumulate counts 2).
+hipError_t launch_microbench(int kind, int blocks, int iters, float* sink, hipStream_t st);
+double microbench_ops(int kind, int blocks, int iters);
+
 }  // namespace gbm3d

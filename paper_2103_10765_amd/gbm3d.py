@@ -20,6 +20,7 @@ BATCH_GRAPH, BATCH_BASIC_ONLY = 1, 2
 W_TV, W_NNZ, W_UNIT = 0, 1, 2
 STACK_BIOR15, STACK_DCT = 0, 1
 BM_AUTO, BM_SHIFT, BM_CORR = 0, 1, 2
+PROBE_FP64, PROBE_MFMA_I8, PROBE_MFMA_BF16 = 0, 1, 2
 
 
 class Params(ctypes.Structure):
@@ -111,6 +112,8 @@ _SIGNATURES = {
     "gbm3d_global_default_params": (None, [ctypes.POINTER(GlobalParams)]),
     "gbm3d_global_basic": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(GlobalParams), _P, _P]),
     "gbm3d_global_match": (_I, [_P, _P, _I, _I, ctypes.POINTER(GlobalParams), _P, _P]),
+    "gbm3d_probe": (_I, [_P, _I, _I, _I, _P, _P]),
+    "gbm3d_probe_ops": (ctypes.c_double, [_I, _I, _I]),
 }
 
 
@@ -413,6 +416,17 @@ class Context:
         self._check(lib().gbm3d_quantize(self._h, _dev(x, torch.float32, "in"), _dev(out, torch.uint16, "out"),
                                          x.numel(), _stream(stream)))
         return out
+
+    def probe(self, kind: int, blocks: int, iters: int, sink=None, stream=None):
+        """One peak-rate probe launch (PROBE_FP64 / PROBE_MFMA_I8 /
+        PROBE_MFMA_BF16); returns (sink, arithmetic operations of the launch)."""
+        if sink is None:
+            sink = torch.empty(blocks * 256, dtype=torch.float32, device=torch.device("cuda", self.device))
+        if sink.numel() < blocks * 256:
+            raise ValueError("sink needs blocks * 256 floats")
+        self._check(lib().gbm3d_probe(self._h, kind, blocks, iters, _dev(sink, torch.float32, "sink"),
+                                      _stream(stream)))
+        return sink, float(lib().gbm3d_probe_ops(kind, blocks, iters))
 
 
 _default_ctx: dict[int, Context] = {}

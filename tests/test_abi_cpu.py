@@ -103,3 +103,16 @@ def test_create_without_device_fails_cleanly(G):
     h = ctypes.c_void_p()
     s = G.lib().gbm3d_create(ctypes.byref(h), 0)
     assert s in (G.EHIP, G.EINVAL) and not h.value
+
+
+def test_probe_operation_counts(G):
+    """Arithmetic operations of a peak-rate probe launch: 8 chains per thread
+    (fp64 FMA) or per wave (one 16x16x64 int8 / 16x16x32 bf16 MFMA each), a
+    multiply-add counting 2; unknown kinds give 0."""
+    L = G.lib()
+    blocks, iters = 3, 5
+    threads, waves = blocks * 256, blocks * 4
+    assert L.gbm3d_probe_ops(G.PROBE_FP64, blocks, iters) == threads * iters * 8 * 2
+    assert L.gbm3d_probe_ops(G.PROBE_MFMA_I8, blocks, iters) == waves * iters * 8 * 16 * 16 * 64 * 2
+    assert L.gbm3d_probe_ops(G.PROBE_MFMA_BF16, blocks, iters) == waves * iters * 8 * 16 * 16 * 32 * 2
+    assert L.gbm3d_probe_ops(7, blocks, iters) == 0.0
