@@ -188,7 +188,7 @@ def sigma_bench(ctx, p, Zt_shape, steps=50):
     """The 512^2 image at sigma 15, 25 and 50 / 255: Mpixel/s and PSNR."""
     import numpy as np
     import torch
-    from oracle import gbm3d_oracle as O
+    from paper_2103_10765_amd.gbm3d import psnr_db
     from paper_2103_10765_amd import synth
     H, W = Zt_shape
     res = {}
@@ -208,8 +208,8 @@ def sigma_bench(ctx, p, Zt_shape, steps=50):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         res[f"{s255:g}"] = {"mpix_s": H * W / (ms * 1e-3) / 1e6,
-                            "psnr_db": O.psnr(out.cpu().numpy().astype(np.float64), clean),
-                            "psnr_noisy_db": O.psnr(Z / 65535.0, clean)}
+                            "psnr_db": psnr_db(out.cpu().numpy().astype(np.float64), clean),
+                            "psnr_noisy_db": psnr_db(Z / 65535.0, clean)}
     return res
 
 
@@ -219,7 +219,7 @@ def global_bench(ctx, Zt, clean, sigma, steps=20):
     on the same image: Mpixel/s and PSNR of each."""
     import numpy as np
     import torch
-    from oracle import gbm3d_oracle as O
+    from paper_2103_10765_amd.gbm3d import psnr_db
     H, W = Zt.shape
     out = torch.empty((H, W), dtype=torch.float32, device="cuda")
 
@@ -238,9 +238,9 @@ def global_bench(ctx, Zt, clean, sigma, steps=20):
     from paper_2103_10765_amd import gbm3d
     gp = gbm3d.global_default_params()
     ms_g = timed(lambda: ctx.global_basic(Zt, sigma, out=out))
-    p_g = O.psnr(out.cpu().numpy().astype(np.float64), clean)
+    p_g = psnr_db(out.cpu().numpy().astype(np.float64), clean)
     ms_b = timed(lambda: ctx.basic(Zt, sigma, out=out))
-    p_b = O.psnr(out.cpu().numpy().astype(np.float64), clean)
+    p_b = psnr_db(out.cpu().numpy().astype(np.float64), clean)
     # its largest kernel, the tile matching (one launch per translation),
     # alone through its own entry point: exact distances, 3 FLOP per (pixel,
     # displacement) as for the grouped matcher, on the fp64 vector ALU
@@ -430,7 +430,7 @@ def main():
     import numpy as np
     import torch
 
-    from oracle import gbm3d_oracle as O
+    from paper_2103_10765_amd.gbm3d import psnr_db
     from paper_2103_10765_amd import gbm3d, synth
 
     sigma = args.sigma / 255.0
@@ -467,7 +467,7 @@ def main():
     value = H * W / (ms * 1e-3) / 1e6
 
     Y = out.cpu().numpy().astype(np.float64)
-    psnr = O.psnr(Y, clean)
+    psnr = psnr_db(Y, clean)
 
     # per-kernel durations: the same steps with library-recorded events
     ctx.timing(True)
@@ -523,7 +523,7 @@ def main():
                                "patch 8, step 3, search 39, K 16/32", "image_seed": 2,
                    "block_matching": tuned if tuned else args.bm_method},
         "psnr_db": psnr,
-        "psnr_noisy_db": O.psnr(Z / 65535.0, clean),
+        "psnr_noisy_db": psnr_db(Z / 65535.0, clean),
         "psnr_gap_db": None,
         "roofline": roof,
         "kernels": kernels,
