@@ -281,9 +281,14 @@ __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __r
   constexpr int kRows = T::kFwdRows, kCols = T::kFwdCols, kHalfCols = kCols / 2;
   __shared__ float in_s[2][kRows][2][kHalfCols];
   __shared__ float xs[2][kRows][2 * TX];
-  // per window row / column: the (unspun) volume coordinate, and with GATHER
-  // the tile offset of the spun coordinate
-  __shared__ int row_at[kRows], col_at[kCols], row_tile[GATHER ? kRows : 1], col_tile[GATHER ? kCols : 1];
+  // per window row / column: the volume coordinate (with GATHER: of the
+  // unspun volume V, and which of the window's tile rows / columns holds it)
+  constexpr int kTileRows = (kRows + 2 * N - 2) / N, kTileCols = (kCols + 2 * N - 2) / N;
+  static_assert(kRows + kCols + 2 * kTileRows * kTileCols <= kGlThreads, "one table entry per thread");
+  __shared__ int row_at[kRows], col_at[kCols], row_lt[GATHER ? kRows : 1], col_lt[GATHER ? kCols : 1];
+  // with GATHER: the match displacement (dy, dx) of slices 2 kp + j of every
+  // tile the window touches
+  __shared__ int disp_y[GATHER ? 2 : 1][kTileRows][kTileCols], disp_x[GATHER ? 2 : 1][kTileRows][kTileCols];
   const int hy = Ly >> 1, hx = Lx >> 1, hk = Lk >> 1;
   const int h = blockIdx.z / hk, kp = blockIdx.z - h * hk;
   const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY;
@@ -292,56 +297,48 @@ __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __r
   dst += static_cast<size_t>(h) * K * hw;
   const float c = 0.70710678118654752f;
   const int tid = threadIdx.x;
-  if (tid < kRows) {
-    const int y = wrap(2 * cy0 - 4 + tid, Ly);
-    if constexpr (GATHER) {
-      const int ys = wrap1(y - h, H);
-      row_at[tid] = ys;
-      row_tile[tid] = (ys / N) * (W / N);
-    } else {
-      row_at[tid] = y;
+  if constexpr (GATHER) {
+    // V_h[k][y][x] = V[(k - h) mod K][(y - h) mod H][(x - h) mod W]: the
+    // window's rows (columns) are consecutive mod H (W) from ys0 (xs0)
+    const int ys0 = wrap1(wrap(2 * cy0 - 4, Ly) - h, H), xs0 = wrap1(wrap(2 * cx0 - 4, Lx) - h, W);
+    if (tid < kRows) {
+      row_at[tid] = wrap(ys0 + tid, H);
+      row_lt[tid] = (ys0 % N + tid) / N;
+    } else if (tid < kRows + kCols) {
+      const int i = tid - kRows;
+      col_at[i] = wrap(xs0 + i, W);
+      col_lt[i] = (xs0 % N + i) / N;
+    } else if (tid < kRows + kCols + 2 * kTileRows * kTileCols) {
+      const int t = tid - kRows - kCols;
+      const int j = t / (kTileRows * kTileCols), lr = (t / kTileCols) % kTileRows, lc = t % kTileCols;
+      const int TH = H / N, TW = W / N;
+      const int trow = (ys0 / N + lr) % TH, tcol = (xs0 / N + lc) % TW;
+      const int rank = idx[(static_cast<size_t>(trow) * TW + tcol) * K + wrap1(2 * kp + j - h, K)];
+      const int q = rank / S;
+      disp_y[j][lr][lc] = q - S / 2;
+      disp_x[j][lr][lc] = rank - q * S - S / 2;
     }
-  } else if (tid < kRows + kCols) {
-    const int x = wrap(2 * cx0 - 4 + tid - kRows, Lx);
-    if constexpr (GATHER) {
-      const int xs = wrap1(x - h, W);
-      col_at[tid - kRows] = xs;
-      col_tile[tid - kRows] = xs / N;
-    } else {
-      col_at[tid - kRows] = x;
+  } else {
+    if (tid < kRows) {
+      row_at[tid] = wrap(2 * cy0 - 4 + tid, Ly);
+    } else if (tid < kRows + kCols) {
+      col_at[tid - kRows] = wrap(2 * cx0 - 4 + tid - kRows, Lx);
     }
   }
   __syncthreads();
   float v0[T::kFwdIters], v1[T::kFwdIters];
   if constexpr (GATHER) {
     // V[k'][ys][xs] = z at (ys, xs) + the k'-th match displacement of its tile
-    const int R = S / 2;
-    const float inv_s = 1.0f / static_cast<float>(S);
-    const int16_t* idx0 = idx + wrap1(2 * kp - h, K);
-    const int16_t* idx1 = idx + wrap1(2 * kp + 1 - h, K);
-    int r0[T::kFwdIters], r1[T::kFwdIters];
 #pragma unroll
     for (int it = 0; it < T::kFwdIters; ++it) {
       const int e = tid + it * kGlThreads;
       if (e < kRows * kCols) {
         const int r = e / kCols, col = e - r * kCols;
-        const size_t g = static_cast<size_t>(row_tile[r] + col_tile[col]) * K;
-        r0[it] = idx0[g];
-        r1[it] = idx1[g];
-      }
-    }
-    auto pixel = [&](int rank, int ys, int xs) {
-      const int q = static_cast<int>((static_cast<float>(rank) + 0.5f) * inv_s);  // rank / S, exact for rank < S^2
-      const int y = wrap1(ys + q - R, H), x = wrap1(xs + (rank - q * S) - R, W);
-      return static_cast<float>(img[static_cast<size_t>(y) * W + x]) * (1.0f / 65535.0f);
-    };
-#pragma unroll
-    for (int it = 0; it < T::kFwdIters; ++it) {
-      const int e = tid + it * kGlThreads;
-      if (e < kRows * kCols) {
-        const int r = e / kCols, col = e - r * kCols;
-        v0[it] = pixel(r0[it], row_at[r], col_at[col]);
-        v1[it] = pixel(r1[it], row_at[r], col_at[col]);
+        const int ys = row_at[r], xs = col_at[col], lr = row_lt[r], lc = col_lt[col];
+        const size_t o0 = static_cast<size_t>(wrap1(ys + disp_y[0][lr][lc], H)) * W + wrap1(xs + disp_x[0][lr][lc], W);
+        const size_t o1 = static_cast<size_t>(wrap1(ys + disp_y[1][lr][lc], H)) * W + wrap1(xs + disp_x[1][lr][lc], W);
+        v0[it] = static_cast<float>(img[o0]) * (1.0f / 65535.0f);
+        v1[it] = static_cast<float>(img[o1]) * (1.0f / 65535.0f);
       }
     }
   } else {
