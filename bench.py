@@ -103,6 +103,24 @@ def measured_traffic(kernel):
     return float(fetch_kib) / fetch_scale + float(write_kib) / write_scale
 
 
+SQ_FILE = os.path.join(ROOT, "profiles", "sq_counters_denoise_512.md")
+N_SIMD, CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs; a wave64 VALU instruction takes 4 SIMD cycles
+
+
+def measured_valu_insts(variant, kernel):
+    """SQ_INSTS_VALU per dispatch of one kernel variant (e.g.
+    'bm_corr_kernel<16, 2, 2, false>') from the committed counter summary;
+    None when it is missing or the group's sources changed since."""
+    if not os.path.exists(SQ_FILE):
+        return None
+    with open(SQ_FILE) as fh:
+        for line in fh:
+            parts = line.strip().split("|")
+            if len(parts) == 4 and parts[0] == "@sq" and parts[1] == variant:
+                return float(parts[3]) if parts[2] == source_digest(kernel) else None
+    return None
+
+
 def copy_calibration(mib):
     """One plain device-to-device copy of `mib` MiB (the reference kernel for
     scaling FETCH_SIZE / WRITE_SIZE to bytes)."""
@@ -502,6 +520,17 @@ def main():
     else:
         bm_method = args.bm_method
     work = algorithmic_work(H, W, p.search, p.k_ht, p.k_wiener, bm_method)
+    # the kernel variants this run launched, for the instruction counters
+    def bm_variant(K):
+        t = tuned.get(f"K{K}")
+        if not t:
+            return None
+        s = t["split"]
+        return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
+    variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
+                "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"] * 2,
+                "group_ht": [f"group_ht_kernel<{p.k_ht}, false>"],
+                "group_wiener": [f"group_wiener_kernel<{p.k_wiener}, false>"], "reduce": ["reduce_kernel<false>"] * 2}
     for name, k in kernels.items():
         bound, amount, unit = work[name]
         peak, punit, scale = PEAKS[bound]
@@ -510,12 +539,18 @@ def main():
         k["unit"] = punit
         k["frac"] = k["achieved"] / peak
         k["traffic_bytes"] = measured_traffic(name)
+        # vector-instruction issue: committed SQ_INSTS_VALU of the same
+        # variants x 4 cycles over every SIMD's cycles of the measured time
+        insts = [measured_valu_insts(v, name) if v else None for v in variants.get(name, [])]
+        if insts and None not in insts:
+            k["valu_issue_frac"] = sum(insts) * 4 / (N_SIMD * CLOCK_HZ * len(insts) * k["avg_us"] * 1e-6)
     dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
     bound, amount, unit = work[dom]
     peak, punit, scale = PEAKS[bound]
     roof = {"bound": bound, "kernel": dom, "achieved": kernels[dom]["achieved"], "peak": peak, "unit": punit,
             "frac": kernels[dom]["frac"], "traffic": measured_traffic(dom), "avg_us": kernels[dom]["avg_us"],
-            "work_per_launch": amount, "work_unit": unit}
+            "work_per_launch": amount, "work_unit": unit,
+            "valu_issue_frac": kernels[dom].get("valu_issue_frac")}
 
     rec = {
         "metric": "Mpixel/s two-stage denoise at sigma=25 (plain vs learned pilot) + PSNR gap, 1 GPU",
