@@ -286,6 +286,37 @@ def global_bench(ctx, Zt, clean, sigma, steps=20):
                          "frac": tflops / FP64_VALU_PEAK_TFLOPS}}
 
 
+def tiled_bench(ctx, sigma, steps=5):
+    """The two-stage denoise on 256 + 8 sub-images (stride 256, both stages
+    of all sub-images in one batched call each) beside the whole-image call,
+    at 512^2 and on the 4096^2 edge-rich image: ms, Mpixel/s and PSNR."""
+    import numpy as np
+    import torch
+    from paper_2103_10765_amd import synth, tiled
+    from paper_2103_10765_amd.gbm3d import psnr_db
+    res = {"size": tiled.SIZE, "stride": tiled.STRIDE}
+    for name, (clean, Z) in (("512", synth.make_case(512, 512, sigma, 2)),
+                             ("4096", synth.large_image_case(4096, sigma, 4))):
+        Zt = torch.from_numpy(Z).cuda()
+        row = {}
+        for mode, fn in (("tiled", lambda: tiled.denoise(ctx, Zt, sigma)[0]), ("whole", lambda: ctx.denoise(Zt, sigma))):
+            out = fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            row[mode] = {"ms": ms, "mpix_s": Z.size / (ms * 1e-3) / 1e6,
+                         "psnr_db": psnr_db(out.cpu().numpy().astype(np.float64), clean)}
+        res[name] = row
+        del Zt
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(Z, sigma, size=320):
     """The CPU oracle (one thread) on a size x size crop of the same image."""
     import numpy as np
@@ -588,6 +619,7 @@ def main():
         from paper_2103_10765_amd import pnp
         rec["pnp"] = pnp.bench(ctx)
         rec["global_stage1"] = global_bench(ctx, Zt, clean, sigma)
+        rec["tiled_sub_images"] = tiled_bench(ctx, sigma)
         mp = copy_bandwidth()
         mp.update(unit_peaks(ctx))
         rec["measured_peaks"] = mp
