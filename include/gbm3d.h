@@ -197,8 +197,11 @@ typedef struct {
 
 void gbm3d_global_default_params(gbm3d_global_params* p);
 
-/* noisy: device u16 [H][W]; out: device float [H][W].  H, W: multiples of
- * patch, at least max(search, patch).  The context keeps 2 * cycles float
+/* noisy: device u16 [H][W]; out: device float [H][W].  H, W in
+ * [max(search, patch), 32768]; sides that are not multiples of patch are
+ * handled as the paper does (Sec. 3.1): the image is extended at the bottom
+ * and right with mirrored values (edge pixel repeated first) to the next
+ * multiples, filtered, and the estimate cropped back to H x W.  The context keeps 2 * cycles float
  * volumes of k H W entries (all cycle spins are filtered together) and 2 H W
  * 64-bit sums as workspace; GBM3D_ENOMEM when they cannot be allocated. */
 int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
@@ -207,7 +210,8 @@ int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, floa
 /* The tile matching of gbm3d_global_basic alone (S^K_pq of Sec. 3.1 for the
  * reference tiles): idx device int16 [(H/patch)(W/patch)][k], tiles in raster
  * order, displacement ranks r = (dy+R)*search + (dx+R), slot 0 the tile
- * itself, then ascending (distance, rank). */
+ * itself, then ascending (distance, rank).  H and W must be multiples of
+ * patch here. */
 int gbm3d_global_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W,
                        const gbm3d_global_params* params, int16_t* idx, void* stream);
 

@@ -37,7 +37,8 @@ design notes):
   sigma * N^2 * K;
 * the translations are h = 0 and N/4 along both axes (two repeated trials,
   Sec. 5; eq. firstEst lists N/2 as a third), the cycle spins h = 0, 1;
-* the image sides must be multiples of N (the paper pads otherwise).
+* image sides that are not multiples of N are mirror-padded (mirror_pad), as
+  the paper does, and the estimate is cropped back.
 """
 from __future__ import annotations
 
@@ -193,8 +194,22 @@ def phi(Z: np.ndarray, sigma: float, p: GlobalParams = GDEFAULT) -> np.ndarray:
     return num / den
 
 
+def mirror_pad(Z: np.ndarray, N: int) -> np.ndarray:
+    """Z extended past its bottom and right edges with mirrored values up to
+    the next multiples of N (Sec. 3.1: sizes that are not multiples of the
+    block size are padded with mirrored image values).  Reading: the edge
+    pixel is repeated first, row (column) L + i takes row L - 1 - i, and only
+    the ends are padded."""
+    H, W = Z.shape
+    return np.pad(Z, ((0, (-H) % N), (0, (-W) % N)), mode="symmetric")
+
+
 def global_basic(Z: np.ndarray, sigma: float, p: GlobalParams = GDEFAULT) -> np.ndarray:
-    """Y_f = mean over translations h of S_{-h} phi(S_h Z)."""
+    """Y_f = mean over translations h of S_{-h} phi(S_h Z); an image whose
+    sides are not multiples of N is filtered mirror-padded and cropped."""
+    H, W = Z.shape
+    if H % p.patch or W % p.patch:
+        return global_basic(mirror_pad(Z, p.patch), sigma, p)[:H, :W]
     Y = np.zeros(Z.shape)
     for h in p.shifts:
         Y += np.roll(phi(np.roll(Z, (h, h), axis=(0, 1)), sigma, p), (-h, -h), axis=(0, 1))

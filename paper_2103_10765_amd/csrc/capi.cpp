@@ -66,7 +66,7 @@ struct gbm3d_ctx {
   std::string err;
   Buffer stack_a, stack_b, idx, partials, basic, q, norm;
   // global stage 1
-  Buffer gl_a, gl_b, gl_num, gl_idx, gl_shift;
+  Buffer gl_a, gl_b, gl_num, gl_idx, gl_shift, gl_pad, gl_out;
   // block-matching choices per (K, shape class)
   std::map<std::pair<int, int>, TuneEntry> tuned;
   // batches
@@ -639,7 +639,7 @@ void gbm3d_destroy(gbm3d_ctx* ctx) {
     drop_graph(ctx);
     for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->norm, &ctx->batch_ws,
                       &ctx->batch_table, &ctx->pilot_w, &ctx->pilot_act, &ctx->pilot_part, &ctx->gl_a, &ctx->gl_b,
-                      &ctx->gl_num, &ctx->gl_idx, &ctx->gl_shift})
+                      &ctx->gl_num, &ctx->gl_idx, &ctx->gl_shift, &ctx->gl_pad, &ctx->gl_out})
       if (b->p) (void)hipFree(b->p);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
@@ -832,7 +832,8 @@ void gbm3d_global_default_params(gbm3d_global_params* p) {
 
 namespace {
 
-int resolve_global(gbm3d_ctx* ctx, const gbm3d_global_params* params, int H, int W, gbm3d_global_params& p) {
+int resolve_global(gbm3d_ctx* ctx, const gbm3d_global_params* params, int H, int W, gbm3d_global_params& p,
+                   bool any_size) {
   gbm3d_global_default_params(&p);
   if (params) {
     if (params->struct_size != sizeof(gbm3d_global_params))
@@ -856,8 +857,10 @@ int resolve_global(gbm3d_ctx* ctx, const gbm3d_global_params* params, int H, int
   if (!(p.ht_a >= 0.0f) || !(p.ht_b >= 0.0f) || !(p.tv_eps_rel > 0.0f))
     return fail(ctx, GBM3D_EINVAL, "global thresholds and eps must be non-negative (eps > 0)");
   const int lo = p.search > p.patch ? p.search : p.patch;
-  if (H < lo || W < lo || H > 32768 || W > 32768 || H % p.patch || W % p.patch)
-    return fail(ctx, GBM3D_EINVAL, "image %dx%d must be multiples of %d in [%d, 32768]", H, W, p.patch, lo);
+  if (H < lo || W < lo || H > 32768 || W > 32768)
+    return fail(ctx, GBM3D_EINVAL, "image %dx%d: sides must be in [%d, 32768]", H, W, lo);
+  if (!any_size && (H % p.patch || W % p.patch))
+    return fail(ctx, GBM3D_EINVAL, "image %dx%d: sides must be multiples of %d", H, W, p.patch);
   return GBM3D_OK;
 }
 
@@ -868,7 +871,7 @@ int gbm3d_global_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, const 
   if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
   if (!img || !idx) return fail(ctx, GBM3D_EINVAL, "NULL image or index pointer");
   gbm3d_global_params p;
-  CHECK(resolve_global(ctx, params, H, W, p));
+  CHECK(resolve_global(ctx, params, H, W, p, false));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
   HIP_TRY(ctx, gbm3d::launch_global_match(img, H, W, p.patch, p.search, p.k, idx, static_cast<hipStream_t>(stream)),
@@ -882,21 +885,33 @@ int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, floa
   if (!noisy || !out) return fail(ctx, GBM3D_EINVAL, "NULL image or output pointer");
   CHECK(check_sigma(ctx, sigma));
   gbm3d_global_params p;
-  CHECK(resolve_global(ctx, params, H, W, p));
+  CHECK(resolve_global(ctx, params, H, W, p, true));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
-  const size_t hw = static_cast<size_t>(H) * W;
-  const size_t vb = gbm3d::global_volume_bytes(H, W, p.k);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // sides that are not multiples of the tile side: filter the image
+  // mirror-padded at the bottom and right, then crop (Sec. 3.1)
+  const int Hp = (H + p.patch - 1) / p.patch * p.patch, Wp = (W + p.patch - 1) / p.patch * p.patch;
+  const bool padded = Hp != H || Wp != W;
+  const size_t hw = static_cast<size_t>(Hp) * Wp;
+  const size_t vb = gbm3d::global_volume_bytes(Hp, Wp, p.k);
+  if (padded) {
+    CHECK(ensure(ctx, ctx->gl_pad, hw * sizeof(uint16_t), "padded image"));
+    CHECK(ensure(ctx, ctx->gl_out, hw * sizeof(float), "padded estimate"));
+    HIP_TRY(ctx,
+            gbm3d::launch_global_pad(noisy, H, W, static_cast<uint16_t*>(ctx->gl_pad.p), Hp, Wp, st),
+            "mirror padding launch");
+  }
   CHECK(ensure(ctx, ctx->gl_a, p.cycles * vb, "global volumes"));
   CHECK(ensure(ctx, ctx->gl_b, p.cycles * vb, "global volumes"));
   CHECK(ensure(ctx, ctx->gl_num, 2 * hw * sizeof(unsigned long long), "global sums"));
   CHECK(ensure(ctx, ctx->gl_idx, (hw / (p.patch * p.patch)) * p.k * sizeof(int16_t), "global matches"));
   CHECK(ensure(ctx, ctx->gl_shift, hw * sizeof(uint16_t), "translated image"));
   gbm3d::GlobalJob j{};
-  j.noisy = noisy;
-  j.out = out;
-  j.H = H;
-  j.W = W;
+  j.noisy = padded ? static_cast<const uint16_t*>(ctx->gl_pad.p) : noisy;
+  j.out = padded ? static_cast<float*>(ctx->gl_out.p) : out;
+  j.H = Hp;
+  j.W = Wp;
   j.sigma = sigma;
   j.patch = p.patch;
   j.search = p.search;
@@ -913,9 +928,14 @@ int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, floa
   j.num = static_cast<unsigned long long*>(ctx->gl_num.p);
   j.idx = static_cast<int16_t*>(ctx->gl_idx.p);
   j.shifted = static_cast<uint16_t*>(ctx->gl_shift.p);
-  hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(ctx, timed(ctx, "global_basic", st, [&] { return gbm3d::launch_global_basic(j, st); }),
           "global stage 1 launch");
+  if (padded)
+    HIP_TRY(ctx,
+            hipMemcpy2DAsync(out, static_cast<size_t>(W) * sizeof(float), ctx->gl_out.p,
+                             static_cast<size_t>(Wp) * sizeof(float), static_cast<size_t>(W) * sizeof(float), H,
+                             hipMemcpyDeviceToDevice, st),
+            "crop copy");
   return GBM3D_OK;
 }
 

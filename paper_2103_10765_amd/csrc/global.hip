@@ -211,6 +211,20 @@ __device__ __forceinline__ int wrap(int j, int L) {
   return j;
 }
 
+// dst [Hp][Wp]: img extended past its bottom and right edges with mirrored
+// values, the edge pixel repeated first (row / column L + i reads L - 1 - i;
+// Hp - H <= H and Wp - W <= W)
+__global__ void gl_mirror_pad_kernel(const uint16_t* __restrict__ img, int H, int W, uint16_t* __restrict__ dst,
+                                     int Hp, int Wp) {
+  const size_t n = static_cast<size_t>(Hp) * Wp;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int y = static_cast<int>(i / Wp), x = static_cast<int>(i - static_cast<size_t>(y) * Wp);
+    const int ys = y < H ? y : 2 * H - 1 - y, xs = x < W ? x : 2 * W - 1 - x;
+    dst[i] = img[static_cast<size_t>(ys) * W + xs];
+  }
+}
+
 // out[y][x] = img[(y - t) mod H][(x - t) mod W]  (S_t of the image)
 __global__ void gl_roll_kernel(const uint16_t* __restrict__ img, int H, int W, int t, uint16_t* __restrict__ out) {
   const size_t n = static_cast<size_t>(H) * W;
@@ -686,6 +700,12 @@ hipError_t launch_global_match(const uint16_t* img, int H, int W, int patch, int
   if (patch == 8 && k == 8) return match_nk<8, 8>(img, H, W, search, idx, st);
   if (patch == 8 && k == 32) return match_nk<8, 32>(img, H, W, search, idx, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_global_pad(const uint16_t* img, int H, int W, uint16_t* dst, int Hp, int Wp, hipStream_t st) {
+  hipLaunchKernelGGL(gl_mirror_pad_kernel, dim3(grid_for(static_cast<size_t>(Hp) * Wp)), dim3(kGlThreads), 0, st, img,
+                     H, W, dst, Hp, Wp);
+  return hipGetLastError();
 }
 
 hipError_t launch_global_basic(const GlobalJob& j, hipStream_t st) {

@@ -89,6 +89,9 @@ size_t global_volume_bytes(int H, int W, int K);
 hipError_t launch_global_match(const uint16_t* img, int H, int W, int patch, int search, int k, int16_t* idx,
                                hipStream_t st);
 hipError_t launch_global_basic(const GlobalJob& job, hipStream_t st);
+// dst [Hp][Wp] = img [H][W] mirror-padded at the bottom and right (edge pixel
+// repeated first); H <= Hp <= 2 H, W <= Wp <= 2 W
+hipError_t launch_global_pad(const uint16_t* img, int H, int W, uint16_t* dst, int Hp, int Wp, hipStream_t st);
 
 // Peak-rate probes (kind 0 = fp64 vector FMA, 1 = int8 MFMA, 2 = bf16 MFMA):
 // blocks of 256 threads, iters rounds each, one float per thread to sink.

@@ -99,3 +99,27 @@ def test_global_beats_noise_and_matches_grouped_quality():
     Yb = O.basic_estimate(Z, SIG)
     assert O.psnr(Yg, clean) > O.psnr(Z / 65535.0, clean) + 8.0
     assert O.psnr(Yg, clean) > O.psnr(Yb, clean) - 0.5
+
+
+def test_mirror_pad_repeats_the_edge_then_mirrors():
+    """Rows / columns past the end read the image backwards from its last
+    row / column (explicit loop); sizes already multiples are unchanged."""
+    Z = np.arange(5 * 7, dtype=np.uint16).reshape(5, 7)
+    P = G.mirror_pad(Z, 4)
+    assert P.shape == (8, 8)
+    for y in range(8):
+        for x in range(8):
+            ys = y if y < 5 else 2 * 5 - 1 - y
+            xs = x if x < 7 else 2 * 7 - 1 - x
+            assert P[y, x] == Z[ys, xs]
+    assert np.array_equal(G.mirror_pad(P, 4), P)
+
+
+def test_non_multiple_sizes_keep_constants():
+    """A constant image of a size that is not a multiple of the tile side
+    comes back constant and of its own size."""
+    Z = np.full((37, 45), 20000, dtype=np.uint16)
+    p = G.GDEFAULT.with_(patch=8, search=9, k=8, levels=2, shifts=(0,))
+    Y = G.global_basic(Z, 20 / 255, p)
+    assert Y.shape == (37, 45)
+    assert np.allclose(Y, 20000 / 65535, atol=1e-9)

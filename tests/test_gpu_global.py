@@ -116,6 +116,26 @@ def test_global_full_size(torch, G, ctx):
 
 
 def test_global_rejects_bad_shapes(G, ctx, torch):
-    Z = up(torch, np.zeros((50, 64), dtype=np.uint16))
+    """Sides below the search window are refused; the tile matching alone
+    still needs multiples of the tile side."""
     with pytest.raises(G.GBM3DError):
-        ctx.global_basic(Z, SIG)
+        ctx.global_basic(up(torch, np.zeros((30, 64), dtype=np.uint16)), SIG)
+    with pytest.raises(G.GBM3DError):
+        ctx.global_match(up(torch, np.zeros((50, 64), dtype=np.uint16)))
+
+
+@pytest.mark.parametrize("H,W,s,seed,ov", [(50, 64, 25, 28, {}), (70, 93, 25, 29, {}),
+                                            (45, 61, 35, 30, {"patch": 8, "search": 15, "k": 8, "levels": 2})])
+def test_global_parity_mirror_padded(torch, G, ctx, H, W, s, seed, ov):
+    """Sides that are not multiples of the tile side: mirror padding at the
+    bottom and right, filtering, cropping; against the oracle's."""
+    say("global basic padded", H, W, s, ov)
+    clean, Z = synth.make_case(H, W, s / 255, seed)
+    gp = G.global_default_params(**ov)
+    Yg = ctx.global_basic(up(torch, Z), s / 255, gp).cpu().numpy().astype(np.float64)
+    Yo = GO.global_basic(Z, s / 255, oparams(gp))
+    assert Yg.shape == (H, W)
+    err = np.abs(Yg - Yo)
+    say("max", err.max(), "psnr", O.psnr(Yg, clean), O.psnr(Yo, clean))
+    assert err.max() <= 2e-4
+    assert abs(O.psnr(Yg, clean) - O.psnr(Yo, clean)) <= 0.01
