@@ -201,9 +201,11 @@ void gbm3d_global_default_params(gbm3d_global_params* p);
  * [max(search, patch), 32768]; sides that are not multiples of patch are
  * handled as the paper does (Sec. 3.1): the image is extended at the bottom
  * and right with mirrored values (edge pixel repeated first) to the next
- * multiples, filtered, and the estimate cropped back to H x W.  The context keeps 2 * cycles float
- * volumes of k H W entries (all cycle spins are filtered together) and 2 H W
- * 64-bit sums as workspace; GBM3D_ENOMEM when they cannot be allocated. */
+ * multiples, filtered, and the estimate cropped back to H x W.  All
+ * translations and cycle spins are filtered together, so the context keeps
+ * 2 * n_shifts * cycles float volumes of k H W entries (of the padded size)
+ * and 2 * n_shifts H W 64-bit sums as workspace; GBM3D_ENOMEM when they
+ * cannot be allocated. */
 int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
                        const gbm3d_global_params* params, float* out, void* stream);
 

@@ -902,11 +902,13 @@ int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, floa
             gbm3d::launch_global_pad(noisy, H, W, static_cast<uint16_t*>(ctx->gl_pad.p), Hp, Wp, st),
             "mirror padding launch");
   }
-  CHECK(ensure(ctx, ctx->gl_a, p.cycles * vb, "global volumes"));
-  CHECK(ensure(ctx, ctx->gl_b, p.cycles * vb, "global volumes"));
-  CHECK(ensure(ctx, ctx->gl_num, 2 * hw * sizeof(unsigned long long), "global sums"));
-  CHECK(ensure(ctx, ctx->gl_idx, (hw / (p.patch * p.patch)) * p.k * sizeof(int16_t), "global matches"));
-  CHECK(ensure(ctx, ctx->gl_shift, hw * sizeof(uint16_t), "translated image"));
+  // per translation: cycles volume pairs, its sums, matches and translated image
+  const size_t T = static_cast<size_t>(p.n_shifts);
+  CHECK(ensure(ctx, ctx->gl_a, T * p.cycles * vb, "global volumes"));
+  CHECK(ensure(ctx, ctx->gl_b, T * p.cycles * vb, "global volumes"));
+  CHECK(ensure(ctx, ctx->gl_num, T * 2 * hw * sizeof(unsigned long long), "global sums"));
+  CHECK(ensure(ctx, ctx->gl_idx, T * (hw / (p.patch * p.patch)) * p.k * sizeof(int16_t), "global matches"));
+  CHECK(ensure(ctx, ctx->gl_shift, T * hw * sizeof(uint16_t), "translated images"));
   gbm3d::GlobalJob j{};
   j.noisy = padded ? static_cast<const uint16_t*>(ctx->gl_pad.p) : noisy;
   j.out = padded ? static_cast<float*>(ctx->gl_out.p) : out;

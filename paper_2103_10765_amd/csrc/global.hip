@@ -35,6 +35,20 @@ constexpr int kGlThreads = 256;
 constexpr int kMaxSearch = 39;
 constexpr double kKeyInfG = __builtin_huge_val();
 
+// The translations of one call, all filtered in the same launches:
+// translation ti moves the image by t[ti] along both axes (S_t); its
+// translated image is the noisy one when t[ti] = 0, else slice ti of the
+// translated-image buffer.  Per-translation buffers are slices ti of theirs.
+struct Shifts {
+  int n;
+  int t[4];
+};
+
+__device__ __forceinline__ const uint16_t* translated(const uint16_t* noisy, const uint16_t* shifted, size_t hw,
+                                                      const Shifts& sh, int ti) {
+  return sh.t[ti] ? shifted + static_cast<size_t>(ti) * hw : noisy;
+}
+
 // ---------------------------------------------------------------------------
 // Tile matching: one workgroup per reference tile.
 // ---------------------------------------------------------------------------
@@ -51,8 +65,10 @@ struct TileSmem {
 };
 
 template <int N, int K>
-__global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __restrict__ img, int H, int W, int S,
-                                                              int16_t* __restrict__ idx) {
+// grid: (tiles, translations)
+__global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __restrict__ noisy,
+                                                              const uint16_t* __restrict__ shifted, Shifts sh, int H,
+                                                              int W, int S, int16_t* __restrict__ idx) {
   using Sm = TileSmem<N>;
   constexpr int P = Sm::kPitch;
   constexpr int L = K - 1;
@@ -63,6 +79,8 @@ __global__ __launch_bounds__(kGlThreads) void gl_match_kernel(const uint16_t* __
   const int R = S / 2;
   const int side = S + N - 1;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint16_t* img = translated(noisy, shifted, static_cast<size_t>(H) * W, sh, blockIdx.y);
+  idx += static_cast<size_t>(blockIdx.y) * gridDim.x * K;
   {
     // the (S + N - 1)^2 search region (rows and columns wrap at most once:
     // R < H, W), all loads issued before any store
@@ -225,9 +243,14 @@ __global__ void gl_mirror_pad_kernel(const uint16_t* __restrict__ img, int H, in
   }
 }
 
-// out[y][x] = img[(y - t) mod H][(x - t) mod W]  (S_t of the image)
-__global__ void gl_roll_kernel(const uint16_t* __restrict__ img, int H, int W, int t, uint16_t* __restrict__ out) {
+// slice ti of shifted: S_t of the image, img[(y - t) mod H][(x - t) mod W],
+// for every translation t = sh.t[ti] other than 0; grid (g, translations)
+__global__ void gl_roll_kernel(const uint16_t* __restrict__ img, int H, int W, Shifts sh,
+                               uint16_t* __restrict__ shifted) {
+  const int t = sh.t[blockIdx.y];
+  if (t == 0) return;
   const size_t n = static_cast<size_t>(H) * W;
+  uint16_t* out = shifted + blockIdx.y * n;
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
     const int y = static_cast<int>(i / W), x = static_cast<int>(i - static_cast<size_t>(y) * W);
@@ -279,13 +302,15 @@ struct LevelTile {
 // within the region.  Output bands go to their Mallat positions (low half /
 // high half of each axis) in dst; every band but low-low-low is hard
 // thresholded with tau.  With GATHER the input is the spun volume V_h,
-// gathered from the image through the matches, instead of src.  Every cycle
-// spin h has its own pair of volumes, K H W elements apart in src and dst.
-// grid: (ceil(Lx / 2 / TX), ceil(Ly / 2 / TY), Lk / 2 * spins), z = h Lk / 2 + kp
+// gathered from the translated image through its matches, instead of src.
+// Every (translation ti, cycle spin h) has its own pair of volumes, volume
+// v = ti spins + h at v K H W elements into src and dst.
+// grid: (ceil(Lx / 2 / TX), ceil(Ly / 2 / TY), Lk / 2 * volumes), z = v Lk / 2 + kp
 template <int N, int K, bool GATHER, int TY, int TX>
 __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __restrict__ src,
-                                                                 const uint16_t* __restrict__ img,
-                                                                 const int16_t* __restrict__ idx, int S,
+                                                                 const uint16_t* __restrict__ noisy,
+                                                                 const uint16_t* __restrict__ shifted, Shifts sh,
+                                                                 int spins, const int16_t* __restrict__ idx, int S,
                                                                  float* __restrict__ dst, int H, int W, int Lk, int Ly,
                                                                  int Lx, float tau) {
   using T = LevelTile<TY, TX>;
@@ -304,11 +329,17 @@ __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __r
   // tile the window touches
   __shared__ int disp_y[GATHER ? 2 : 1][kTileRows][kTileCols], disp_x[GATHER ? 2 : 1][kTileRows][kTileCols];
   const int hy = Ly >> 1, hx = Lx >> 1, hk = Lk >> 1;
-  const int h = blockIdx.z / hk, kp = blockIdx.z - h * hk;
+  const int v = blockIdx.z / hk, kp = blockIdx.z - v * hk;
+  const int ti = v / spins, h = v - ti * spins;
   const int cx0 = blockIdx.x * TX, cy0 = blockIdx.y * TY;
   const size_t hw = static_cast<size_t>(H) * W;
-  if constexpr (!GATHER) src += static_cast<size_t>(h) * K * hw;
-  dst += static_cast<size_t>(h) * K * hw;
+  if constexpr (!GATHER) src += static_cast<size_t>(v) * K * hw;
+  dst += static_cast<size_t>(v) * K * hw;
+  const uint16_t* img = nullptr;
+  if constexpr (GATHER) {
+    img = translated(noisy, shifted, hw, sh, ti);
+    idx += static_cast<size_t>(ti) * (H / N) * (W / N) * K;
+  }
   const float c = 0.70710678118654752f;
   const int tid = threadIdx.x;
   if constexpr (GATHER) {
@@ -415,7 +446,8 @@ __global__ __launch_bounds__(kGlThreads) void gl_forward_kernel(const float* __r
 // Mallat positions in the region; the workgroup rebuilds slices 2 kp, 2 kp + 1,
 // rows 2 cy0 .. 2 cy0 + 2 TY - 1 and columns 2 cx0 .. 2 cx0 + 2 TX - 1
 // (synthesis along x, then y, then the Haar pair along k) at the same
-// positions of dst.  Volumes and grid as in the forward kernel.
+// positions of dst.  Volumes and grid as in the forward kernel (z = v Lk / 2
+// + kp over every volume v).
 template <int K, int TY, int TX>
 __global__ __launch_bounds__(kGlThreads) void gl_inverse_kernel(const float* __restrict__ src,
                                                                  float* __restrict__ dst, int H, int W, int Lk, int Ly,
@@ -525,11 +557,13 @@ __global__ void gl_zero_kernel(unsigned long long* __restrict__ p, size_t n) {
 // is summed in LDS first; only its covered cells go to the image with global
 // integer atomics.
 template <int N, int K>
+// grid: (tiles, translations); translation ti reads volumes ti spins ..
+// ti spins + spins - 1, its matches and its sums (numerators then
+// denominators, 2 H W words per translation).
 __global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* __restrict__ vol, int spins,
                                                                    const int16_t* __restrict__ idx, int H, int W,
                                                                    int S, float eps,
-                                                                   unsigned long long* __restrict__ num,
-                                                                   unsigned long long* __restrict__ den) {
+                                                                   unsigned long long* __restrict__ sums) {
   constexpr int kVals = N * N * K;
   constexpr int kFoot = (kMaxSearch + N - 1) * (kMaxSearch + N - 1);
   __shared__ float blk[kVals];
@@ -540,6 +574,11 @@ __global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* _
   const int g = blockIdx.x;
   const int y0 = (g / tiles_x) * N, x0 = (g % tiles_x) * N;
   const int side = S + N - 1;
+  const int ti = blockIdx.y;
+  vol += static_cast<size_t>(ti) * spins * K * hw;
+  idx += static_cast<size_t>(ti) * gridDim.x * K;
+  unsigned long long* num = sums + static_cast<size_t>(ti) * 2 * hw;
+  unsigned long long* den = num + hw;
   for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
     fnum[i] = 0;
     fden[i] = 0;
@@ -606,23 +645,31 @@ __global__ __launch_bounds__(kGlThreads) void gl_aggregate_kernel(const float* _
   }
 }
 
-// out[(y - t) mod H][(x - t) mod W] (=|+=) scale * num / den  (S_{-t} of the estimate)
-__global__ void gl_normalize_kernel(const unsigned long long* __restrict__ num,
-                                    const unsigned long long* __restrict__ den, int H, int W, int t, int first,
-                                    float scale, float* __restrict__ out) {
+// out[y][x] = (1 / translations) sum_ti num_ti / den_ti at ((y + t) mod H,
+// (x + t) mod W), t = sh.t[ti] (S_{-t} of each translation's estimate),
+// summed in translation order
+__global__ void gl_normalize_kernel(const unsigned long long* __restrict__ sums, int H, int W, Shifts sh,
+                                    float* __restrict__ out) {
   const size_t n = static_cast<size_t>(H) * W;
+  const float scale = 1.0f / static_cast<float>(sh.n);
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
     const int y = static_cast<int>(i / W), x = static_cast<int>(i - static_cast<size_t>(y) * W);
-    const float v = scale * static_cast<float>(static_cast<double>(static_cast<long long>(num[i])) /
-                                               static_cast<double>(static_cast<long long>(den[i])));
-    const size_t o = static_cast<size_t>(pmod(y - t, H)) * W + pmod(x - t, W);
-    out[o] = first ? v : out[o] + v;
+    float acc = 0.0f;
+    for (int ti = 0; ti < sh.n; ++ti) {
+      const int t = sh.t[ti];
+      const size_t o = static_cast<size_t>(pmod(y + t, H)) * W + pmod(x + t, W);
+      const unsigned long long* num = sums + static_cast<size_t>(ti) * 2 * n;
+      const float v = scale * static_cast<float>(static_cast<double>(static_cast<long long>(num[o])) /
+                                                 static_cast<double>(static_cast<long long>(num[n + o])));
+      acc = ti == 0 ? v : acc + v;
+    }
+    out[i] = acc;
   }
 }
 
-dim3 level_grid(int Lk, int Ly, int Lx, int ty, int tx, int spins) {
-  return dim3((Lx / 2 + tx - 1) / tx, (Ly / 2 + ty - 1) / ty, Lk / 2 * spins);
+dim3 level_grid(int Lk, int Ly, int Lx, int ty, int tx, int volumes) {
+  return dim3((Lx / 2 + tx - 1) / tx, (Ly / 2 + ty - 1) / ty, Lk / 2 * volumes);
 }
 
 unsigned grid_for(size_t n) {
@@ -636,47 +683,43 @@ hipError_t global_nk(const GlobalJob& j, hipStream_t st) {
   const size_t hw = static_cast<size_t>(H) * W;
   const int tiles = (H / N) * (W / N);
   const float eps = j.tv_eps_rel * j.sigma * static_cast<float>(N * N * K);
-  for (int ti = 0; ti < j.n_shifts; ++ti) {
-    const int t = j.shifts[ti];
-    const uint16_t* img = j.noisy;
-    if (t != 0) {
-      hipLaunchKernelGGL(gl_roll_kernel, dim3(grid_for(hw)), dim3(kGlThreads), 0, st, j.noisy, H, W, t, j.shifted);
-      img = j.shifted;
-    }
-    hipLaunchKernelGGL((gl_match_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, img, H, W, j.search, j.idx);
-    // every cycle spin in the same launches: forward level l writes
-    // buf[l & 1]; the next level reads only the low-low-low region of it, so
-    // every level's detail bands stay where they were written.  The inverse
-    // retraces the same buffers and the finest level leaves the filtered spun
-    // volumes in vol_a.
-    float* buf[2] = {j.vol_b, j.vol_a};
-    const int C = j.cycles;
-    for (int l = 0; l < j.levels; ++l) {
-      const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
-      const float tau = j.sigma * (j.ht_a - j.ht_b * static_cast<float>(l + 1));
-      if (l == 0)
-        hipLaunchKernelGGL((gl_forward_kernel<N, K, true, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32, C),
-                           dim3(kGlThreads), 0, st, nullptr, img, j.idx, j.search, buf[0], H, W, Lk, Ly, Lx, tau);
-      else
-        hipLaunchKernelGGL((gl_forward_kernel<N, K, false, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16, C),
-                           dim3(kGlThreads), 0, st, buf[(l - 1) & 1], nullptr, nullptr, j.search, buf[l & 1], H, W, Lk,
-                           Ly, Lx, tau);
-    }
-    for (int l = j.levels - 1; l >= 0; --l) {
-      const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
-      if (l == 0)
-        hipLaunchKernelGGL((gl_inverse_kernel<K, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32, C), dim3(kGlThreads), 0, st,
-                           buf[0], j.vol_a, H, W, Lk, Ly, Lx);
-      else
-        hipLaunchKernelGGL((gl_inverse_kernel<K, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16, C), dim3(kGlThreads), 0, st,
-                           buf[l & 1], buf[(l - 1) & 1], H, W, Lk, Ly, Lx);
-    }
-    hipLaunchKernelGGL(gl_zero_kernel, dim3(grid_for(2 * hw)), dim3(kGlThreads), 0, st, j.num, 2 * hw);
-    hipLaunchKernelGGL((gl_aggregate_kernel<N, K>), dim3(tiles), dim3(kGlThreads), 0, st, j.vol_a, C, j.idx, H, W,
-                       j.search, eps, j.num, j.num + hw);
-    hipLaunchKernelGGL(gl_normalize_kernel, dim3(grid_for(hw)), dim3(kGlThreads), 0, st, j.num, j.num + hw, H, W, t,
-                       ti == 0 ? 1 : 0, 1.0f / static_cast<float>(j.n_shifts), j.out);
+  Shifts sh{};
+  sh.n = j.n_shifts;
+  for (int i = 0; i < 4; ++i) sh.t[i] = i < j.n_shifts ? j.shifts[i] : 0;
+  const int T = j.n_shifts, C = j.cycles, V = T * C;
+  // every translation and cycle spin in the same launches
+  hipLaunchKernelGGL(gl_roll_kernel, dim3(grid_for(hw), T), dim3(kGlThreads), 0, st, j.noisy, H, W, sh, j.shifted);
+  hipLaunchKernelGGL((gl_match_kernel<N, K>), dim3(tiles, T), dim3(kGlThreads), 0, st, j.noisy, j.shifted, sh, H, W,
+                     j.search, j.idx);
+  // forward level l writes buf[l & 1]; the next level reads only the
+  // low-low-low region of it, so every level's detail bands stay where they
+  // were written.  The inverse retraces the same buffers and the finest level
+  // leaves the filtered spun volumes in vol_a.
+  float* buf[2] = {j.vol_b, j.vol_a};
+  for (int l = 0; l < j.levels; ++l) {
+    const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
+    const float tau = j.sigma * (j.ht_a - j.ht_b * static_cast<float>(l + 1));
+    if (l == 0)
+      hipLaunchKernelGGL((gl_forward_kernel<N, K, true, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32, V), dim3(kGlThreads),
+                         0, st, nullptr, j.noisy, j.shifted, sh, C, j.idx, j.search, buf[0], H, W, Lk, Ly, Lx, tau);
+    else
+      hipLaunchKernelGGL((gl_forward_kernel<N, K, false, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16, V), dim3(kGlThreads),
+                         0, st, buf[(l - 1) & 1], nullptr, nullptr, sh, C, nullptr, j.search, buf[l & 1], H, W, Lk, Ly,
+                         Lx, tau);
   }
+  for (int l = j.levels - 1; l >= 0; --l) {
+    const int Lk = K >> l, Ly = H >> l, Lx = W >> l;
+    if (l == 0)
+      hipLaunchKernelGGL((gl_inverse_kernel<K, 16, 32>), level_grid(Lk, Ly, Lx, 16, 32, V), dim3(kGlThreads), 0, st,
+                         buf[0], j.vol_a, H, W, Lk, Ly, Lx);
+    else
+      hipLaunchKernelGGL((gl_inverse_kernel<K, 8, 16>), level_grid(Lk, Ly, Lx, 8, 16, V), dim3(kGlThreads), 0, st,
+                         buf[l & 1], buf[(l - 1) & 1], H, W, Lk, Ly, Lx);
+  }
+  hipLaunchKernelGGL(gl_zero_kernel, dim3(grid_for(2 * hw * T)), dim3(kGlThreads), 0, st, j.num, 2 * hw * T);
+  hipLaunchKernelGGL((gl_aggregate_kernel<N, K>), dim3(tiles, T), dim3(kGlThreads), 0, st, j.vol_a, C, j.idx, H, W,
+                     j.search, eps, j.num);
+  hipLaunchKernelGGL(gl_normalize_kernel, dim3(grid_for(hw)), dim3(kGlThreads), 0, st, j.num, H, W, sh, j.out);
   return hipGetLastError();
 }
 
@@ -686,8 +729,9 @@ size_t global_volume_bytes(int H, int W, int K) { return static_cast<size_t>(K) 
 
 template <int N, int K>
 static hipError_t match_nk(const uint16_t* img, int H, int W, int search, int16_t* idx, hipStream_t st) {
-  hipLaunchKernelGGL((gl_match_kernel<N, K>), dim3((H / N) * (W / N)), dim3(kGlThreads), 0, st, img, H, W, search,
-                     idx);
+  const Shifts none{1, {0, 0, 0, 0}};
+  hipLaunchKernelGGL((gl_match_kernel<N, K>), dim3((H / N) * (W / N), 1), dim3(kGlThreads), 0, st, img, nullptr, none, H,
+                     W, search, idx);
   return hipGetLastError();
 }
 

@@ -67,10 +67,11 @@ int reduce_items_for(int H, int W);
 hipError_t launch_quantize(const float* in, uint16_t* out, size_t n, hipStream_t st);
 
 // Global stage 1 (the volume form of Sec. 3): one image, every buffer on the
-// device.  vol_a, vol_b: cycles * global_volume_bytes each (one volume per
-// cycle spin); num: 2 H W 64-bit words (numerators, then denominators); idx:
-// (H/patch)(W/patch) k int16; shifted: H W uint16 (used when a translation is
-// not 0).
+// device, every translation and cycle spin filtered in the same launches.
+// Per translation (n_shifts of them, slices in this order): vol_a, vol_b:
+// cycles * global_volume_bytes each; num: 2 H W 64-bit words (numerators,
+// then denominators); idx: (H/patch)(W/patch) k int16; shifted: H W uint16
+// (written for the translations that are not 0).
 struct GlobalJob {
   const uint16_t* noisy;
   float* out;
