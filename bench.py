@@ -259,9 +259,10 @@ def global_bench(ctx, Zt, clean, sigma, steps=20):
     p_g = psnr_db(out.cpu().numpy().astype(np.float64), clean)
     ms_b = timed(lambda: ctx.basic(Zt, sigma, out=out))
     p_b = psnr_db(out.cpu().numpy().astype(np.float64), clean)
-    # its largest kernel, the tile matching (one launch per translation),
-    # alone through its own entry point: exact distances, 3 FLOP per (pixel,
-    # displacement) as for the grouped matcher, on the fp64 vector ALU
+    # its largest kernel, the tile matching, alone through its own entry
+    # point (one translation per launch; inside the stage all translations
+    # share one launch): exact distances, 3 FLOP per (pixel, displacement)
+    # as for the grouped matcher, on the fp64 vector ALU
     ms_m = timed(lambda: ctx.global_match(Zt, gp))
     flop = 3.0 * H * W * (gp.search * gp.search - 1)
     tflops = flop / (ms_m * 1e-3) / 1e12
@@ -281,7 +282,7 @@ def global_bench(ctx, Zt, clean, sigma, steps=20):
             # form (Table 2, MATLAB with GPU filtering and CPU matching)
             "paper_table2_g_bm3d1_s": {"512": 0.334, "4096": 14.08},
             "roofline": {"kernel": "gl_match_kernel", "bound": "alu", "avg_us": 1e3 * ms_m,
-                         "launches_per_call": gp.n_shifts, "work_per_launch": flop, "work_unit": "FLOP",
+                         "translations_per_call": gp.n_shifts, "work_per_launch": flop, "work_unit": "FLOP",
                          "achieved": tflops, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": tflops / FP64_VALU_PEAK_TFLOPS}}
 
