@@ -318,6 +318,42 @@ def tiled_bench(ctx, sigma, steps=5):
     return res
 
 
+def recompute_bench(ctx, sigma, steps=10):
+    """Stage 1 with every block's bior1.5 spectrum read from the precomputed
+    stack (default) against computed inside the group kernel from the block's
+    pixels (no stack), at 512^2 and on the 4096^2 edge-rich image: ms per
+    stage-1 call (matching included) and of the group kernel alone."""
+    import torch
+    from paper_2103_10765_amd import gbm3d, synth
+    res = {}
+    for name, (_, Z) in (("512", synth.make_case(512, 512, sigma, 2)),
+                         ("4096", synth.large_image_case(4096, sigma, 4))):
+        Zt = torch.from_numpy(Z).cuda()
+        out = torch.empty(Zt.shape, dtype=torch.float32, device="cuda")
+        row = {}
+        for mode, src in (("stack", gbm3d.HT_STACK), ("recompute", gbm3d.HT_RECOMPUTE)):
+            p = gbm3d.default_params(ht_source=src)
+            ctx.basic(Zt, sigma, p, out=out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                ctx.basic(Zt, sigma, p, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ctx.timing(True)
+            ctx.timing_reset()
+            ctx.basic(Zt, sigma, p, out=out)
+            torch.cuda.synchronize()
+            tot, n = ctx.timing_read("group_ht")
+            ctx.timing(False)
+            row[mode] = {"stage1_ms": e0.elapsed_time(e1) / steps, "group_ht_ms": tot / max(n, 1)}
+        res[name] = row
+        del Zt, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(Z, sigma, size=320):
     """The CPU oracle (one thread) on a size x size crop of the same image."""
     import numpy as np
@@ -621,6 +657,7 @@ def main():
         rec["pnp"] = pnp.bench(ctx)
         rec["global_stage1"] = global_bench(ctx, Zt, clean, sigma)
         rec["tiled_sub_images"] = tiled_bench(ctx, sigma)
+        rec["stage1_recompute"] = recompute_bench(ctx, sigma)
         mp = copy_bandwidth()
         mp.update(unit_peaks(ctx))
         rec["measured_peaks"] = mp

@@ -87,7 +87,17 @@ typedef struct {
                            1 | 2 | 4; 0 = tuned or chosen by image size      */
   int32_t bm_method;    /* GBM3D_BM_AUTO (tuned or default) | GBM3D_BM_SHIFT |
                            GBM3D_BM_CORR                                     */
+  int32_t ht_source;    /* where stage 1 takes each matched block's bior1.5
+                           spectrum from: GBM3D_HT_STACK (default: the
+                           precomputed stack of every block) |
+                           GBM3D_HT_RECOMPUTE (transformed from the block's
+                           pixels inside the group kernel; no stack; single
+                           images only, batches return GBM3D_EUNSUPPORTED);
+                           the same result bit for bit                       */
 } gbm3d_params;
+
+#define GBM3D_HT_STACK     0
+#define GBM3D_HT_RECOMPUTE 1
 
 /* One image of a batch (see gbm3d_denoise_batch). */
 typedef struct {

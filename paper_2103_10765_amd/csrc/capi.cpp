@@ -187,6 +187,8 @@ int check_ht(gbm3d_ctx* ctx, const gbm3d_params& p) {
     return fail(ctx, GBM3D_EINVAL, "ht_weight %d unknown", p.ht_weight);
   if (!(p.tv_eps_rel > 0.0f) || !std::isfinite(p.tv_eps_rel))
     return fail(ctx, GBM3D_EINVAL, "tv_eps_rel must be > 0 and finite");
+  if (p.ht_source != GBM3D_HT_STACK && p.ht_source != GBM3D_HT_RECOMPUTE)
+    return fail(ctx, GBM3D_EINVAL, "ht_source %d unknown", p.ht_source);
   return GBM3D_OK;
 }
 
@@ -317,10 +319,15 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
   r.partials = static_cast<unsigned long long*>(ctx->partials.p);
   r.eps = tv_eps(p, sigma);
   CHECK(run_match(ctx, r, R, p.k_ht, p, 0, st));
-  HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(r, nullptr, 0, 0, 0, 0, st); }),
-          "stack launch");
+  const int recompute = p.ht_source == GBM3D_HT_RECOMPUTE ? 1 : 0;
+  if (recompute)
+    HIP_TRY(ctx, gbm3d::launch_clear_weights(r, st), "weight clearing launch");
+  else
+    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(r, nullptr, 0, 0, 0, 0, st); }),
+            "stack launch");
   HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
-            return gbm3d::launch_group_ht(r, nullptr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0, st);
+            return gbm3d::launch_group_ht(r, nullptr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, recompute, 0,
+                                          st);
           }),
           "hard-threshold group launch");
   HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, R, 0, 0, st); }),
@@ -513,7 +520,7 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
     HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, 2 * cu, st); }),
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
-              return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, cu, st);
+              return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0, cu, st);
             }),
             "batch hard-threshold groups");
     HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 0, 8 * cu, st); }),
@@ -607,6 +614,7 @@ void gbm3d_default_params(gbm3d_params* p) {
   p->keep_dc = 1;
   p->bm_split = 0;
   p->bm_method = GBM3D_BM_AUTO;
+  p->ht_source = GBM3D_HT_STACK;
 }
 
 int gbm3d_create(gbm3d_ctx** out, int hip_device) {
@@ -992,6 +1000,8 @@ int gbm3d_denoise_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gb
   CHECK(check_k(ctx, p.k_ht, p, "k_ht"));
   CHECK(check_k(ctx, p.k_wiener, p, "k_wiener"));
   CHECK(check_ht(ctx, p));
+  if (p.ht_source != GBM3D_HT_STACK)
+    return fail(ctx, GBM3D_EUNSUPPORTED, "batches take stage-1 spectra from the stack (ht_source %d)", p.ht_source);
   const bool basic_only = (flags & GBM3D_BATCH_BASIC_ONLY) != 0;
   for (int i = 0; i < n; ++i) {
     const gbm3d_image& im = imgs[i];

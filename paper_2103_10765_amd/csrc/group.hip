@@ -250,7 +250,51 @@ struct GroupWalk {
     }
     return true;
   }
+  // the pixels of group j's blocks instead of their spectra: v[k] = z at
+  // (row lane / 8, column lane % 8) of slot k's block (periodic),
+  // z = Z / 65535 as the stack kernel reads it
+  template <int K>
+  __device__ __forceinline__ bool gather_pixels(int j, int r, const uint16_t* __restrict__ img, float (&v)[1][K],
+                                                int& fo, int& pos_v) const {
+    int p, q;
+    if (!ref_of(j, p, q)) return false;
+    slot_pos<K>(g, r, p, q, fy0, fx0, lane, pos_v, fo);
+    const int a = lane >> 3, b = lane & 7;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int pos = __builtin_amdgcn_readlane(pos_v, k);
+      const int y = pos / g.W, x = pos - y * g.W;
+      const int yy = y + a >= g.H ? y + a - g.H : y + a, xx = x + b >= g.W ? x + b - g.W : x + b;
+      v[0][k] = static_cast<float>(img[static_cast<size_t>(yy) * g.W + xx]) * (1.0f / 65535.0f);
+    }
+    return true;
+  }
 };
+
+// The forward 2-D bior1.5 transform (three periodic Mallat levels, rows then
+// columns at each, as the stage-1 stack computes it) of K blocks whose
+// pixels the lanes hold (lane = pixel a * 8 + b), CH blocks at a time
+// through the wave's scratch (the same separable passes as the inverse);
+// afterwards v[k] is coefficient `lane` of block k.
+template <int K, int CH>
+__device__ __forceinline__ void forward_blocks(float* xw, int lane, float (&v)[K]) {
+  const int a = lane >> 3, b = lane & 7;
+  constexpr Mat8 A8 = bior_analysis(8);
+  constexpr Mat8 A4 = bior_analysis(4);
+  constexpr Mat8 A2 = bior_analysis(2);
+#pragma unroll
+  for (int c0 = 0; c0 < K; c0 += CH) {
+    wave_lds_sync();  // earlier reads of the scratch are done
+#pragma unroll
+    for (int k = 0; k < CH; ++k) xw[k * kBlockFloats + a * kScratchPitch + b] = v[c0 + k];
+    wave_lds_sync();
+    inverse_level<CH, 8>(xw, lane, [&](const float* x, float* y) { apply_mat<8>(A8, x, y); });
+    inverse_level<CH, 4>(xw, lane, [&](const float* x, float* y) { apply_mat<4>(A4, x, y); });
+    inverse_level<CH, 2>(xw, lane, [&](const float* x, float* y) { apply_mat<2>(A2, x, y); });
+#pragma unroll
+    for (int k = 0; k < CH; ++k) v[c0 + k] = xw[k * kBlockFloats + a * kScratchPitch + b];
+  }
+}
 
 // Runs filter(v, fo_v, pos_v) on every group of this wave in the tile, v the
 // gathered spectra.  Small groups also keep the next group's spectra in
@@ -291,8 +335,10 @@ __device__ __forceinline__ void for_each_group(const GroupWalk<WAVES>& walk, con
   }
 }
 
-// One work item = one tile of references: stage-1 groups.
-template <int K, bool BATCH>
+// One work item = one tile of references: stage-1 groups.  RECOMPUTE: the
+// blocks' spectra are computed here from the image's pixels instead of
+// gathered from the bior1.5 stack.
+template <int K, bool BATCH, bool RECOMPUTE>
 __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[GroupCfg<K, true, BATCH>::chunk * kBlockFloats],
                                               const ImgRec& r, int R, const HtParams& hp, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
@@ -312,7 +358,7 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[Group
   using Cfg = GroupCfg<K, true, BATCH>;
   const GroupWalk<Cfg::waves> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
   const float* const stacks[1] = {r.stack_a};
-  for_each_group<K, 1, Cfg::prefetch>(walk, stacks, [&](const float (&cur)[1][K], int fo_v, int pos_v) {
+  auto filter = [&](const float (&cur)[1][K], int fo_v, int pos_v) {
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = cur[0][k];
@@ -367,7 +413,22 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[Group
     }
     accumulate<K>(acc, g, fo_v, 0, u, w, lane);
     add_block_weights<K>(bw, pos_v, w, lane);
-  });
+  };
+  if constexpr (RECOMPUTE) {
+    int r0 = walk.template rank<K>(0);
+    for (int j = 0; j < walk.kGroups; ++j) {
+      const int r1 = walk.template rank<K>(j + 1);
+      float cur[1][K];
+      int fo = 0, pos = 0;
+      if (walk.template gather_pixels<K>(j, r0, r.noisy, cur, fo, pos)) {
+        forward_blocks<K, Cfg::chunk>(xw, lane, cur[0]);
+        filter(cur, fo, pos);
+      }
+      r0 = r1;
+    }
+  } else {
+    for_each_group<K, 1, Cfg::prefetch>(walk, stacks, filter);
+  }
   flush_acc(acc, n_acc, tile_sums(r) + static_cast<size_t>(item) * n_acc);
 }
 
@@ -441,7 +502,7 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc,
 }
 
 // (the second launch bound is the minimum number of waves per SIMD)
-template <int K, bool BATCH>
+template <int K, bool BATCH, bool RECOMPUTE>
 __global__ __launch_bounds__((GroupCfg<K, true, BATCH>::threads),
                              (GroupCfg<K, true, BATCH>::min_waves_per_simd)) void group_ht_kernel(ImgRec one,
                                                                                                    WorkList wl, int R,
@@ -449,8 +510,17 @@ __global__ __launch_bounds__((GroupCfg<K, true, BATCH>::threads),
   using Cfg = GroupCfg<K, true, BATCH>;
   __shared__ acc_t acc[Foot::entries];
   __shared__ float scratch[Cfg::waves][Cfg::chunk * kBlockFloats];
-  for_each_item<BATCH>(one, wl,
-                       [&](const ImgRec& r, int item) { group_ht_body<K, BATCH>(acc, scratch, r, R, hp, item); });
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
+    group_ht_body<K, BATCH, RECOMPUTE>(acc, scratch, r, R, hp, item);
+  });
+}
+
+// the block-start weights the aggregation adds into (the bior1.5 stack
+// launch clears them otherwise)
+__global__ void clear_weights_kernel(acc_t* __restrict__ w, size_t n) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    w[i] = 0;
 }
 
 template <int K, bool BATCH>
@@ -602,30 +672,42 @@ int group_items_for(int H, int W, int R) {
 int reduce_items_for(int H, int W) { return reduce_items(H, W); }
 
 template <int K>
-static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int grid_cap,
-                              hipStream_t st) {
+static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int recompute,
+                              int grid_cap, hipStream_t st) {
   if (!wl) {
-    hipLaunchKernelGGL((group_ht_kernel<K, false>), dim3(group_items_for(one.H, one.W, R)),
-                       dim3(GroupCfg<K, true, false>::threads), 0, st, one, WorkList{}, R, hp);
+    if (recompute)
+      hipLaunchKernelGGL((group_ht_kernel<K, false, true>), dim3(group_items_for(one.H, one.W, R)),
+                         dim3(GroupCfg<K, true, false>::threads), 0, st, one, WorkList{}, R, hp);
+    else
+      hipLaunchKernelGGL((group_ht_kernel<K, false, false>), dim3(group_items_for(one.H, one.W, R)),
+                         dim3(GroupCfg<K, true, false>::threads), 0, st, one, WorkList{}, R, hp);
   } else {
+    if (recompute) return hipErrorInvalidValue;  // batches read the stack
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_ht_kernel<K, true>), dim3(std::min(wl->total, grid_cap)),
+    hipLaunchKernelGGL((group_ht_kernel<K, true, false>), dim3(std::min(wl->total, grid_cap)),
                        dim3(GroupCfg<K, true, true>::threads), 0, st, one, *wl, R, hp);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, float ht_a, float ht_b,
-                           int weight_mode, int keep_dc, int grid_cap, hipStream_t st) {
+                           int weight_mode, int keep_dc, int recompute, int grid_cap, hipStream_t st) {
   const HtParams hp{ht_a, ht_b, weight_mode, keep_dc};
   switch (K) {
-    case 2: return launch_ht_k<2>(one, wl, R, hp, grid_cap, st);
-    case 4: return launch_ht_k<4>(one, wl, R, hp, grid_cap, st);
-    case 8: return launch_ht_k<8>(one, wl, R, hp, grid_cap, st);
-    case 16: return launch_ht_k<16>(one, wl, R, hp, grid_cap, st);
-    case 32: return launch_ht_k<32>(one, wl, R, hp, grid_cap, st);
+    case 2: return launch_ht_k<2>(one, wl, R, hp, recompute, grid_cap, st);
+    case 4: return launch_ht_k<4>(one, wl, R, hp, recompute, grid_cap, st);
+    case 8: return launch_ht_k<8>(one, wl, R, hp, recompute, grid_cap, st);
+    case 16: return launch_ht_k<16>(one, wl, R, hp, recompute, grid_cap, st);
+    case 32: return launch_ht_k<32>(one, wl, R, hp, recompute, grid_cap, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_clear_weights(const ImgRec& one, hipStream_t st) {
+  const size_t n = block_weight_entries(one.H, one.W);
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(clear_weights_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, one.partials, n);
+  return hipGetLastError();
 }
 
 template <int K>

@@ -50,9 +50,14 @@ int stack_items_for(int H, int W);
 size_t partials_bytes(int H, int W, int R);
 int group_items_for(int H, int W, int R);
 
-// stage-1 groups: stack_a (bior) + idx -> partials (weights scaled by rec.eps)
+// stage-1 groups: stack_a (bior) + idx -> partials (weights scaled by rec.eps);
+// recompute (one image only): the blocks' spectra from rec.noisy's pixels
+// instead of stack_a
 hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, float ht_a, float ht_b,
-                           int weight_mode, int keep_dc, int grid_cap, hipStream_t st);
+                           int weight_mode, int keep_dc, int recompute, int grid_cap, hipStream_t st);
+// zeroes the block-start weights of rec.partials (what the bior1.5 stack
+// launch does when the stage-1 groups read the stack)
+hipError_t launch_clear_weights(const ImgRec& one, hipStream_t st);
 
 // stage-2 groups: stack_a (noisy DCT) + stack_b (pilot DCT) + idx -> partials
 hipError_t launch_group_wiener(const ImgRec& one, const WorkList* wl, int R, int K, int grid_cap, hipStream_t st);

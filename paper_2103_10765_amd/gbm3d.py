@@ -21,6 +21,7 @@ W_TV, W_NNZ, W_UNIT = 0, 1, 2
 STACK_BIOR15, STACK_DCT = 0, 1
 BM_AUTO, BM_SHIFT, BM_CORR = 0, 1, 2
 PROBE_FP64, PROBE_MFMA_I8, PROBE_MFMA_BF16 = 0, 1, 2
+HT_STACK, HT_RECOMPUTE = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -38,6 +39,7 @@ class Params(ctypes.Structure):
         ("keep_dc", ctypes.c_int32),
         ("bm_split", ctypes.c_int32),
         ("bm_method", ctypes.c_int32),
+        ("ht_source", ctypes.c_int32),
     ]
 
 

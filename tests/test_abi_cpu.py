@@ -38,6 +38,7 @@ def test_default_params(G):
     p = G.default_params()
     assert p.struct_size == ctypes.sizeof(G.Params)
     assert (p.patch, p.step, p.search, p.k_ht, p.k_wiener) == (8, 3, 39, 16, 32)
+    assert p.ht_source == G.HT_STACK
     assert abs(p.ht_a - 3.6) < 1e-6 and abs(p.ht_b - 0.3) < 1e-6
     assert p.ht_weight == G.W_TV and p.keep_dc == 1
     assert p.bm_split == 0 and p.bm_method == G.BM_AUTO

@@ -195,6 +195,34 @@ def test_basic_parity(torch, G, ctx, H, W, S, sigma, seed):
     _check_stage1(Yg, Yo, idx, margin, p, clean)
 
 
+@pytest.mark.parametrize("H,W,S,seed", [(128, 128, 39, 1), (96, 130, 21, 9), (39, 41, 39, 11)])
+def test_basic_recompute_equals_stack(torch, G, ctx, H, W, S, seed):
+    """Stage 1 with each matched block's spectrum computed inside the group
+    kernel from its pixels equals the stack path bit for bit (the same
+    separable passes in the same order), and so do both stages; against the
+    oracle as any stage-1 result."""
+    say("basic recompute", H, W, S)
+    clean, Z = synth.make_case(H, W, SIG, seed)
+    Zt = up(torch, Z)
+    gp = G.default_params(search=S)
+    gr = G.default_params(search=S, ht_source=G.HT_RECOMPUTE)
+    a = ctx.basic(Zt, SIG, gp).cpu().numpy()
+    b = ctx.basic(Zt, SIG, gr).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.array_equal(ctx.denoise(Zt, SIG, gp).cpu().numpy(), ctx.denoise(Zt, SIG, gr).cpu().numpy())
+    p = oparams(G, gp)
+    Yo, (idx, margin, _, _) = O.basic_estimate(Z, SIG, p, return_parts=True)
+    _check_stage1(b.astype(np.float64), Yo, idx, margin, p, clean)
+
+
+def test_recompute_refused_for_batches(torch, G, ctx):
+    _, Z = synth.make_case(64, 64, SIG, 12)
+    with pytest.raises(G.GBM3DError):
+        ctx.denoise_batch([up(torch, Z)], [SIG], params=G.default_params(ht_source=G.HT_RECOMPUTE))
+    with pytest.raises(G.GBM3DError):
+        ctx.basic(up(torch, Z), SIG, G.default_params(ht_source=7))
+
+
 @pytest.mark.parametrize("weight", [1, 2])
 def test_basic_weight_variants(torch, G, ctx, weight):
     H, W = 60, 66
