@@ -597,7 +597,7 @@ def main():
         return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
     variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
                 "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"] * 2,
-                "group_ht": [f"group_ht_kernel<{p.k_ht}, false>"],
+                "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false>"],
                 "group_wiener": [f"group_wiener_kernel<{p.k_wiener}, false>"], "reduce": ["reduce_kernel<false>"] * 2}
     for name, k in kernels.items():
         bound, amount, unit = work[name]
