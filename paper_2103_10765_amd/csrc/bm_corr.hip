@@ -57,7 +57,9 @@ static_assert(12 * 3 + 4 * kMaxNb + 12 <= kPitch, "plane rows too short");
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // Candidate blocks of an nb x nb grid in rings of growing Chebyshev distance
-// from its centre (near displacements first tighten the bounds early).
+// from its centre (near displacements first tighten the bounds early), each
+// entry the block's (row << 8) | column, so no division by the run-time nb is
+// left in the walk.
 struct BlockOrder {
   int b[kMaxNb + 1][kMaxNb * kMaxNb];  // 32-bit entries: read with scalar loads
 };
@@ -71,7 +73,7 @@ constexpr BlockOrder make_block_order() {
         int dr = 2 * (b / nb) - (nb - 1), dc = 2 * (b % nb) - (nb - 1);
         dr = dr < 0 ? -dr : dr;
         dc = dc < 0 ? -dc : dc;
-        if ((dr > dc ? dr : dc) == ring) o.b[nb][n++] = b;
+        if ((dr > dc ? dr : dc) == ring) o.b[nb][n++] = (b / nb) << 8 | (b % nb);
       }
   }
   return o;
@@ -316,7 +318,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
     auto norms = [&](int j, double (&nv)[4]) {
       if (j < nblk) {
         const int b = kOrder.b[nb][j];
-        const int br = b / nb, bc = b - br * nb;
+        const int br = b >> 8, bc = b & 255;
         const double* nc = ncand + static_cast<size_t>(4 * br) * We + 4 * bc;
 #pragma unroll
         for (int i = 0; i < 4; ++i) nv[i] = nc[i];
@@ -326,7 +328,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
     // the reference itself) instead of buffering those below the bound
     auto block = [&](int j, const double (&nv)[4], auto warm, double (&keys)[4]) {
       const int b = kOrder.b[nb][j];
-      const int br = b / nb, bc = b - br * nb;
+      const int br = b >> 8, bc = b & 255;
       // operand: candidate m = n -> block row n / 4, column n % 4
       i32x4 ch, cl;
       load_operand(hp, lp, 4 * br + (n >> 2), 12 * t + 4 * bc + (n & 3), g, ch, cl);
