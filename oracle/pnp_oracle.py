@@ -39,9 +39,17 @@ def strengths(iters: int, s0: float, s1: float) -> np.ndarray:
     return s0 * (s1 / s0) ** (np.arange(iters) / (iters - 1))
 
 
+def gbm3d_denoiser(params: O.Params = O.DEFAULT):
+    """D_s(q): two-stage G-BM3D of the uint16 image q at strength s."""
+    return lambda q, s: O.denoise(q, float(s), params)[0]
+
+
 def pnp_admm(y: np.ndarray, Kf: np.ndarray, sigma_n: float, iters: int, s0: float, s1: float,
-             params: O.Params = O.DEFAULT):
-    """Restored image x and the last denoiser output v after `iters` rounds."""
+             params: O.Params = O.DEFAULT, denoiser=None):
+    """Restored image x and the last denoiser output v after `iters` rounds.
+    denoiser(q, s) maps the uint16 image q and the strength s to the prior
+    step's output (default: the two-stage G-BM3D with `params`)."""
+    D = gbm3d_denoiser(params) if denoiser is None else denoiser
     Y = np.fft.fft2(y)
     x = y.copy()
     v = y.copy()
@@ -49,6 +57,6 @@ def pnp_admm(y: np.ndarray, Kf: np.ndarray, sigma_n: float, iters: int, s0: floa
     for s in strengths(iters, s0, s1):
         mu = (sigma_n / s) ** 2
         x = x_step(Y, Kf, v - u, mu)
-        v = O.denoise(O.quantize(x + u), float(s), params)[0]
+        v = D(O.quantize(x + u), s)
         u = u + x - v
     return x, v

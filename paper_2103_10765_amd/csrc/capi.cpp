@@ -307,19 +307,20 @@ float tv_eps(const gbm3d_params& p, float sigma) { return p.tv_eps_rel * sigma *
 int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, const gbm3d_params& p,
               float* basic, uint16_t* q, hipStream_t st) {
   const int R = p.search / 2;
-  CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
+  const int recompute = p.ht_source == GBM3D_HT_RECOMPUTE ? 1 : 0;
+  // the recompute form transforms each matched block from its pixels: no stack
+  if (!recompute) CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
   CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_ht * sizeof(int16_t), "idx"));
   CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
   ImgRec r = blank_rec(H, W, sigma);
   r.noisy = noisy;
   r.basic = basic;
   r.q = q;
-  r.stack_a = static_cast<float*>(ctx->stack_a.p);
+  r.stack_a = recompute ? nullptr : static_cast<float*>(ctx->stack_a.p);
   r.idx = static_cast<int16_t*>(ctx->idx.p);
   r.partials = static_cast<unsigned long long*>(ctx->partials.p);
   r.eps = tv_eps(p, sigma);
   CHECK(run_match(ctx, r, R, p.k_ht, p, 0, st));
-  const int recompute = p.ht_source == GBM3D_HT_RECOMPUTE ? 1 : 0;
   if (recompute)
     HIP_TRY(ctx, gbm3d::launch_clear_weights(r, st), "weight clearing launch");
   else

@@ -1,6 +1,7 @@
 """Pins of the global stage-1 oracle (CPU only): transform round trip and
 separability, band levels, brute-force tile matching, the volume's first
-slice, zero-threshold identity, constants, and the averaging operators."""
+slice, zero-threshold identity, constants, the averaging operators, the TV
+weights in closed form, and the kept final approximation band."""
 import numpy as np
 
 from oracle import gbm3d_oracle as O
@@ -123,3 +124,56 @@ def test_non_multiple_sizes_keep_constants():
     Y = G.global_basic(Z, 20 / 255, p)
     assert Y.shape == (37, 45)
     assert np.allclose(Y, 20000 / 65535, atol=1e-9)
+
+
+def test_tv_weights_closed_form():
+    """w = 1 / (TV + eps) per tile, TV the anisotropic L1 norm of forward,
+    non-periodic differences along the match axis and both image axes
+    (Sec. 3.1 weight 1/TV), on four tiles whose TV has a closed form: a
+    horizontal ramp a*x gives K N (N-1) |a|, a vertical ramp b*y gives
+    K N (N-1) |b|, per-slice offsets c_k give N^2 sum |c_{k+1} - c_k|, and
+    their sum adds up (each difference runs along one axis)."""
+    N, K = 4, 4
+    p = G.GDEFAULT.with_(patch=N, k=K)
+    sig = 0.2
+    a, b, c = 0.03, -0.05, np.array([0.0, 0.4, 0.1, 0.7])
+    yy, xx = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    U = np.zeros((K, 2 * N, 2 * N))
+    U[:, :N, :N] = 0.5 + a * xx                                        # tile 0 (raster order)
+    U[:, :N, N:] = 0.2 + b * yy                                        # tile 1
+    U[:, N:, :N] = c[:, None, None] + 0 * xx                           # tile 2
+    U[:, N:, N:] = c[:, None, None] + a * xx + b * yy                  # tile 3
+    ramp = K * N * (N - 1)
+    dc = N * N * np.abs(np.diff(c)).sum()
+    tv = np.array([ramp * abs(a), ramp * abs(b), dc, ramp * (abs(a) + abs(b)) + dc])
+    eps = p.tv_eps_rel * sig * N * N * K
+    assert np.allclose(G.tv_weights(U, sig, p), 1.0 / (tv + eps), rtol=1e-13, atol=0)
+
+
+def test_final_approximation_is_kept_details_thresholded():
+    """Detail bands are hard-thresholded at tau_l = sigma (3.6 - 0.3 l) and the
+    final approximation band is kept whatever its size (the reading of the
+    3-D transform's threshold rule, Sec. 3): a volume whose coefficients are
+    all in the approximation band, every one below tau_3, comes back exactly;
+    adding one level-2 detail coefficient just below tau_2 and one level-1
+    coefficient just above tau_1 returns the volume without the first."""
+    K, H, W = 16, 32, 32
+    p = G.GDEFAULT.with_(cycles=1)
+    sig = 0.1
+    lev = G.coefficient_levels(K, H, W, p.levels)
+    tau = lambda l: sig * (p.ht_a - p.ht_b * l)
+    rng = np.random.default_rng(21)
+    C = np.zeros((K, H, W))
+    approx = lev == 0
+    C[approx] = rng.uniform(0.2, 0.9, approx.sum()) * tau(3) * rng.choice([-1.0, 1.0], approx.sum())
+    V = G.idwt3(C, p.levels)
+    assert np.abs(G.filter_volume(V, sig, p) - V).max() < 1e-12
+    C2 = C.copy()
+    k2 = tuple(np.argwhere(lev == 2)[5])
+    k1 = tuple(np.argwhere(lev == 1)[100])
+    C2[k2] = 0.999 * tau(2)
+    C2[k1] = -1.001 * tau(1)
+    want = C2.copy()
+    want[k2] = 0.0
+    got = G.filter_volume(G.idwt3(C2, p.levels), sig, p)
+    assert np.abs(got - G.idwt3(want, p.levels)).max() < 1e-12

@@ -157,6 +157,13 @@ def test_match_max_width_sampled(torch, G, ctx, method):
 # ---------------------------------------------------------------------------
 
 FLAG_MAXABS = 5e-3   # bound on pixels near a flipped hard-threshold decision
+# Near-threshold groups: at most 1e-3 of the groups, with a floor of 3 groups
+# for the small images here (the oracle on these inputs gives 0 in most cases,
+# 3 of 1408 groups at 96 x 130, sigma 15/255, and 1 of 288 with K = 32), and at
+# most 12% of the checked pixels covered by them (measured at most 10.4%).
+FLAG_GROUP_FLOOR = 3
+FLAG_GROUP_FRAC = 1e-3
+FLAG_PIXEL_FRAC = 0.12
 
 
 def _check_stage1(Yg, Yo, idx, margin, p, clean=None, ref_ids=None, window=None):
@@ -166,14 +173,15 @@ def _check_stage1(Yg, Yo, idx, margin, p, clean=None, ref_ids=None, window=None)
     H, W = Yg.shape
     flag = O.flagged_pixels(H, W, idx, margin, p, ref_ids=ref_ids)
     n_flag_groups = int((margin < 1e-5).sum())
-    assert n_flag_groups <= max(4, 0.005 * len(margin)), n_flag_groups
     if window is not None:
         rows, cols = window
         Yg, Yo, flag = Yg[np.ix_(rows, cols)], Yo[np.ix_(rows, cols)], flag[np.ix_(rows, cols)]
         if clean is not None:
             clean = clean[np.ix_(rows, cols)]
+    say(f"  near-threshold groups {n_flag_groups} of {len(margin)}, flagged pixels {flag.mean():.4f}")
+    assert n_flag_groups <= max(FLAG_GROUP_FLOOR, FLAG_GROUP_FRAC * len(margin)), n_flag_groups
+    assert flag.mean() <= FLAG_PIXEL_FRAC, flag.mean()
     err = np.abs(Yg - Yo)
-    assert (~flag).sum() > 0.5 * Yg.size
     assert err[~flag].max() <= MAXABS, (err[~flag].max(), n_flag_groups)
     if flag.any():
         assert err[flag].max() <= FLAG_MAXABS, err[flag].max()
@@ -195,17 +203,19 @@ def test_basic_parity(torch, G, ctx, H, W, S, sigma, seed):
     _check_stage1(Yg, Yo, idx, margin, p, clean)
 
 
-@pytest.mark.parametrize("H,W,S,seed", [(128, 128, 39, 1), (96, 130, 21, 9), (39, 41, 39, 11)])
-def test_basic_recompute_equals_stack(torch, G, ctx, H, W, S, seed):
+@pytest.mark.parametrize("H,W,S,seed,k_ht", [(128, 128, 39, 1, 16), (96, 130, 21, 9, 16), (39, 41, 39, 11, 16),
+                                              (70, 77, 21, 20, 2), (64, 90, 15, 21, 8), (81, 64, 39, 22, 32)])
+def test_basic_recompute_equals_stack(torch, G, ctx, H, W, S, seed, k_ht):
     """Stage 1 with each matched block's spectrum computed inside the group
     kernel from its pixels equals the stack path bit for bit (the same
     separable passes in the same order), and so do both stages; against the
-    oracle as any stage-1 result."""
-    say("basic recompute", H, W, S)
+    oracle as any stage-1 result.  Every group size's launch shape (chunks of
+    K blocks for K <= 8, of 16 for K = 32)."""
+    say("basic recompute", H, W, S, "k_ht", k_ht)
     clean, Z = synth.make_case(H, W, SIG, seed)
     Zt = up(torch, Z)
-    gp = G.default_params(search=S)
-    gr = G.default_params(search=S, ht_source=G.HT_RECOMPUTE)
+    gp = G.default_params(search=S, k_ht=k_ht)
+    gr = G.default_params(search=S, k_ht=k_ht, ht_source=G.HT_RECOMPUTE)
     a = ctx.basic(Zt, SIG, gp).cpu().numpy()
     b = ctx.basic(Zt, SIG, gr).cpu().numpy()
     assert np.array_equal(a, b)

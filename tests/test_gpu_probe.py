@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 def ctx():
     import torch
     if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+        pytest.fail("no GPU visible to torch")
     from paper_2103_10765_amd import gbm3d
     c = gbm3d.Context(0)
     yield c

@@ -59,3 +59,35 @@ def test_observation_model():
     assert abs(k.sum() - 1.0) < 1e-12 and np.allclose(k, k.T)
     resid = y - np.real(np.fft.ifft2(np.fft.fft2(clean) * synth.psf_spectrum(k, 96, 96)))
     assert abs(resid.std() - 0.02) < 0.002
+
+
+def test_admm_rounds_by_hand():
+    """Three rounds of the loop on a constant image with no blur and an affine
+    stand-in denoiser D(q, s) = q / 65535 / 2 + s, derived by hand from the
+    textbook plug-and-play ADMM: x = (y + mu (v - u)) / (1 + mu) with
+    mu = (sigma_n / s)^2 (the x-step without blur), v = D(Q(x + u)), and the
+    dual update u <- u + x - v; strengths geometric from s0 to s1."""
+    H, W = 6, 5
+    c, sn, s0, s1 = 0.4, 0.03, 0.08, 0.02
+    y = np.full((H, W), c)
+    delta = np.zeros((3, 3))
+    delta[1, 1] = 1.0
+    Kf = synth.psf_spectrum(delta, H, W)
+
+    def D(q, s):
+        return q.astype(np.float64) / 65535.0 / 2.0 + s
+
+    def Q(t):
+        return np.floor(min(max(t, 0.0), 1.0) * 65535.0 + 0.5) / 65535.0
+
+    x, v, u = c, c, 0.0
+    for s in (s0, s0 * (s1 / s0) ** 0.5, s1):
+        mu = (sn / s) ** 2
+        x = (c + mu * (v - u)) / (1.0 + mu)
+        v = Q(x + u) / 2.0 + s
+        u = u + x - v
+    gx, gv = P.pnp_admm(y, Kf, sn, 3, s0, s1, denoiser=D)
+    assert np.abs(gx - x).max() < 1e-12 and np.abs(gv - v).max() < 1e-12
+    # the hand derivation is not degenerate: the dual variable and the
+    # strength schedule both change the result
+    assert abs(x - c) > 1e-3 and abs(u) > 1e-3
