@@ -227,6 +227,27 @@ int gbm3d_global_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, floa
 int gbm3d_global_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W,
                        const gbm3d_global_params* params, int16_t* idx, void* stream);
 
+/* gbm3d_denoise for callers that cannot allocate device memory: code under
+ * hipGraph stream capture, tight serving loops, hosts that forbid hipMalloc.
+ * Same arguments, validation and result (bit for bit) as gbm3d_denoise, but
+ * every intermediate buffer (norm table, two patch stacks, match indices,
+ * aggregation sums, and the basic estimate and pilot when basic_out / q_out
+ * are NULL) is a slice of one static device array of
+ * GBM3D_NOALLOC_SCRATCH_BYTES per device, which the library holds on every
+ * device it runs on until the process ends.  The call makes no hipMalloc,
+ * hipFree or other allocating call and records no timing events.  It
+ * returns GBM3D_EINVAL, launching nothing, when the image needs more scratch
+ * than that (with the default parameters 512 x 512 fits; the error text
+ * gives the bytes needed).  Every call on a device shares that device's
+ * array and leaves its contents behind (the kernels clear what must start
+ * at zero), so calls that overlap on one device — on two streams, from two
+ * contexts or two threads — race and give undefined results; serialise them.
+ * The caller owns noisy, out, basic_out and q_out as in gbm3d_denoise. */
+#define GBM3D_NOALLOC_SCRATCH_BYTES (160u * 1024u * 1024u)
+int gbm3d_denoise_noalloc(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
+                          const gbm3d_params* params, float* out, float* basic_out,
+                          uint16_t* q_out, void* stream);
+
 /* A batch of images of any sizes (the plug-and-play use case of Sec. 1: one
  * denoiser call per iteration, many images).  imgs: HOST array of n
  * descriptors (device pointers inside).  For each image: if pilot == NULL,

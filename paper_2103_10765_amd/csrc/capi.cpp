@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,13 @@
 
 using gbm3d::ImgRec;
 using gbm3d::WorkList;
+
+// Workspace of gbm3d_denoise_noalloc: one fixed array per device, reserved
+// when the library's code object is loaded there and held until the process
+// ends.  Its host-side name is only a stand-in for the symbol: host code
+// reaches the memory through the address hipGetSymbolAddress returns for
+// the current device (scratch_addr below), never through the name itself.
+static __device__ __align__(256) unsigned char scratch[GBM3D_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -34,6 +42,30 @@ struct TimingRecord {
 };
 
 thread_local std::string g_thread_error;
+
+// Device address of `scratch` on each device, looked up once per device by
+// gbm3d_create with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_addr[dev] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_addr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_addr[dev];
+}
 
 // Work lists of the batch phases: per-image prefix offsets of the items.
 enum Phase { kNorm1, kBm1, kStack1, kGroup1, kReduce1, kNorm2, kBm2, kStack2, kGroup2, kReduce2, kPhases };
@@ -280,10 +312,13 @@ BmChoice choose_bm(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles, int 
 }
 
 // Block matching of one image (r.noisy, or r.pilot with use_pilot) into r.idx.
+// The correlation kernel's norm table is r.norm when set, else the context's.
 int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const BmChoice& c, int use_pilot, hipStream_t st) {
   if (c.method == GBM3D_BM_CORR) {
-    CHECK(ensure(ctx, ctx->norm, gbm3d::norm_bytes(r.H, r.W), "norm table"));
-    r.norm = static_cast<double*>(ctx->norm.p);
+    if (!r.norm) {
+      CHECK(ensure(ctx, ctx->norm, gbm3d::norm_bytes(r.H, r.W), "norm table"));
+      r.norm = static_cast<double*>(ctx->norm.p);
+    }
     HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(r, nullptr, R, use_pilot, 0, st); }),
             "norm table launch");
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
@@ -303,22 +338,42 @@ int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const gbm3d_params& p, in
 
 float tv_eps(const gbm3d_params& p, float sigma) { return p.tv_eps_rel * sigma * 64.0f * static_cast<float>(p.k_ht); }
 
+// Device buffers of one image's stages: the context's workspace (grown on
+// demand), or slices of the static scratch (gbm3d_denoise_noalloc).
+struct Workspace {
+  float* stack_a = nullptr;
+  float* stack_b = nullptr;
+  int16_t* idx = nullptr;
+  unsigned long long* partials = nullptr;
+  double* norm = nullptr;
+};
+
 // Stage 1 of one image into `basic` (and optionally its quantisation into q).
+// ws: preassigned buffers, or NULL for the context's workspace.
 int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, const gbm3d_params& p,
-              float* basic, uint16_t* q, hipStream_t st) {
+              float* basic, uint16_t* q, hipStream_t st, const Workspace* ws = nullptr) {
   const int R = p.search / 2;
   const int recompute = p.ht_source == GBM3D_HT_RECOMPUTE ? 1 : 0;
-  // the recompute form transforms each matched block from its pixels: no stack
-  if (!recompute) CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
-  CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_ht * sizeof(int16_t), "idx"));
-  CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
+  Workspace w;
+  if (ws) {
+    w = *ws;
+  } else {
+    // the recompute form transforms each matched block from its pixels: no stack
+    if (!recompute) CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
+    CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_ht * sizeof(int16_t), "idx"));
+    CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
+    w.stack_a = static_cast<float*>(ctx->stack_a.p);
+    w.idx = static_cast<int16_t*>(ctx->idx.p);
+    w.partials = static_cast<unsigned long long*>(ctx->partials.p);
+  }
   ImgRec r = blank_rec(H, W, sigma);
   r.noisy = noisy;
   r.basic = basic;
   r.q = q;
-  r.stack_a = recompute ? nullptr : static_cast<float*>(ctx->stack_a.p);
-  r.idx = static_cast<int16_t*>(ctx->idx.p);
-  r.partials = static_cast<unsigned long long*>(ctx->partials.p);
+  r.stack_a = recompute ? nullptr : w.stack_a;
+  r.idx = w.idx;
+  r.partials = w.partials;
+  r.norm = w.norm;
   r.eps = tv_eps(p, sigma);
   CHECK(run_match(ctx, r, R, p.k_ht, p, 0, st));
   if (recompute)
@@ -337,20 +392,30 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
 }
 
 int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int H, int W, float sigma,
-               const gbm3d_params& p, float* out, hipStream_t st) {
+               const gbm3d_params& p, float* out, hipStream_t st, const Workspace* ws = nullptr) {
   const int R = p.search / 2;
-  CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
-  CHECK(ensure(ctx, ctx->stack_b, stack_bytes(H, W), "pilot stack"));
-  CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_wiener * sizeof(int16_t), "idx"));
-  CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
+  Workspace w;
+  if (ws) {
+    w = *ws;
+  } else {
+    CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
+    CHECK(ensure(ctx, ctx->stack_b, stack_bytes(H, W), "pilot stack"));
+    CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_wiener * sizeof(int16_t), "idx"));
+    CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
+    w.stack_a = static_cast<float*>(ctx->stack_a.p);
+    w.stack_b = static_cast<float*>(ctx->stack_b.p);
+    w.idx = static_cast<int16_t*>(ctx->idx.p);
+    w.partials = static_cast<unsigned long long*>(ctx->partials.p);
+  }
   ImgRec r = blank_rec(H, W, sigma);
   r.noisy = noisy;
   r.pilot = pilot;
   r.out = out;
-  r.stack_a = static_cast<float*>(ctx->stack_a.p);
-  r.stack_b = static_cast<float*>(ctx->stack_b.p);
-  r.idx = static_cast<int16_t*>(ctx->idx.p);
-  r.partials = static_cast<unsigned long long*>(ctx->partials.p);
+  r.stack_a = w.stack_a;
+  r.stack_b = w.stack_b;
+  r.idx = w.idx;
+  r.partials = w.partials;
+  r.norm = w.norm;
   CHECK(run_match(ctx, r, R, p.k_wiener, p, 1, st));
   HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 0, 0, 0, st); }),
           "stack launch");
@@ -633,6 +698,14 @@ int gbm3d_create(gbm3d_ctx** out, int hip_device) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, GBM3D_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", dev,
                 prop.gcnArchName);
+  {
+    // the no-allocation entry point's scratch on this device
+    DeviceGuard g(dev);
+    if (!g.ok) return fail(nullptr, GBM3D_EHIP, "hipSetDevice(%d) failed", dev);
+    e = resolve_scratch(dev);
+    if (e != hipSuccess)
+      return fail(nullptr, GBM3D_EHIP, "device scratch of device %d: %s", dev, hipGetErrorString(e));
+  }
   gbm3d_ctx* ctx = new gbm3d_ctx();
   ctx->device = dev;
   ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -988,6 +1061,60 @@ int gbm3d_denoise(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sig
   }
   CHECK(run_basic(ctx, noisy, H, W, sigma, p, basic, q, st));
   return run_wiener(ctx, noisy, q, H, W, sigma, p, out, st);
+}
+
+int gbm3d_denoise_noalloc(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma,
+                          const gbm3d_params* params, float* out, float* basic_out, uint16_t* q_out, void* stream) {
+  const gbm3d_params p = resolve(params);
+  if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
+  if (!noisy || !out) return fail(ctx, GBM3D_EINVAL, "NULL image or output pointer");
+  CHECK(check_shape(ctx, H, W, p));
+  CHECK(check_k(ctx, p.k_ht, p, "k_ht"));
+  CHECK(check_k(ctx, p.k_wiener, p, "k_wiener"));
+  CHECK(check_sigma(ctx, sigma));
+  CHECK(check_ht(ctx, p));
+  // slices of the scratch: the same buffers gbm3d_denoise takes from the
+  // context's workspace
+  const int R = p.search / 2;
+  const size_t hw = static_cast<size_t>(H) * W;
+  size_t off = 0;
+  auto take = [&off](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t o_norm = take(gbm3d::norm_bytes(H, W));
+  const size_t o_sa = take(stack_bytes(H, W));
+  const size_t o_sb = take(stack_bytes(H, W));
+  const size_t o_idx = take(n_refs(H, W) * std::max(p.k_ht, p.k_wiener) * sizeof(int16_t));
+  const size_t o_part = take(gbm3d::partials_bytes(H, W, R));
+  const size_t o_basic = basic_out ? 0 : take(hw * sizeof(float));
+  const size_t o_q = q_out ? 0 : take(hw * sizeof(uint16_t));
+  if (off > static_cast<size_t>(GBM3D_NOALLOC_SCRATCH_BYTES))
+    return fail(ctx, GBM3D_EINVAL, "image %dx%d needs %zu bytes of scratch; the static scratch holds %zu", H, W, off,
+                static_cast<size_t>(GBM3D_NOALLOC_SCRATCH_BYTES));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
+  char* base = static_cast<char*>(scratch_addr(ctx->device));
+  if (!base) return fail(ctx, GBM3D_EHIP, "device scratch of device %d not resolved", ctx->device);
+  Workspace ws;
+  ws.norm = reinterpret_cast<double*>(base + o_norm);
+  ws.stack_a = reinterpret_cast<float*>(base + o_sa);
+  ws.stack_b = reinterpret_cast<float*>(base + o_sb);
+  ws.idx = reinterpret_cast<int16_t*>(base + o_idx);
+  ws.partials = reinterpret_cast<unsigned long long*>(base + o_part);
+  float* basic = basic_out ? basic_out : reinterpret_cast<float*>(base + o_basic);
+  uint16_t* q = q_out ? q_out : reinterpret_cast<uint16_t*>(base + o_q);
+  // per-kernel timing would create events: none for this call
+  struct TimingOff {
+    gbm3d_ctx* c;
+    bool was;
+    ~TimingOff() { c->timing = was; }
+  } off_timing{ctx, ctx->timing};
+  ctx->timing = false;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CHECK(run_basic(ctx, noisy, H, W, sigma, p, basic, q, st, &ws));
+  return run_wiener(ctx, noisy, q, H, W, sigma, p, out, st, &ws);
 }
 
 int gbm3d_denoise_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_params* params, int flags,

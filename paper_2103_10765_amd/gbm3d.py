@@ -96,6 +96,7 @@ _SIGNATURES = {
     "gbm3d_basic": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P]),
     "gbm3d_wiener": (_I, [_P, _P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P]),
     "gbm3d_denoise": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P, _P, _P]),
+    "gbm3d_denoise_noalloc": (_I, [_P, _P, _I, _I, _F, ctypes.POINTER(Params), _P, _P, _P, _P]),
     "gbm3d_quantize": (_I, [_P, _P, _P, ctypes.c_size_t, _P]),
     "gbm3d_denoise_batch": (_I, [_P, ctypes.POINTER(Image), _I, ctypes.POINTER(Params), _I, _P]),
     "gbm3d_pilot_param_count": (_I, []),
@@ -287,6 +288,21 @@ class Context:
         self._check(lib().gbm3d_denoise(self._h, _dev(noisy, torch.uint16, "noisy"), H, W, float(sigma),
                                         self._params(params), _dev(out, torch.float32, "out"), b, q,
                                         _stream(stream)))
+        return out
+
+    def denoise_noalloc(self, noisy: torch.Tensor, sigma: float, params: Params | None = None, out=None,
+                        basic_out=None, q_out=None, stream=None):
+        """denoise() with every intermediate buffer in the library's static
+        device scratch (no device allocation inside the call).  `out` must be
+        given when the caller cannot allocate either."""
+        H, W = _hw(noisy)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=noisy.device)
+        b = _dev(basic_out, torch.float32, "basic_out") if basic_out is not None else None
+        q = _dev(q_out, torch.uint16, "q_out") if q_out is not None else None
+        self._check(lib().gbm3d_denoise_noalloc(self._h, _dev(noisy, torch.uint16, "noisy"), H, W, float(sigma),
+                                                self._params(params), _dev(out, torch.float32, "out"), b, q,
+                                                _stream(stream)))
         return out
 
     def denoise_batch(self, noisy, sigmas, pilots=None, outs=None, params: Params | None = None,
