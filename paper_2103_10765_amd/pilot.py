@@ -107,10 +107,13 @@ def loss_weights(sig_t, mode: str):
 
 
 def train(ctx, Zt, target, sig_t, steps: int, batch: int = 64, seed: int = 0, ckpt: str | None = None,
-          ckpt_every: int = 500, resume: bool = True, log=print, weighting: str = "none"):
+          ckpt_every: int = 500, resume: bool = True, log=print, weighting: str = "none", hist_every: int = 100,
+          stop_after: int | None = None):
     """Adam on the (optionally per-crop weighted) mean squared error between
     the pilot and the stage-1 target.  The batch order is a seeded permutation
-    per epoch, so a resumed run continues exactly where it stopped."""
+    per epoch, so a resumed run continues exactly where it stopped.  The loss
+    is recorded every `hist_every` steps; `stop_after` ends the run after that
+    step (checkpointed when `ckpt` is set), as an interrupted run would."""
     import torch
     n = Zt.shape[0]
     dev = Zt.device
@@ -138,12 +141,15 @@ def train(ctx, Zt, target, sig_t, steps: int, batch: int = 64, seed: int = 0, ck
                        sig_t.index_select(0, ids).contiguous(), grad=grad, loss=loss,
                        weight=None if w_all is None else w_all.index_select(0, ids).contiguous())
         ctx.pilot_adam(master, m, v, grad, step, lr_at(step, steps))
-        if step % 100 == 0 or step == steps:
+        if step % hist_every == 0 or step == steps:
             hist.append((step, loss.item()))
             log(f"step {step} loss {hist[-1][1]:.3e} lr {lr_at(step, steps):.2e} {time.perf_counter() - t0:.1f}s")
-        if ckpt and (step % ckpt_every == 0 or step == steps):
+        stop = stop_after is not None and step >= stop_after
+        if ckpt and (step % ckpt_every == 0 or step == steps or stop):
             save_checkpoint(ckpt, master, m, v, step, {"batch": batch, "seed": seed, "steps": steps,
                                                        "weighting": weighting})
+        if stop:
+            break
     torch.cuda.synchronize()
     return master, hist
 

@@ -122,3 +122,28 @@ def test_pilot_training_reduces_loss(torch, G, ctx):
         ctx.pilot_adam(theta, m, v, grad, step, 1e-3)
     say("losses", losses[0], losses[-1])
     assert losses[-1] < 0.7 * losses[0]
+
+
+def test_pilot_checkpoint_resume_reproduces_the_run(torch, G, ctx, tmp_path):
+    """A run interrupted after a checkpoint and resumed from it gives the same
+    loss at every step, and the same final weights, as the uninterrupted run
+    (seeded per-epoch batch order, Adam moments and step restored)."""
+    from paper_2103_10765_amd import pilot
+    n, H, W, steps, batch = 24, 32, 32, 9, 8
+    Z, sig = _batch(n, H, W, 70)
+    Zt, st = torch.from_numpy(Z).cuda(), torch.from_numpy(sig).cuda()
+    target = torch.from_numpy(np.stack([synth.clean_image(H, W, 70 + i) for i in range(n)]).astype(np.float32)).cuda()
+    quiet = lambda s: None  # noqa: E731
+    full, hist_full = pilot.train(ctx, Zt, target, st, steps, batch=batch, seed=3, log=quiet, hist_every=1,
+                                  weighting="sigma")
+    ck = str(tmp_path / "ck.npz")
+    _, hist_a = pilot.train(ctx, Zt, target, st, steps, batch=batch, seed=3, ckpt=ck, ckpt_every=100, log=quiet,
+                            hist_every=1, weighting="sigma", stop_after=4)
+    assert [s for s, _ in hist_a] == [1, 2, 3, 4]
+    _, _, _, step, meta = pilot.load_checkpoint(ck)
+    assert step == 4 and meta["seed"] == 3
+    resumed, hist_b = pilot.train(ctx, Zt, target, st, steps, batch=batch, seed=3, ckpt=ck, ckpt_every=100,
+                                  log=quiet, hist_every=1, weighting="sigma")
+    say("loss history", hist_full)
+    assert hist_a + hist_b == hist_full
+    assert torch.equal(resumed, full)
