@@ -26,11 +26,12 @@ PEAKS = {"hbm": (HBM_PEAK_GBS, "GB/s", 1e9), "alu": (FP64_VALU_PEAK_TFLOPS, "TFL
          "mfma": (INT8_MFMA_PEAK_TOPS, "TOP/s", 1e12), "mfma_bf16": (BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", 1e12)}
 
 
-def algorithmic_work(H, W, search, k1, k2, bm_method="shift"):
-    """Per-launch algorithmic bytes (HBM-bound kernels), FLOP (shift-wise
-    matching on the fp64 vector ALU) or int8 operations (correlation matching
-    on the matrix cores: four byte-plane dot products of 64 per reference and
-    displacement, 2 operations per multiply-accumulate)."""
+def algorithmic_work(H, W, search, k1, k2):
+    """Per-launch algorithmic work of each kernel: bytes for the HBM-bound
+    ones; for block matching (either kernel) 5 FLOP of exact arithmetic per
+    (pixel, displacement) pair -- one difference, one fused square-accumulate
+    (2 FLOP) and the two running-sum additions of the box filter -- on the
+    fp64 vector ALU."""
     from paper_2103_10765_amd import gbm3d
     nref = gbm3d.n_refs(H, W, 3)
     R = search // 2
@@ -43,14 +44,8 @@ def algorithmic_work(H, W, search, k1, k2, bm_method="shift"):
     partial_bytes = n_tiles * FY * FXP * 8  # 64-bit fixed-point numerator footprints
     weight_bytes = H * W * 8  # 64-bit block-start weights
     S2 = search * search
-    if bm_method == "corr":
-        bm = ("mfma", nref * (S2 - 1) * 64 * 4 * 2.0, "OP")
-    else:
-        # one difference + one fused square-accumulate per (pixel, displacement)
-        bm = ("alu", 3.0 * H * W * (S2 - 1), "FLOP")
     return {
-        "bm": bm,
-        "bm_norm": ("hbm", H * W * 2 + (H + 64) * (W + 64) * 8, "B"),
+        "bm": ("alu", BM_FLOP_PER_PAIR * H * W * (S2 - 1), "FLOP"),
         # the bior launch and the first of the two DCT launches clear the weights
         "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes, "B"),
         "stack_dct": ("hbm", H * W * (2 + 256) + weight_bytes / 2, "B"),
@@ -62,9 +57,25 @@ def algorithmic_work(H, W, search, k1, k2, bm_method="shift"):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_denoise_512.txt")
+BM_FLOP_PER_PAIR = 5
+
+
+def bm_int8_view(H, W, search, avg_us):
+    """The correlation matcher read against the int8 matrix cores instead:
+    the 64 multiply-accumulates of one block inner product (2 operations
+    each) per (reference, displacement) pair."""
+    from paper_2103_10765_amd import gbm3d
+    ops = 2.0 * 64 * gbm3d.n_refs(H, W, 3) * (search * search - 1)
+    tops = ops / (avg_us * 1e-6) / 1e12
+    return {"ops_per_launch": ops, "achieved": tops, "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",
+            "frac": tops / INT8_MFMA_PEAK_TOPS}
+
+
+TRAFFIC_FILES = {512: os.path.join(ROOT, "profiles", "hbm_traffic_denoise_512.txt"),
+                 4096: os.path.join(ROOT, "profiles", "hbm_traffic_denoise_4096.txt")}
 KERNEL_SOURCES = {
-    "bm": ["bm.hip", "bm_corr.hip", "common.h"], "bm_norm": ["bm_corr.hip", "common.h"], "stack_bior": ["stack.hip", "common.h"], "stack_dct": ["stack.hip", "common.h"],
+    "bm": ["bm.hip", "bm_corr.hip", "common.h", "topk.h"],
+    "stack_bior": ["stack.hip", "common.h"], "stack_dct": ["stack.hip", "common.h"],
     "group_ht": ["group.hip", "common.h"], "group_wiener": ["group.hip", "common.h"], "reduce": ["group.hip", "common.h"],
 }
 
@@ -79,15 +90,17 @@ def source_digest(kernel):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary:
-    (FETCH_SIZE + WRITE_SIZE) per dispatch, each divided by what the same
-    counter reads per byte of a plain device copy of known size.  None when
-    the summary is missing or the kernel's sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(kernel, size=512):
+    """HBM bytes per launch of `kernel` on the size x size denoise from the
+    committed counter summary: (FETCH_SIZE + WRITE_SIZE) per dispatch, each
+    divided by what the same counter reads per byte of a plain device copy of
+    known size.  None when the summary is missing or the kernel's sources
+    changed since it was taken."""
+    path = TRAFFIC_FILES.get(size)
+    if not path or not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             parts = line.split()
             if len(parts) >= 2 and parts[0].startswith("@"):
@@ -465,6 +478,23 @@ def size_bench(ctx, p):
     return res
 
 
+def kernels_4096(ctx, p, steps=3):
+    """Per-kernel entries (as for the benchmark image) on the 4096^2
+    edge-rich image at sigma 25/255, where the patch stacks (4.3 GB each) are
+    far larger than the 256 MB last-level cache: the HBM-bound kernels' true
+    test."""
+    import torch
+    from paper_2103_10765_amd import synth
+    _, Z = synth.large_image_case(4096, synth.SIGMA25, 4)
+    Zt = torch.from_numpy(Z).cuda()
+    ctx.denoise(Zt, synth.SIGMA25, p)
+    torch.cuda.synchronize()
+    res = per_kernel(ctx, Zt, synth.SIGMA25, p, steps)
+    del Zt
+    torch.cuda.empty_cache()
+    return res
+
+
 def pilot_bench(ctx):
     """Learned pilot vs plain stage 1, both followed by the Wiener stage, on the
     32 x 512^2 evaluation batch at sigma 25/255 (needs trained weights)."""
@@ -476,6 +506,54 @@ def pilot_bench(ctx):
     with np.load(pilot.DEFAULT_WEIGHTS, allow_pickle=False) as f:
         master = torch.from_numpy(f["master"]).cuda()
     return pilot.evaluate(ctx, master, log=lambda s: None)
+
+
+def per_kernel(ctx, Zt, sigma, p, steps, variants=None):
+    """Average duration per launch of every kernel of the two-stage denoise
+    of Zt (library-recorded HIP events on the launch stream around each
+    launch, over `steps` denoise calls), with its algorithmic work against
+    the unit's spec peak, the counter-measured HBM bytes of the committed
+    summary for this image size (when the kernel's sources have not changed
+    since), and, with `variants`, the vector-instruction issue fraction."""
+    import torch
+    H, W = (int(v) for v in Zt.shape)
+    ctx.timing(True)
+    ctx.timing_reset()
+    for _ in range(steps):
+        ctx.denoise(Zt, sigma, p)
+    torch.cuda.synchronize()
+    kernels = {}
+    for name in ("bm", "stack_bior", "stack_dct", "group_ht", "group_wiener", "reduce"):
+        tot, n = ctx.timing_read(name)
+        if n:
+            kernels[name] = {"avg_us": 1e3 * tot / n, "launches_per_step": n / steps, "ms_per_step": tot / steps}
+    ctx.timing(False)
+    work = algorithmic_work(H, W, p.search, p.k_ht, p.k_wiener)
+    for name, k in kernels.items():
+        bound, amount, unit = work[name]
+        peak, punit, scale = PEAKS[bound]
+        k["bound"] = bound
+        k["work_per_launch"] = amount
+        k["work_unit"] = unit
+        k["achieved"] = amount / (k["avg_us"] * 1e-6) / scale
+        k["peak"] = peak
+        k["unit"] = punit
+        k["frac"] = k["achieved"] / peak
+        tb = measured_traffic(name, H if H == W else 0)
+        k["traffic_bytes"] = tb
+        if tb is not None:
+            # what the counters saw leave and enter HBM, over the same time
+            k["hbm_counted_GBps"] = tb / (k["avg_us"] * 1e-6) / 1e9
+            k["hbm_counted_frac"] = k["hbm_counted_GBps"] / HBM_PEAK_GBS
+        if name == "bm":
+            k["int8_view"] = bm_int8_view(H, W, p.search, k["avg_us"])
+        if variants:
+            # vector-instruction issue: committed SQ_INSTS_VALU of the same
+            # variants x 4 cycles over every SIMD's cycles of the measured time
+            insts = [measured_valu_insts(v, name) if v else None for v in variants.get(name, [])]
+            if insts and None not in insts:
+                k["valu_issue_frac"] = sum(insts) * 4 / (N_SIMD * CLOCK_HZ * len(insts) * k["avg_us"] * 1e-6)
+    return kernels
 
 
 def main():
@@ -568,26 +646,6 @@ def main():
     psnr = psnr_db(Y, clean)
 
     # per-kernel durations: the same steps with library-recorded events
-    ctx.timing(True)
-    ctx.timing_reset()
-    for _ in range(args.steps):
-        ctx.denoise(Zt, sigma, p, out=out)
-    torch.cuda.synchronize()
-    kernels = {}
-    for name in ("bm", "bm_norm", "stack_bior", "stack_dct", "group_ht", "group_wiener", "reduce"):
-        tot, n = ctx.timing_read(name)
-        if n:
-            kernels[name] = {"avg_us": 1e3 * tot / n, "launches_per_step": n / args.steps,
-                             "ms_per_step": tot / args.steps}
-    ctx.timing(False)
-
-    # the matching kernel both stages ran
-    if tuned:
-        methods = {v["method"] for v in tuned.values()}
-        bm_method = methods.pop() if len(methods) == 1 else "mixed"
-    else:
-        bm_method = args.bm_method
-    work = algorithmic_work(H, W, p.search, p.k_ht, p.k_wiener, bm_method)
     # the kernel variants this run launched, for the instruction counters
     def bm_variant(K):
         t = tuned.get(f"K{K}")
@@ -595,30 +653,19 @@ def main():
             return None
         s = t["split"]
         return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
-    variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
+    variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)],
                 "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"] * 2,
                 "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false>"],
                 "group_wiener": [f"group_wiener_kernel<{p.k_wiener}, false>"], "reduce": ["reduce_kernel<false>"] * 2}
-    for name, k in kernels.items():
-        bound, amount, unit = work[name]
-        peak, punit, scale = PEAKS[bound]
-        k["bound"] = bound
-        k["achieved"] = amount / (k["avg_us"] * 1e-6) / scale
-        k["unit"] = punit
-        k["frac"] = k["achieved"] / peak
-        k["traffic_bytes"] = measured_traffic(name)
-        # vector-instruction issue: committed SQ_INSTS_VALU of the same
-        # variants x 4 cycles over every SIMD's cycles of the measured time
-        insts = [measured_valu_insts(v, name) if v else None for v in variants.get(name, [])]
-        if insts and None not in insts:
-            k["valu_issue_frac"] = sum(insts) * 4 / (N_SIMD * CLOCK_HZ * len(insts) * k["avg_us"] * 1e-6)
+    kernels = per_kernel(ctx, Zt, sigma, p, args.steps, variants)
     dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
-    bound, amount, unit = work[dom]
-    peak, punit, scale = PEAKS[bound]
-    roof = {"bound": bound, "kernel": dom, "achieved": kernels[dom]["achieved"], "peak": peak, "unit": punit,
-            "frac": kernels[dom]["frac"], "traffic": measured_traffic(dom), "avg_us": kernels[dom]["avg_us"],
-            "work_per_launch": amount, "work_unit": unit,
-            "valu_issue_frac": kernels[dom].get("valu_issue_frac")}
+    k = kernels[dom]
+    roof = {"bound": k["bound"], "kernel": dom, "achieved": k["achieved"], "peak": k["peak"], "unit": k["unit"],
+            "frac": k["frac"], "traffic": k["traffic_bytes"], "avg_us": k["avg_us"],
+            "work_per_launch": k["work_per_launch"], "work_unit": k["work_unit"],
+            "valu_issue_frac": k.get("valu_issue_frac")}
+    if "int8_view" in k:
+        roof["int8_view"] = k["int8_view"]
 
     rec = {
         "metric": "Mpixel/s two-stage denoise at sigma=25 (plain vs learned pilot) + PSNR gap, 1 GPU",
@@ -652,6 +699,7 @@ def main():
             rec["pilot"]["conv"] = pilot_conv_rate(ctx)
         rec["batch"] = batch_bench(ctx)
         rec["sizes"] = size_bench(ctx, p)
+        rec["kernels_4096"] = kernels_4096(ctx, p)
         rec["sigmas"] = sigma_bench(ctx, p, (H, W))
         from paper_2103_10765_amd import pnp
         rec["pnp"] = pnp.bench(ctx)
@@ -666,6 +714,15 @@ def main():
             if k["bound"] == "hbm":
                 k["frac_of_measured_copy"] = k["achieved"] / mp["copy_GBps"]
             k["frac_of_measured_peak"] = k["achieved"] / measured[k["bound"]]
+        for k in rec["kernels_4096"].values():
+            if k["bound"] == "hbm":
+                k["frac_of_measured_copy"] = k["achieved"] / mp["copy_GBps"]
+                if "hbm_counted_GBps" in k:
+                    k["hbm_counted_frac_of_copy"] = k["hbm_counted_GBps"] / mp["copy_GBps"]
+            k["frac_of_measured_peak"] = k["achieved"] / measured[k["bound"]]
+        for k in kernels.values():
+            if "hbm_counted_GBps" in k:
+                k["hbm_counted_frac_of_copy"] = k["hbm_counted_GBps"] / mp["copy_GBps"]
         roof["frac_of_measured_peak"] = roof["achieved"] / measured[roof["bound"]]
         gr = rec["global_stage1"]["roofline"]
         gr["frac_of_measured_peak"] = gr["achieved"] / mp["fp64_fma_TFLOPs"]
