@@ -31,7 +31,7 @@
 // c = 256 (Phh - Yh) + Phl + Plh - nh; since |Pll - Yl| < 2^21, clamping c
 // to [-2^13, 2^13] keeps the sign, so a pair survives iff
 // 256 clamp(c) + Pll > Yl.  The few survivors are parked
-// raw (s', Pll, position) in the lane's LDS buffer; when some lane's buffer
+// raw (c, Pll, position) in the lane's LDS buffer; when some lane's buffer
 // is nearly full, every lane forms the exact keys of its parked pairs in
 // float64 (integers below 2^51), drops those outside its window and merges
 // them into its sorted list.  The first blocks of each wave (those nearest
@@ -539,8 +539,8 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 #pragma unroll
       for (int e = 0; e < KB; ++e) {
         if (e >= cnt) w[e] = 0ull;
-        const int w0 = static_cast<int>(static_cast<unsigned>(w[e])), w1 = static_cast<int>(w[e] >> 32);
-        const int cy = 4 * ((w1 >> 4) & 15) + g, cx = 4 * (w1 & 15) + (w0 & 3);
+        const int w1 = static_cast<int>(w[e] >> 32);
+        const int cy = 4 * ((w1 >> 4) & 15) + g, cx = 4 * (w1 & 15) + ((w1 >> 8) & 3);
         nlv[e] = nlo[cy * G::kCandCols + cbase + cx];
       }
       double b[P];
@@ -548,8 +548,8 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       for (int e = 0; e < P; ++e) {
         if (e < KB) {
           const int w0 = static_cast<int>(static_cast<unsigned>(w[e])), w1 = static_cast<int>(w[e] >> 32);
-          const int cy = 4 * ((w1 >> 4) & 15) + g, cx = 4 * (w1 & 15) + (w0 & 3);
-          const double key = exact_key(w0 >> 2, w1 >> 10, cy, cx, nlv[e]);
+          const int cy = 4 * ((w1 >> 4) & 15) + g, cx = 4 * (w1 & 15) + ((w1 >> 8) & 3);
+          const double key = exact_key(w0 + 256 * yh, w1 >> 10, cy, cx, nlv[e]);
           b[e] = e < cnt ? key : kInf;
         } else {
           b[e] = kInf;
@@ -572,13 +572,13 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       const unsigned pos = static_cast<unsigned>(o.br << 4 | o.bc);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int c = o.hh[i] * 256 + o.cc[i];
+        const int c = o.hh[i] * 256 + o.cc[i];  // s' - 256 Yh
         const int cl = c < -8192 ? -8192 : (c > 8192 ? 8192 : c);
         if (cl * 256 + o.ll[i] > ylb) {
-          const int sp = (o.hh[i] + o.yh) * 256 + o.cc[i];
-          const unsigned lo = (static_cast<unsigned>(sp) << 2) | static_cast<unsigned>(i);
-          const unsigned hi = (static_cast<unsigned>(o.ll[i]) << 10) | pos;
-          mybuf[cnt * kWave] = (static_cast<unsigned long long>(hi) << 32) | lo;
+          // c as is (s' = c + 256 Yh: Yh stays until the next merge), and
+          // Pll above the candidate's column in the block and the block's position
+          const unsigned hi = (static_cast<unsigned>(o.ll[i]) << 10) | (static_cast<unsigned>(i) << 8) | pos;
+          mybuf[cnt * kWave] = (static_cast<unsigned long long>(hi) << 32) | static_cast<unsigned>(c);
           ++cnt;
         }
       }
