@@ -46,6 +46,8 @@ def algorithmic_work(H, W, search, k1, k2):
     S2 = search * search
     return {
         "bm": ("alu", BM_FLOP_PER_PAIR * H * W * (S2 - 1), "FLOP"),
+        # pixels in; one float64 table entry out per bordered position
+        "bm_norm": ("hbm", H * W * 2 + (H + 64) * (W + 64) * 8, "B"),
         # the bior launch and the first of the two DCT launches clear the weights
         "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes, "B"),
         "stack_dct": ("hbm", H * W * (2 + 256) + weight_bytes / 2, "B"),
@@ -74,7 +76,7 @@ def bm_int8_view(H, W, search, avg_us):
 TRAFFIC_FILES = {512: os.path.join(ROOT, "profiles", "hbm_traffic_denoise_512.txt"),
                  4096: os.path.join(ROOT, "profiles", "hbm_traffic_denoise_4096.txt")}
 KERNEL_SOURCES = {
-    "bm": ["bm.hip", "bm_corr.hip", "common.h", "topk.h"],
+    "bm": ["bm.hip", "bm_corr.hip", "common.h", "topk.h"], "bm_norm": ["bm_corr.hip", "common.h"],
     "stack_bior": ["stack.hip", "common.h"], "stack_dct": ["stack.hip", "common.h"],
     "group_ht": ["group.hip", "common.h"], "group_wiener": ["group.hip", "common.h"], "reduce": ["group.hip", "common.h"],
 }
@@ -523,7 +525,7 @@ def per_kernel(ctx, Zt, sigma, p, steps, variants=None):
         ctx.denoise(Zt, sigma, p)
     torch.cuda.synchronize()
     kernels = {}
-    for name in ("bm", "stack_bior", "stack_dct", "group_ht", "group_wiener", "reduce"):
+    for name in ("bm", "bm_norm", "stack_bior", "stack_dct", "group_ht", "group_wiener", "reduce"):
         tot, n = ctx.timing_read(name)
         if n:
             kernels[name] = {"avg_us": 1e3 * tot / n, "launches_per_step": n / steps, "ms_per_step": tot / steps}
@@ -653,7 +655,7 @@ def main():
             return None
         s = t["split"]
         return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
-    variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)],
+    variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
                 "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"] * 2,
                 "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false>"],
                 "group_wiener": [f"group_wiener_kernel<{p.k_wiener}, false>"], "reduce": ["reduce_kernel<false>"] * 2}

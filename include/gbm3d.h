@@ -230,7 +230,7 @@ int gbm3d_global_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W,
 /* gbm3d_denoise for callers that cannot allocate device memory: code under
  * hipGraph stream capture, tight serving loops, hosts that forbid hipMalloc.
  * Same arguments, validation and result (bit for bit) as gbm3d_denoise, but
- * every intermediate buffer (two patch stacks, match indices,
+ * every intermediate buffer (norm table, two patch stacks, match indices,
  * aggregation sums, and the basic estimate and pilot when basic_out / q_out
  * are NULL) is a slice of one static device array of
  * GBM3D_NOALLOC_SCRATCH_BYTES per device, which the library holds on every
@@ -321,7 +321,7 @@ int gbm3d_pilot_adam(gbm3d_ctx* ctx, float* master, float* m, float* v, const fl
 /* Per-kernel timing for benchmarking.  While enabled, the context brackets
  * every kernel it launches with two HIP events recorded on the launch stream.
  * gbm3d_timing_read synchronises the pending events and returns, for one
- * kernel name ("bm", "stack_bior", "stack_dct", "group_ht",
+ * kernel name ("bm", "bm_norm", "stack_bior", "stack_dct", "group_ht",
  * "group_wiener", "reduce"), the summed elapsed milliseconds and the number of
  * launches since the last reset.  Off by default. */
 int gbm3d_timing_enable(gbm3d_ctx* ctx, int on);

@@ -68,7 +68,7 @@ void* scratch_addr(int dev) {
 }
 
 // Work lists of the batch phases: per-image prefix offsets of the items.
-enum Phase { kBm1, kStack1, kGroup1, kReduce1, kBm2, kStack2, kGroup2, kReduce2, kPhases };
+enum Phase { kNorm1, kBm1, kStack1, kGroup1, kReduce1, kNorm2, kBm2, kStack2, kGroup2, kReduce2, kPhases };
 
 struct BatchPlan {
   std::vector<ImgRec> recs;
@@ -96,7 +96,7 @@ struct gbm3d_ctx {
   int device = 0;
   int n_cu = 256;
   std::string err;
-  Buffer stack_a, stack_b, idx, partials, basic, q;
+  Buffer stack_a, stack_b, idx, partials, basic, q, norm;
   // global stage 1
   Buffer gl_a, gl_b, gl_num, gl_idx, gl_shift, gl_pad, gl_out;
   // block-matching choices per (K, shape class)
@@ -312,8 +312,15 @@ BmChoice choose_bm(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles, int 
 }
 
 // Block matching of one image (r.noisy, or r.pilot with use_pilot) into r.idx.
+// The correlation kernel's norm table is r.norm when set, else the context's.
 int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const BmChoice& c, int use_pilot, hipStream_t st) {
   if (c.method == GBM3D_BM_CORR) {
+    if (!r.norm) {
+      CHECK(ensure(ctx, ctx->norm, gbm3d::norm_bytes(r.H, r.W), "norm table"));
+      r.norm = static_cast<double*>(ctx->norm.p);
+    }
+    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(r, nullptr, R, use_pilot, 0, st); }),
+            "norm table launch");
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
               return gbm3d::launch_bm_corr(r, nullptr, R, K, c.split, use_pilot, 0, st);
             }),
@@ -338,6 +345,7 @@ struct Workspace {
   float* stack_b = nullptr;
   int16_t* idx = nullptr;
   unsigned long long* partials = nullptr;
+  double* norm = nullptr;
 };
 
 // Stage 1 of one image into `basic` (and optionally its quantisation into q).
@@ -365,6 +373,7 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
   r.stack_a = recompute ? nullptr : w.stack_a;
   r.idx = w.idx;
   r.partials = w.partials;
+  r.norm = w.norm;
   r.eps = tv_eps(p, sigma);
   CHECK(run_match(ctx, r, R, p.k_ht, p, 0, st));
   if (recompute)
@@ -406,6 +415,7 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
   r.stack_b = w.stack_b;
   r.idx = w.idx;
   r.partials = w.partials;
+  r.norm = w.norm;
   CHECK(run_match(ctx, r, R, p.k_wiener, p, 1, st));
   HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 0, 0, 0, st); }),
           "stack launch");
@@ -453,6 +463,7 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
   };
   plan.bm_split1 = split_of(c1, tiles1, waves1);
   plan.bm_split2 = split_of(c2, tiles2, waves2);
+  const bool need_norm = (tiles1 > 0 && c1.method == GBM3D_BM_CORR) || (tiles2 > 0 && c2.method == GBM3D_BM_CORR);
   // workspace slices
   size_t total = 0;
   std::vector<size_t> off(n);
@@ -460,6 +471,7 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
     const int H = imgs[i].H, W = imgs[i].W;
     const bool s1 = imgs[i].pilot == nullptr;
     off[i] = total;
+    if (need_norm) total += align256(gbm3d::norm_bytes(H, W));              // norm table
     total += align256(stack_bytes(H, W));                                   // stack_a
     if (!basic_only) total += align256(stack_bytes(H, W));                  // stack_b
     total += align256(n_refs(H, W) * kmax * sizeof(int16_t));               // idx
@@ -475,6 +487,10 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
     const bool s1 = im.pilot == nullptr;
     ImgRec r = blank_rec(H, W, im.sigma);
     char* c = base + off[i];
+    if (need_norm) {
+      r.norm = reinterpret_cast<double*>(c);
+      c += align256(gbm3d::norm_bytes(H, W));
+    }
     r.stack_a = reinterpret_cast<float*>(c);
     c += align256(stack_bytes(H, W));
     if (!basic_only) {
@@ -510,14 +526,13 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
     const bool s2 = !basic_only;
     const bool corr1 = plan.bm_method1 == GBM3D_BM_CORR, corr2 = plan.bm_method2 == GBM3D_BM_CORR;
     const int items[kPhases] = {
-        s1 ? (corr1 ? gbm3d::corr_items_for(H, W, p.k_ht, plan.bm_split1) : gbm3d::bm_items_for(H, W, plan.bm_split1))
-           : 0,
+        s1 && corr1 ? gbm3d::norm_items_for(H, W) : 0,
+        s1 ? (corr1 ? gbm3d::corr_items_for(H, W, plan.bm_split1) : gbm3d::bm_items_for(H, W, plan.bm_split1)) : 0,
         s1 ? gbm3d::stack_items_for(H, W) : 0,
         s1 ? gbm3d::group_items_for(H, W, R) : 0,
         s1 ? gbm3d::reduce_items_for(H, W) : 0,
-        s2 ? (corr2 ? gbm3d::corr_items_for(H, W, p.k_wiener, plan.bm_split2)
-                    : gbm3d::bm_items_for(H, W, plan.bm_split2))
-           : 0,
+        s2 && corr2 ? gbm3d::norm_items_for(H, W) : 0,
+        s2 ? (corr2 ? gbm3d::corr_items_for(H, W, plan.bm_split2) : gbm3d::bm_items_for(H, W, plan.bm_split2)) : 0,
         s2 ? gbm3d::stack_items_for(H, W) : 0,
         s2 ? gbm3d::group_items_for(H, W, R) : 0,
         s2 ? gbm3d::reduce_items_for(H, W) : 0,
@@ -537,14 +552,16 @@ WorkList worklist(const gbm3d_ctx* ctx, const BatchPlan& plan, int n, int phase)
   return w;
 }
 
-// Batch matching phase.
-int launch_batch_match(gbm3d_ctx* ctx, const WorkList& bm, int R, int K, int method, int split, int use_pilot,
-                       hipStream_t st) {
+// Batch matching phase: norm tables first when the correlation kernel runs.
+int launch_batch_match(gbm3d_ctx* ctx, const WorkList& nm, const WorkList& bm, int R, int K, int method, int split,
+                       int use_pilot, hipStream_t st) {
   const ImgRec none = blank_rec(0, 0, 0.0f);
   const int cu = ctx->n_cu;
   if (method == GBM3D_BM_CORR) {
+    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(none, &nm, R, use_pilot, 4 * cu, st); }),
+            "batch norm tables");
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
-              return gbm3d::launch_bm_corr(none, &bm, R, K, split, use_pilot, 2 * cu, st);
+              return gbm3d::launch_bm_corr(none, &bm, R, K, split, use_pilot, 4 * cu, st);
             }),
             "batch block matching");
   } else {
@@ -562,10 +579,10 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
   const ImgRec none = blank_rec(0, 0, 0.0f);
   const int cu = ctx->n_cu;
   if (plan.any_stage1) {
-    const WorkList bm = worklist(ctx, plan, n, kBm1);
+    const WorkList nm = worklist(ctx, plan, n, kNorm1), bm = worklist(ctx, plan, n, kBm1);
     const WorkList sk = worklist(ctx, plan, n, kStack1);
     const WorkList gr = worklist(ctx, plan, n, kGroup1), rd = worklist(ctx, plan, n, kReduce1);
-    CHECK(launch_batch_match(ctx, bm, R, p.k_ht, plan.bm_method1, plan.bm_split1, 0, st));
+    CHECK(launch_batch_match(ctx, nm, bm, R, p.k_ht, plan.bm_method1, plan.bm_split1, 0, st));
     HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, 2 * cu, st); }),
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
@@ -576,10 +593,10 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
             "batch aggregation");
   }
   if (plan.any_stage2) {
-    const WorkList bm = worklist(ctx, plan, n, kBm2);
+    const WorkList nm = worklist(ctx, plan, n, kNorm2), bm = worklist(ctx, plan, n, kBm2);
     const WorkList sk = worklist(ctx, plan, n, kStack2);
     const WorkList gr = worklist(ctx, plan, n, kGroup2), rd = worklist(ctx, plan, n, kReduce2);
-    CHECK(launch_batch_match(ctx, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
+    CHECK(launch_batch_match(ctx, nm, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
     HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, 2 * cu, st); }),
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, 2 * cu, st); }),
@@ -702,7 +719,7 @@ void gbm3d_destroy(gbm3d_ctx* ctx) {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     drop_graph(ctx);
-    for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->batch_ws,
+    for (Buffer* b : {&ctx->stack_a, &ctx->stack_b, &ctx->idx, &ctx->partials, &ctx->basic, &ctx->q, &ctx->norm, &ctx->batch_ws,
                       &ctx->batch_table, &ctx->pilot_w, &ctx->pilot_act, &ctx->pilot_part, &ctx->gl_a, &ctx->gl_b,
                       &ctx->gl_num, &ctx->gl_idx, &ctx->gl_shift, &ctx->gl_pad, &ctx->gl_out})
       if (b->p) (void)hipFree(b->p);
@@ -1066,6 +1083,7 @@ int gbm3d_denoise_noalloc(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, f
     off += align256(bytes);
     return o;
   };
+  const size_t o_norm = take(gbm3d::norm_bytes(H, W));
   const size_t o_sa = take(stack_bytes(H, W));
   const size_t o_sb = take(stack_bytes(H, W));
   const size_t o_idx = take(n_refs(H, W) * std::max(p.k_ht, p.k_wiener) * sizeof(int16_t));
@@ -1080,6 +1098,7 @@ int gbm3d_denoise_noalloc(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, f
   char* base = static_cast<char*>(scratch_addr(ctx->device));
   if (!base) return fail(ctx, GBM3D_EHIP, "device scratch of device %d not resolved", ctx->device);
   Workspace ws;
+  ws.norm = reinterpret_cast<double*>(base + o_norm);
   ws.stack_a = reinterpret_cast<float*>(base + o_sa);
   ws.stack_b = reinterpret_cast<float*>(base + o_sb);
   ws.idx = reinterpret_cast<int16_t*>(base + o_idx);

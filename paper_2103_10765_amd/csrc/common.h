@@ -259,6 +259,7 @@ struct ImgRec {
   unsigned long long* partials;    // 64-bit fixed-point aggregation sums: H*W block-start
                                    // weights (cleared by the stack launch into stack_a),
                                    // then the tiles' numerator footprints
+  double* norm;                    // block norms with a periodic border (correlation matching)
   int H, W;
   float sigma, eps;
 };

@@ -25,11 +25,17 @@ long bm_waves_unsplit(int H, int W);
 int bm_items_for(int H, int W, int split);
 
 // Correlation-form matching (Theorem 1, int8 matrix cores): the same indices.
-// Each workgroup forms the block norms it needs itself.  split: waves
-// sharing a 4x4 reference tile (1, 2, 4; 0 = by size).
+// launch_bm_norm writes rec.norm (norm_bytes: the block norms of the noisy or
+// pilot image with a periodic border, times 2048, plus a column term that
+// depends on R) and must precede launch_bm_corr with the same R on the
+// stream.  split: waves sharing a 4x4 reference tile (1, 2, 4; 0 = by size).
+hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int R, int use_pilot, int grid_cap,
+                          hipStream_t st);
 hipError_t launch_bm_corr(const ImgRec& one, const WorkList* wl, int R, int K, int split, int use_pilot, int grid_cap,
                           hipStream_t st);
-int corr_items_for(int H, int W, int K, int split);
+size_t norm_bytes(int H, int W);
+int norm_items_for(int H, int W);
+int corr_items_for(int H, int W, int split);
 long corr_tiles(int H, int W);
 int corr_auto_split(long tiles);
 
