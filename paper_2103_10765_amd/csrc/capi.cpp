@@ -571,9 +571,11 @@ int launch_batch_match(gbm3d_ctx* ctx, const WorkList& nm, const WorkList& bm, i
   return GBM3D_OK;
 }
 
-// The batch launch sequence (also what a graph captures).  Persistent grids:
-// two matching / stack workgroups, one group workgroup and eight reduction
-// workgroups per compute unit.
+// The batch launch sequence (also what a graph captures).  Persistent grids
+// of as many workgroups as fit each compute unit together: four matching
+// (correlation) or stack workgroups, two shift-wise matching ones, two
+// hard-threshold group tiles (groups up to 16) or one, and eight reduction
+// workgroups.
 int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_params& p, hipStream_t st) {
   const int R = p.search / 2;
   const ImgRec none = blank_rec(0, 0, 0.0f);
@@ -583,10 +585,11 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
     const WorkList sk = worklist(ctx, plan, n, kStack1);
     const WorkList gr = worklist(ctx, plan, n, kGroup1), rd = worklist(ctx, plan, n, kReduce1);
     CHECK(launch_batch_match(ctx, nm, bm, R, p.k_ht, plan.bm_method1, plan.bm_split1, 0, st));
-    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, 2 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, 4 * cu, st); }),
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
-              return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0, cu, st);
+              return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0,
+                                            (p.k_ht <= 16 ? 2 : 1) * cu, st);
             }),
             "batch hard-threshold groups");
     HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 0, 8 * cu, st); }),
@@ -597,9 +600,9 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
     const WorkList sk = worklist(ctx, plan, n, kStack2);
     const WorkList gr = worklist(ctx, plan, n, kGroup2), rd = worklist(ctx, plan, n, kReduce2);
     CHECK(launch_batch_match(ctx, nm, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
-    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, 2 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, 4 * cu, st); }),
             "batch stack");
-    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, 2 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, 4 * cu, st); }),
             "batch pilot stack");
     HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
               return gbm3d::launch_group_wiener(none, &gr, R, p.k_wiener, cu, st);

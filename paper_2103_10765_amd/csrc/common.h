@@ -271,27 +271,29 @@ struct WorkList {
   int total;           // begin[n]
 };
 
-// image owning work item `item` (begin is non-decreasing, begin[0] = 0)
-__device__ __forceinline__ int find_image(const int* __restrict__ begin, int n, int item) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (begin[mid] <= item) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Runs body(rec, local_item) for this workgroup's items: the single image's
-// item blockIdx.x, or every batch item blockIdx.x + k * gridDim.x.
+// item blockIdx.x, or every batch item blockIdx.x + k * gridDim.x.  A
+// workgroup's batch items increase, so the image owning the next one is found
+// by stepping forward from the current one through the per-image prefix
+// offsets (begin is non-decreasing, begin[0] = 0, begin[n] = total; wave-
+// uniform scalar loads), and its descriptor is reloaded only when it changes.
 template <bool BATCH, typename F>
 __device__ __forceinline__ void for_each_item(const ImgRec& one, const WorkList& wl, F&& body) {
   if constexpr (!BATCH) {
     body(one, static_cast<int>(blockIdx.x));
   } else {
+    int i = -1, lo = 0, hi = 0;  // image i owns items [lo, hi)
+    ImgRec r;
     for (int item = blockIdx.x; item < wl.total; item += gridDim.x) {
-      const int i = find_image(wl.begin, wl.n, item);
-      const ImgRec r = wl.recs[i];
-      body(r, item - wl.begin[i]);
+      if (item >= hi) {
+        do {
+          ++i;
+          lo = hi;
+          hi = wl.begin[i + 1];
+        } while (item >= hi);
+        r = wl.recs[i];
+      }
+      body(r, item - lo);
       __syncthreads();  // LDS is reused by the next item
     }
   }

@@ -63,7 +63,7 @@ struct Foot {
 // the batched variant carries more state per wave and keeps one tile per CU.
 template <int K, bool HT, bool BATCH>
 struct GroupCfg {
-  static constexpr bool two_tiles = HT && K <= 16 && !BATCH;
+  static constexpr bool two_tiles = HT && K <= 16;
   static constexpr int chunk = two_tiles ? (K > 8 ? 8 : K) : (K > 16 ? 16 : K);
   static constexpr int waves =
       two_tiles ? 12
