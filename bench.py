@@ -626,6 +626,16 @@ def main():
         for K in (p.k_ht, p.k_wiener):
             m, sp, t = ctx.autotune(Zt, K, reps=3)
             tuned[f"K{K}"] = {"method": {1: "shift", 2: "corr"}[m], "split": sp, "ms": t}
+        # the stage-1 group-kernel shape the autotuner chose (from its records)
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            ctx.tune_save(os.path.join(td, "tune.txt"))
+            for ln in open(os.path.join(td, "tune.txt")):
+                f = ln.split()
+                if f[0] == "ht" and int(f[1]) == p.k_ht and int(f[2]) == p.search:
+                    tuned["stage1_groups"] = {"shape": ["two tiles of 12 waves per CU",
+                                                        "one tile of 16 waves, prefetch"][int(f[4])],
+                                              "ms_stage1": float(f[5])}
     else:
         p.bm_method = {"shift": gbm3d.BM_SHIFT, "corr": gbm3d.BM_CORR}[args.bm_method]
 
@@ -657,7 +667,8 @@ def main():
         return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
     variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
                 "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"] * 2,
-                "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false>"],
+                "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false, "
+                             f"{'false' if tuned.get('stage1_groups', {}).get('shape', '').startswith('one') else 'true'}>"],
                 "group_wiener": [f"group_wiener_kernel<{p.k_wiener}, false>"], "reduce": ["reduce_kernel<false>"] * 2}
     kernels = per_kernel(ctx, Zt, sigma, p, args.steps, variants)
     dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])

@@ -328,23 +328,33 @@ int gbm3d_timing_enable(gbm3d_ctx* ctx, int on);
 int gbm3d_timing_read(gbm3d_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 int gbm3d_timing_reset(gbm3d_ctx* ctx);
 
-/* Autotuner of the block-matching launch.  Times every variant (GBM3D_BM_SHIFT
- * and GBM3D_BM_CORR, each with bm_split 1, 2 and 4) on the device image img
- * [H][W] with group size K, `reps` runs each after one warm-up run, with HIP
- * events on `stream` (the call synchronises it), and records the fastest for
- * the shape class of (H, W, K): the number of 4x4 reference tiles rounded down
- * to a power of two.  Later calls whose params leave bm_method or bm_split at
- * 0 use the recorded choice of their class (a batch: the class of all its
- * tiles together); without one, the method recorded for the nearest class of
- * the same K with the split chosen by size; else GBM3D_BM_CORR.
- * Indices do not depend on the choice.  best_method, best_split and best_ms (milliseconds per run) may be
- * NULL.  Errors: GBM3D_EINVAL for bad shapes, K or reps < 1. */
-int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, int reps, int* best_method,
-                   int* best_split, float* best_ms, void* stream);
+/* Autotuner of the launch configuration (the paper's method does not depend
+ * on it; results are identical for every choice).  With the caller's params
+ * (NULL = defaults; search, and for the shape below k_ht and the stage-1
+ * options), on the device image img [H][W]:
+ *   - times every block-matching variant (GBM3D_BM_SHIFT and GBM3D_BM_CORR,
+ *     each with bm_split 1, 2 and 4) with group size K, `reps` runs each
+ *     after one warm-up run, and records the fastest;
+ *   - when K == params.k_ht <= 16, also times whole stage-1 runs (that
+ *     matching, sigma 25/255) with each of the two shapes of the stage-1
+ *     group kernel (two tiles of 12 waves per compute unit, or one tile of
+ *     16 waves that prefetches the next group) and records the faster.
+ * Records are keyed by (K, search, shape class of (H, W): the number of 4x4
+ * reference tiles rounded down to a power of two).  Later calls whose params
+ * leave bm_method or bm_split at 0 use the record of their class (a batch:
+ * the class of all its tiles together); without one, the method recorded for
+ * the nearest class of the same K and search, with the split chosen by size;
+ * else GBM3D_BM_CORR.  The stage-1 shape likewise (default: two tiles).
+ * Timing uses HIP events on `stream` (the call synchronises it).
+ * best_method, best_split and best_ms (milliseconds per matching run) may be
+ * NULL.  Errors: GBM3D_EINVAL for bad shapes, params, K or reps < 1. */
+int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, const gbm3d_params* params,
+                   int reps, int* best_method, int* best_split, float* best_ms, void* stream);
 
-/* The recorded choices as text, one "K class method split ms" line each:
- * gbm3d_tune_save writes them to `path`, gbm3d_tune_load adds those of `path`
- * to the context (GBM3D_EINVAL if the file cannot be read or parsed). */
+/* The recorded choices as text, one line each: "bm K search class method
+ * split ms" or "ht K search class shape ms".  gbm3d_tune_save writes them to
+ * `path`, gbm3d_tune_load adds those of `path` to the context (GBM3D_EINVAL,
+ * adding nothing, if the file cannot be read or a line parsed). */
 int gbm3d_tune_save(const gbm3d_ctx* ctx, const char* path);
 int gbm3d_tune_load(gbm3d_ctx* ctx, const char* path);
 

@@ -75,6 +75,7 @@ struct BatchPlan {
   std::vector<int> begin[kPhases];  // n + 1 each
   int bm_method1 = GBM3D_BM_SHIFT, bm_method2 = GBM3D_BM_SHIFT;
   int bm_split1 = 1, bm_split2 = 1;
+  int ht_shape = 0;  // stage-1 group kernel shape
   bool any_stage1 = false, any_stage2 = false;
 };
 
@@ -82,6 +83,20 @@ struct BatchPlan {
 struct TuneEntry {
   int method = GBM3D_BM_SHIFT, split = 1;
   float ms = 0.0f;
+};
+
+// A stage-1 group-kernel shape recorded by the autotuner.
+struct ShapeEntry {
+  int shape = 0;
+  float ms = 0.0f;
+};
+
+// Tuning key: group size, search window, shape class of the image(s).
+struct TuneKey {
+  int K, search, cls;
+  bool operator<(const TuneKey& o) const {
+    return K != o.K ? K < o.K : (search != o.search ? search < o.search : cls < o.cls);
+  }
 };
 
 struct GraphEntry {
@@ -100,7 +115,8 @@ struct gbm3d_ctx {
   // global stage 1
   Buffer gl_a, gl_b, gl_num, gl_idx, gl_shift, gl_pad, gl_out;
   // block-matching choices per (K, shape class)
-  std::map<std::pair<int, int>, TuneEntry> tuned;
+  std::map<TuneKey, TuneEntry> tuned;
+  std::map<TuneKey, ShapeEntry> tuned_shape;  // stage-1 group kernel, keyed by k_ht
   // batches
   Buffer batch_ws, batch_table;
   void* host_stage = nullptr;  // pinned staging of the batch table
@@ -287,21 +303,21 @@ struct BmChoice {
   int method, split;  // split 0: by size inside the launcher
 };
 
-// Explicit params win.  Zeros take the tuned choice of the class; without one,
-// the method of the nearest tuned class of the same K (split then by size),
-// else the default.
+// Explicit params win.  Zeros take the tuned choice of the class (same K and
+// search); without one, the method of the nearest tuned class of the same K
+// and search (split then by size), else the default.
 BmChoice choose_bm(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles, int K) {
   BmChoice c{p.bm_method, p.bm_split};
   const int cls = tile_class(tiles);
-  const auto it = ctx->tuned.find({K, cls});
+  const auto it = ctx->tuned.find({K, p.search, cls});
   if (it != ctx->tuned.end()) {
     if (c.method == GBM3D_BM_AUTO) c.method = it->second.method;
     if (c.split == 0 && c.method == it->second.method) c.split = it->second.split;
   } else if (c.method == GBM3D_BM_AUTO) {
     int best = 1 << 30;
     for (const auto& kv : ctx->tuned) {
-      const int d = std::abs(kv.first.second - cls);
-      if (kv.first.first == K && d < best) {
+      const int d = std::abs(kv.first.cls - cls);
+      if (kv.first.K == K && kv.first.search == p.search && d < best) {
         best = d;
         c.method = kv.second.method;
       }
@@ -309,6 +325,23 @@ BmChoice choose_bm(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles, int 
   }
   if (c.method == GBM3D_BM_AUTO) c.method = GBM3D_BM_CORR;  // the faster kernel on every measured shape
   return c;
+}
+
+// The stage-1 group-kernel shape: the tuned one of the class, else that of
+// the nearest tuned class of the same k_ht and search, else two tiles per CU.
+int choose_shape(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles) {
+  const int cls = tile_class(tiles);
+  const auto it = ctx->tuned_shape.find({p.k_ht, p.search, cls});
+  if (it != ctx->tuned_shape.end()) return it->second.shape;
+  int best = 1 << 30, shape = 0;
+  for (const auto& kv : ctx->tuned_shape) {
+    const int d = std::abs(kv.first.cls - cls);
+    if (kv.first.K == p.k_ht && kv.first.search == p.search && d < best) {
+      best = d;
+      shape = kv.second.shape;
+    }
+  }
+  return shape;
 }
 
 // Block matching of one image (r.noisy, or r.pilot with use_pilot) into r.idx.
@@ -382,8 +415,8 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
     HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(r, nullptr, 0, 0, 0, 0, st); }),
             "stack launch");
   HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
-            return gbm3d::launch_group_ht(r, nullptr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, recompute, 0,
-                                          st);
+            return gbm3d::launch_group_ht(r, nullptr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, recompute,
+                                          choose_shape(ctx, p, gbm3d::corr_tiles(H, W)), 0, st);
           }),
           "hard-threshold group launch");
   HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, R, 0, 0, st); }),
@@ -463,6 +496,7 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
   };
   plan.bm_split1 = split_of(c1, tiles1, waves1);
   plan.bm_split2 = split_of(c2, tiles2, waves2);
+  plan.ht_shape = choose_shape(ctx, p, tiles1);
   const bool need_norm = (tiles1 > 0 && c1.method == GBM3D_BM_CORR) || (tiles2 > 0 && c2.method == GBM3D_BM_CORR);
   // workspace slices
   size_t total = 0;
@@ -589,7 +623,8 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
               return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0,
-                                            (p.k_ht <= 16 ? 2 : 1) * cu, st);
+                                            plan.ht_shape, gbm3d::group_ht_tiles_per_cu(p.k_ht, plan.ht_shape) * cu,
+                                            st);
             }),
             "batch hard-threshold groups");
     HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 0, 8 * cu, st); }),
@@ -659,6 +694,7 @@ std::string graph_key(const BatchPlan& plan, int n, const gbm3d_params& p, int f
   add(&plan.bm_split2, sizeof(int));
   add(&plan.bm_method1, sizeof(int));
   add(&plan.bm_method2, sizeof(int));
+  add(&plan.ht_shape, sizeof(int));
   for (int ph = 0; ph < kPhases; ++ph) add(plan.begin[ph].data(), sizeof(int) * (n + 1));
   return k;
 }
@@ -774,15 +810,16 @@ int gbm3d_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, const 
   return run_match(ctx, r, p.search / 2, K, p, 0, st);
 }
 
-int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, int reps, int* best_method,
-                   int* best_split, float* best_ms, void* stream) {
-  gbm3d_params p;
-  gbm3d_default_params(&p);
+int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, const gbm3d_params* params, int reps,
+                   int* best_method, int* best_split, float* best_ms, void* stream) {
+  gbm3d_params p = resolve(params);
   if (!ctx) return fail(nullptr, GBM3D_EINVAL, "ctx is NULL");
   if (!img) return fail(ctx, GBM3D_EINVAL, "NULL image pointer");
   if (reps < 1) return fail(ctx, GBM3D_EINVAL, "reps %d must be >= 1", reps);
   CHECK(check_shape(ctx, H, W, p));
   CHECK(check_k(ctx, K, p, "K"));
+  const bool tune_shape = K == p.k_ht && K <= 16;
+  if (tune_shape) CHECK(check_ht(ctx, p));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -805,24 +842,51 @@ int gbm3d_autotune(gbm3d_ctx* ctx, const uint16_t* img, int H, int W, int K, int
     ~TimingOff() { c->timing = was; }
   } off{ctx, ctx->timing};
   ctx->timing = false;
+  // milliseconds per run of f, after one warm-up run (which also sizes the workspace)
+  auto time_runs = [&](auto&& f, float& ms) -> int {
+    CHECK(f());
+    HIP_TRY(ctx, hipEventRecord(ev.a, st), "hipEventRecord");
+    for (int i = 0; i < reps; ++i) CHECK(f());
+    HIP_TRY(ctx, hipEventRecord(ev.b, st), "hipEventRecord");
+    HIP_TRY(ctx, hipEventSynchronize(ev.b), "hipEventSynchronize");
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+    ms /= static_cast<float>(reps);
+    return GBM3D_OK;
+  };
   TuneEntry best;
   best.ms = INFINITY;
   const int R = p.search / 2;
   for (int method : {GBM3D_BM_SHIFT, GBM3D_BM_CORR}) {
     for (int split : {1, 2, 4}) {
       const BmChoice c{method, split};
-      CHECK(run_match(ctx, r, R, K, c, 0, st));  // warm-up (and workspace)
-      HIP_TRY(ctx, hipEventRecord(ev.a, st), "hipEventRecord");
-      for (int i = 0; i < reps; ++i) CHECK(run_match(ctx, r, R, K, c, 0, st));
-      HIP_TRY(ctx, hipEventRecord(ev.b, st), "hipEventRecord");
-      HIP_TRY(ctx, hipEventSynchronize(ev.b), "hipEventSynchronize");
       float ms = 0.0f;
-      HIP_TRY(ctx, hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
-      ms /= static_cast<float>(reps);
+      CHECK(time_runs([&] { return run_match(ctx, r, R, K, c, 0, st); }, ms));
       if (ms < best.ms) best = TuneEntry{method, split, ms};
     }
   }
-  ctx->tuned[{K, tile_class(gbm3d::corr_tiles(H, W))}] = best;
+  const int cls = tile_class(gbm3d::corr_tiles(H, W));
+  ctx->tuned[{K, p.search, cls}] = best;
+  if (tune_shape) {
+    // the stage-1 group kernel's shape: whole stage-1 runs (matching as just
+    // tuned) at a nominal noise level, one per shape
+    CHECK(ensure(ctx, ctx->basic, static_cast<size_t>(H) * W * sizeof(float), "basic"));
+    gbm3d_params q = p;
+    q.bm_method = best.method;
+    q.bm_split = best.split;
+    ShapeEntry sbest;
+    sbest.ms = INFINITY;
+    for (int shape : {0, 1}) {
+      ctx->tuned_shape[{K, p.search, cls}] = ShapeEntry{shape, 0.0f};
+      float ms = 0.0f;
+      CHECK(time_runs(
+          [&] {
+            return run_basic(ctx, img, H, W, 25.0f / 255.0f, q, static_cast<float*>(ctx->basic.p), nullptr, st);
+          },
+          ms));
+      if (ms < sbest.ms) sbest = ShapeEntry{shape, ms};
+    }
+    ctx->tuned_shape[{K, p.search, cls}] = sbest;
+  }
   if (best_method) *best_method = best.method;
   if (best_split) *best_split = best.split;
   if (best_ms) *best_ms = best.ms;
@@ -836,7 +900,10 @@ int gbm3d_tune_save(const gbm3d_ctx* ctx, const char* path) {
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(c, GBM3D_EINVAL, "cannot write %s", path);
   for (const auto& kv : ctx->tuned)
-    std::fprintf(f, "%d %d %d %d %.6f\n", kv.first.first, kv.first.second, kv.second.method, kv.second.split,
+    std::fprintf(f, "bm %d %d %d %d %d %.6f\n", kv.first.K, kv.first.search, kv.first.cls, kv.second.method,
+                 kv.second.split, static_cast<double>(kv.second.ms));
+  for (const auto& kv : ctx->tuned_shape)
+    std::fprintf(f, "ht %d %d %d %d %.6f\n", kv.first.K, kv.first.search, kv.first.cls, kv.second.shape,
                  static_cast<double>(kv.second.ms));
   const bool ok = std::fclose(f) == 0;
   return ok ? GBM3D_OK : fail(c, GBM3D_EINVAL, "cannot write %s", path);
@@ -847,23 +914,36 @@ int gbm3d_tune_load(gbm3d_ctx* ctx, const char* path) {
   if (!path) return fail(ctx, GBM3D_EINVAL, "NULL path");
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(ctx, GBM3D_EINVAL, "cannot read %s", path);
-  std::vector<std::pair<std::pair<int, int>, TuneEntry>> rows;
-  int K, cls, method, split, line = 0;
-  double ms;
-  int got;
-  while ((got = std::fscanf(f, "%d %d %d %d %lf", &K, &cls, &method, &split, &ms)) == 5) {
-    ++line;
-    if (!is_pow2_group(K) || cls < 0 || cls > 62 || (method != GBM3D_BM_SHIFT && method != GBM3D_BM_CORR) ||
-        (split != 1 && split != 2 && split != 4) || !(ms >= 0.0)) {
-      std::fclose(f);
-      return fail(ctx, GBM3D_EINVAL, "%s: entry %d out of range", path, line);
+  std::vector<std::pair<TuneKey, TuneEntry>> rows;
+  std::vector<std::pair<TuneKey, ShapeEntry>> shapes;
+  char line[256];
+  int n = 0;
+  bool bad = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    ++n;
+    char tag[8] = {0};
+    int K = 0, search = 0, cls = 0, a = 0, b = 0;
+    double ms = 0.0;
+    if (std::sscanf(line, " %7s", tag) != 1) continue;  // blank line
+    if (std::strcmp(tag, "bm") == 0 &&
+        std::sscanf(line, " bm %d %d %d %d %d %lf", &K, &search, &cls, &a, &b, &ms) == 6 && is_pow2_group(K) &&
+        search >= 1 && search <= 39 && (search & 1) && cls >= 0 && cls <= 62 &&
+        (a == GBM3D_BM_SHIFT || a == GBM3D_BM_CORR) && (b == 1 || b == 2 || b == 4) && ms >= 0.0) {
+      rows.push_back({{K, search, cls}, TuneEntry{a, b, static_cast<float>(ms)}});
+    } else if (std::strcmp(tag, "ht") == 0 &&
+               std::sscanf(line, " ht %d %d %d %d %lf", &K, &search, &cls, &a, &ms) == 5 && is_pow2_group(K) &&
+               search >= 1 && search <= 39 && (search & 1) && cls >= 0 && cls <= 62 && (a == 0 || a == 1) &&
+               ms >= 0.0) {
+      shapes.push_back({{K, search, cls}, ShapeEntry{a, static_cast<float>(ms)}});
+    } else {
+      bad = true;
+      break;
     }
-    rows.push_back({{K, cls}, TuneEntry{method, split, static_cast<float>(ms)}});
   }
-  const bool at_end = got == EOF && std::feof(f);
   std::fclose(f);
-  if (!at_end) return fail(ctx, GBM3D_EINVAL, "%s: cannot parse entry %d", path, line + 1);
+  if (bad) return fail(ctx, GBM3D_EINVAL, "%s: cannot parse entry %d", path, n);
   for (const auto& r : rows) ctx->tuned[r.first] = r.second;
+  for (const auto& r : shapes) ctx->tuned_shape[r.first] = r.second;
   return GBM3D_OK;
 }
 

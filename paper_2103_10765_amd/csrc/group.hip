@@ -51,8 +51,9 @@ struct Foot {
   static constexpr int entries = FYmax * FXPmax;
 };
 
-// Launch shape of a group kernel.  The hard-threshold kernel on one image
-// (K <= 16) runs two tiles per CU: 12 waves each (six per SIMD), inverse
+// Launch shape of a group kernel.  The hard-threshold kernel (K <= 16; the
+// WIDE shape, which the autotuner may swap for the one-tile shape below) runs
+// two tiles per CU: 12 waves each (six per SIMD), inverse
 // transforms 8 blocks at a time through each wave's scratch, no prefetch of
 // the next group (the other waves hide the loads).  Otherwise one tile per
 // CU: sixteen waves (four per SIMD) where a 16-block scratch per wave fits
@@ -61,9 +62,9 @@ struct Foot {
 // spectra in flight.  The hard-threshold filter holds all K inverse blocks
 // until its weight is known, which does not fit sixteen waves for K = 32;
 // the batched variant carries more state per wave and keeps one tile per CU.
-template <int K, bool HT, bool BATCH>
+template <int K, bool HT, bool BATCH, bool WIDE = true>
 struct GroupCfg {
-  static constexpr bool two_tiles = HT && K <= 16;
+  static constexpr bool two_tiles = HT && K <= 16 && WIDE;
   static constexpr int chunk = two_tiles ? (K > 8 ? 8 : K) : (K > 16 ? 16 : K);
   static constexpr int waves =
       two_tiles ? 12
@@ -338,8 +339,9 @@ __device__ __forceinline__ void for_each_group(const GroupWalk<WAVES>& walk, con
 // One work item = one tile of references: stage-1 groups.  RECOMPUTE: the
 // blocks' spectra are computed here from the image's pixels instead of
 // gathered from the bior1.5 stack.
-template <int K, bool BATCH, bool RECOMPUTE>
-__device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[GroupCfg<K, true, BATCH>::chunk * kBlockFloats],
+template <int K, bool BATCH, bool RECOMPUTE, bool WIDE>
+__device__ __forceinline__ void group_ht_body(acc_t* acc,
+                                              float (*scratch)[GroupCfg<K, true, BATCH, WIDE>::chunk * kBlockFloats],
                                               const ImgRec& r, int R, const HtParams& hp, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
   const int tyi = item / g.nTx, txi = item % g.nTx;
@@ -355,7 +357,7 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc, float (*scratch)[Group
   const bool dc_lane = hp.keep_dc && lane == 0;
   acc_t* bw = r.partials;  // block-start weights
 
-  using Cfg = GroupCfg<K, true, BATCH>;
+  using Cfg = GroupCfg<K, true, BATCH, WIDE>;
   const GroupWalk<Cfg::waves> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
   const float* const stacks[1] = {r.stack_a};
   auto filter = [&](const float (&cur)[1][K], int fo_v, int pos_v) {
@@ -502,16 +504,17 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc,
 }
 
 // (the second launch bound is the minimum number of waves per SIMD)
-template <int K, bool BATCH, bool RECOMPUTE>
-__global__ __launch_bounds__((GroupCfg<K, true, BATCH>::threads),
-                             (GroupCfg<K, true, BATCH>::min_waves_per_simd)) void group_ht_kernel(ImgRec one,
-                                                                                                   WorkList wl, int R,
-                                                                                                   HtParams hp) {
-  using Cfg = GroupCfg<K, true, BATCH>;
+template <int K, bool BATCH, bool RECOMPUTE, bool WIDE>
+__global__ __launch_bounds__((GroupCfg<K, true, BATCH, WIDE>::threads),
+                             (GroupCfg<K, true, BATCH, WIDE>::min_waves_per_simd)) void group_ht_kernel(ImgRec one,
+                                                                                                         WorkList wl,
+                                                                                                         int R,
+                                                                                                         HtParams hp) {
+  using Cfg = GroupCfg<K, true, BATCH, WIDE>;
   __shared__ acc_t acc[Foot::entries];
   __shared__ float scratch[Cfg::waves][Cfg::chunk * kBlockFloats];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    group_ht_body<K, BATCH, RECOMPUTE>(acc, scratch, r, R, hp, item);
+    group_ht_body<K, BATCH, RECOMPUTE, WIDE>(acc, scratch, r, R, hp, item);
   });
 }
 
@@ -671,34 +674,44 @@ int group_items_for(int H, int W, int R) {
 
 int reduce_items_for(int H, int W) { return reduce_items(H, W); }
 
-template <int K>
-static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int recompute,
-                              int grid_cap, hipStream_t st) {
+template <int K, bool WIDE>
+static hipError_t launch_ht_shape(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int recompute,
+                                  int grid_cap, hipStream_t st) {
+  using Cfg = GroupCfg<K, true, false, WIDE>;
   if (!wl) {
     if (recompute)
-      hipLaunchKernelGGL((group_ht_kernel<K, false, true>), dim3(group_items_for(one.H, one.W, R)),
-                         dim3(GroupCfg<K, true, false>::threads), 0, st, one, WorkList{}, R, hp);
+      hipLaunchKernelGGL((group_ht_kernel<K, false, true, WIDE>), dim3(group_items_for(one.H, one.W, R)),
+                         dim3(Cfg::threads), 0, st, one, WorkList{}, R, hp);
     else
-      hipLaunchKernelGGL((group_ht_kernel<K, false, false>), dim3(group_items_for(one.H, one.W, R)),
-                         dim3(GroupCfg<K, true, false>::threads), 0, st, one, WorkList{}, R, hp);
+      hipLaunchKernelGGL((group_ht_kernel<K, false, false, WIDE>), dim3(group_items_for(one.H, one.W, R)),
+                         dim3(Cfg::threads), 0, st, one, WorkList{}, R, hp);
   } else {
     if (recompute) return hipErrorInvalidValue;  // batches read the stack
     if (wl->total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((group_ht_kernel<K, true, false>), dim3(std::min(wl->total, grid_cap)),
-                       dim3(GroupCfg<K, true, true>::threads), 0, st, one, *wl, R, hp);
+    hipLaunchKernelGGL((group_ht_kernel<K, true, false, WIDE>), dim3(std::min(wl->total, grid_cap)),
+                       dim3(GroupCfg<K, true, true, WIDE>::threads), 0, st, one, *wl, R, hp);
   }
   return hipGetLastError();
 }
 
+template <int K>
+static hipError_t launch_ht_k(const ImgRec& one, const WorkList* wl, int R, const HtParams& hp, int recompute,
+                              int shape, int grid_cap, hipStream_t st) {
+  if (K <= 16 && shape == 1) return launch_ht_shape<K, false>(one, wl, R, hp, recompute, grid_cap, st);
+  return launch_ht_shape<K, true>(one, wl, R, hp, recompute, grid_cap, st);
+}
+
+int group_ht_tiles_per_cu(int K, int shape) { return K <= 16 && shape == 0 ? 2 : 1; }
+
 hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, float ht_a, float ht_b,
-                           int weight_mode, int keep_dc, int recompute, int grid_cap, hipStream_t st) {
+                           int weight_mode, int keep_dc, int recompute, int shape, int grid_cap, hipStream_t st) {
   const HtParams hp{ht_a, ht_b, weight_mode, keep_dc};
   switch (K) {
-    case 2: return launch_ht_k<2>(one, wl, R, hp, recompute, grid_cap, st);
-    case 4: return launch_ht_k<4>(one, wl, R, hp, recompute, grid_cap, st);
-    case 8: return launch_ht_k<8>(one, wl, R, hp, recompute, grid_cap, st);
-    case 16: return launch_ht_k<16>(one, wl, R, hp, recompute, grid_cap, st);
-    case 32: return launch_ht_k<32>(one, wl, R, hp, recompute, grid_cap, st);
+    case 2: return launch_ht_k<2>(one, wl, R, hp, recompute, shape, grid_cap, st);
+    case 4: return launch_ht_k<4>(one, wl, R, hp, recompute, shape, grid_cap, st);
+    case 8: return launch_ht_k<8>(one, wl, R, hp, recompute, shape, grid_cap, st);
+    case 16: return launch_ht_k<16>(one, wl, R, hp, recompute, shape, grid_cap, st);
+    case 32: return launch_ht_k<32>(one, wl, R, hp, recompute, shape, grid_cap, st);
     default: return hipErrorInvalidValue;
   }
 }

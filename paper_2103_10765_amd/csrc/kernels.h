@@ -52,9 +52,13 @@ int group_items_for(int H, int W, int R);
 
 // stage-1 groups: stack_a (bior) + idx -> partials (weights scaled by rec.eps);
 // recompute (one image only): the blocks' spectra from rec.noisy's pixels
-// instead of stack_a
+// instead of stack_a.  shape (K <= 16): 0 = two tiles of 12 waves per CU,
+// 1 = one tile of 16 waves with the next group's spectra prefetched; the
+// same result either way.  group_ht_tiles_per_cu: the persistent-grid
+// multiplier of a shape.
 hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, float ht_a, float ht_b,
-                           int weight_mode, int keep_dc, int recompute, int grid_cap, hipStream_t st);
+                           int weight_mode, int keep_dc, int recompute, int shape, int grid_cap, hipStream_t st);
+int group_ht_tiles_per_cu(int K, int shape);
 // zeroes the block-start weights of rec.partials (what the bior1.5 stack
 // launch does when the stage-1 groups read the stack)
 hipError_t launch_clear_weights(const ImgRec& one, hipStream_t st);

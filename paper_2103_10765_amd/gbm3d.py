@@ -108,7 +108,7 @@ _SIGNATURES = {
     "gbm3d_timing_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)]),
     "gbm3d_timing_reset": (_I, [_P]),
-    "gbm3d_autotune": (_I, [_P, _P, _I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+    "gbm3d_autotune": (_I, [_P, _P, _I, _I, _I, ctypes.POINTER(Params), _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                             ctypes.POINTER(_F), _P]),
     "gbm3d_tune_save": (_I, [_P, ctypes.c_char_p]),
     "gbm3d_tune_load": (_I, [_P, ctypes.c_char_p]),
@@ -413,12 +413,14 @@ class Context:
         self._check(lib().gbm3d_timing_read(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
-    def autotune(self, img: torch.Tensor, K: int, reps: int = 3, stream=None):
-        """Times every block-matching variant on img and records the fastest
-        for its shape class; returns (method, split, ms per run)."""
+    def autotune(self, img: torch.Tensor, K: int, reps: int = 3, params: Params | None = None, stream=None):
+        """Times every block-matching variant on img (and, for K == k_ht <= 16,
+        both stage-1 group-kernel shapes) and records the fastest for its
+        (K, search, shape class); returns (method, split, ms per matching run)."""
         H, W = _hw(img)
         m, sp, ms = _I(), _I(), _F()
-        self._check(lib().gbm3d_autotune(self._h, _dev(img, torch.uint16, "img"), H, W, K, reps,
+        self._check(lib().gbm3d_autotune(self._h, _dev(img, torch.uint16, "img"), H, W, K,
+                                         ctypes.byref(params) if params is not None else None, reps,
                                          ctypes.byref(m), ctypes.byref(sp), ctypes.byref(ms), _stream(stream)))
         return m.value, sp.value, ms.value
 

@@ -92,7 +92,7 @@ def test_null_context_is_rejected(G):
     assert L.gbm3d_basic(None, None, 64, 64, 0.1, None, None, None) == G.EINVAL
     assert L.gbm3d_denoise(None, None, 64, 64, 0.1, None, None, None, None, None) == G.EINVAL
     assert "ctx" in G.last_thread_error()
-    assert L.gbm3d_autotune(None, None, 64, 64, 16, 1, None, None, None, None) == G.EINVAL
+    assert L.gbm3d_autotune(None, None, 64, 64, 16, None, 1, None, None, None, None) == G.EINVAL
     assert L.gbm3d_tune_load(None, b"/nonexistent") == G.EINVAL
     assert L.gbm3d_tune_save(None, b"/nonexistent") == G.EINVAL
 

@@ -423,27 +423,47 @@ def test_methods_give_identical_denoising(torch, G, ctx):
 
 
 def test_autotune_records_and_reloads(torch, G, ctx, tmp_path):
-    """The autotuner times every variant, its choice is then used for auto
-    params (same indices), and the choices survive a save / load."""
+    """The autotuner times every matching variant (and, for K = k_ht, both
+    stage-1 group-kernel shapes), keyed by (K, search, shape class); its
+    choices are then used for auto params (same indices, same estimate), and
+    survive a save / load."""
     say("autotune")
     _, Z = synth.make_case(150, 160, SIG, 19)
     Zt = up(torch, Z)
     m, sp, ms = ctx.autotune(Zt, 16, reps=2)
     assert m in (1, 2) and sp in (1, 2, 4) and ms > 0
+    p21 = G.default_params(search=21)
+    m21, sp21, _ = ctx.autotune(Zt, 16, reps=2, params=p21)
     exp = O.match(Z, 16, O.DEFAULT)
     assert np.array_equal(ctx.match(Zt, 16).cpu().numpy().astype(np.int64), exp)
+    assert np.array_equal(ctx.match(Zt, 16, p21).cpu().numpy().astype(np.int64),
+                          O.match(Z, 16, O.DEFAULT.with_(search=21)))
     path = str(tmp_path / "tune.txt")
     ctx.tune_save(path)
-    line = open(path).read().split()
-    assert [int(x) for x in line[:4]][2:] == [m, sp]
+    rows = [ln.split() for ln in open(path).read().splitlines()]
+    bm = {int(r[2]): r for r in rows if r[0] == "bm"}
+    ht = {int(r[2]): r for r in rows if r[0] == "ht"}
+    assert [int(x) for x in bm[39][4:6]] == [m, sp] and [int(x) for x in bm[21][4:6]] == [m21, sp21]
+    assert set(ht) == {21, 39} and all(int(r[4]) in (0, 1) for r in ht.values())
+    cls = int(ht[39][3])
     c2 = G.Context(0)
     try:
         c2.tune_load(path)
         assert np.array_equal(c2.match(Zt, 16).cpu().numpy().astype(np.int64), exp)
+        # both stage-1 shapes give the same estimate, bit for bit
+        outs = []
+        for shape in (0, 1):
+            f = tmp_path / f"shape{shape}.txt"
+            f.write_text(f"ht 16 39 {cls} {shape} 0.1\n")
+            c2.tune_load(str(f))
+            outs.append(c2.basic(Zt, SIG).cpu().numpy())
+        assert np.array_equal(outs[0], outs[1])
         bad = tmp_path / "bad.txt"
-        bad.write_text("16 5 9 1 0.1\n")
+        bad.write_text("bm 16 39 5 9 1 0.1\n")
         with pytest.raises(G.GBM3DError):
             c2.tune_load(str(bad))
+        with pytest.raises(G.GBM3DError):
+            ctx.autotune(Zt, 16, reps=0)
     finally:
         c2.close()
 
