@@ -30,7 +30,14 @@ FLAGS = [
 # The matching kernels hold only finite keys or +inf in their min/max
 # networks: with NaNs ruled out, v_min_f64 / v_max_f64 need no NaN-quieting
 # operand canonicalisation.
-EXTRA = {"bm.hip": ["-fno-honor-nans"], "bm_corr.hip": ["-fno-honor-nans"]}
+# The learned pilot's fused inference keeps its products' accumulators in
+# ordinary VGPRs (the epilogue reads them without copies out of AGPRs); its
+# values are finite throughout.
+EXTRA = {
+    "bm.hip": ["-fno-honor-nans"],
+    "bm_corr.hip": ["-fno-honor-nans"],
+    "pilot.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
 
 
 def _compile(src: str) -> str:

@@ -1316,13 +1316,14 @@ int check_pilot_shape(gbm3d_ctx* ctx, int B, int H, int W) {
   return GBM3D_OK;
 }
 
-// forward pass; keep_all: acts[l] of every layer input kept (training)
-int pilot_forward(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W, const float* sigma, bool keep_all,
+// training forward pass, one launch per layer: the input of every layer is
+// kept in HBM for the backward pass
+int pilot_forward(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W, const float* sigma,
                   uint16_t* pilot_u16, float* pilot_f32, hipStream_t st) {
   const size_t ab = act_bytes(B, H, W);
   const PilotWeights pw = pilot_weights(ctx);
   char* act = static_cast<char*>(ctx->pilot_act.p);
-  auto buf = [&](int l) { return reinterpret_cast<uint16_t*>(act + (keep_all ? l : (l & 1)) * ab); };
+  auto buf = [&](int l) { return reinterpret_cast<uint16_t*>(act + l * ab); };
   const int cap = 4 * ctx->n_cu;
   HIP_TRY(ctx, timed(ctx, "pilot_prep", st, [&] { return gbm3d::launch_pilot_prep(noisy, sigma, B, H, W, buf(0), st); }),
           "pilot input");
@@ -1364,8 +1365,14 @@ int gbm3d_pilot_infer(gbm3d_ctx* ctx, const uint16_t* noisy, int B, int H, int W
   CHECK(check_pilot_shape(ctx, B, H, W));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, GBM3D_EHIP, "hipSetDevice(%d) failed", ctx->device);
-  CHECK(ensure(ctx, ctx->pilot_act, 2 * act_bytes(B, H, W), "pilot activations"));
-  return pilot_forward(ctx, noisy, B, H, W, sigma, false, pilot_u16, pilot_f32, static_cast<hipStream_t>(stream));
+  const PilotWeights pw = pilot_weights(ctx);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, timed(ctx, "pilot_fused", st, [&] {
+            return gbm3d::launch_pilot_infer_fused(noisy, sigma, pw.wf, pw.bias, B, H, W, pilot_f32, pilot_u16,
+                                                   ctx->n_cu, st);
+          }),
+          "pilot inference");
+  return GBM3D_OK;
 }
 
 int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target, int B, int H, int W,
@@ -1393,7 +1400,7 @@ int gbm3d_pilot_grad(gbm3d_ctx* ctx, const uint16_t* noisy, const float* target,
   float* wpart = static_cast<float*>(ctx->pilot_part.p);
   double* lpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->pilot_part.p) +
                                             gbm3d::pilot_wgrad_partial_floats(wg_grid) * sizeof(float));
-  CHECK(pilot_forward(ctx, noisy, B, H, W, sigma, true, nullptr, pil, st));
+  CHECK(pilot_forward(ctx, noisy, B, H, W, sigma, nullptr, pil, st));
   HIP_TRY(ctx, timed(ctx, "pilot_loss", st, [&] {
             return gbm3d::launch_pilot_loss(pil, target, weight, static_cast<size_t>(H) * W, npix, gbuf[0], lpart,
                                             loss_blocks, loss, st);

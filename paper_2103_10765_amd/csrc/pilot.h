@@ -33,6 +33,12 @@ hipError_t launch_pilot_prep(const uint16_t* noisy, const float* sigma, int N, i
 hipError_t launch_pilot_conv(int mode, const uint16_t* in, const uint16_t* w, const float* bias, const uint16_t* mask,
                              uint16_t* out, const uint16_t* noisy, float* pilot_f32, uint16_t* pilot_u16, int N,
                              int H, int W, int grid_cap, hipStream_t st);
+// inference of all six layers in one launch (one 16 x 32 output tile per
+// workgroup at a time, activations in LDS); grid_cap bounds the persistent grid
+int pilot_fused_tiles(int N, int H, int W);
+hipError_t launch_pilot_infer_fused(const uint16_t* noisy, const float* sigma, const uint16_t* wf, const float* bias,
+                                    int N, int H, int W, float* pilot_f32, uint16_t* pilot_u16, int grid_cap,
+                                    hipStream_t st);
 // loss = sum_p weight[p / hw] (pilot - target)^2 / n (weight NULL: 1), and dL/df
 hipError_t launch_pilot_loss(const float* pilot, const float* target, const float* weight, size_t hw, size_t n,
                              uint16_t* g, double* part, int n_part, float* loss, hipStream_t st);

@@ -155,6 +155,350 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// fused inference: the six layers of one 16 x 32 output tile in one
+// workgroup, every intermediate activation in LDS.  Layer l is evaluated on
+// the tile grown by 5 - l pixels on each side (the receptive field of the
+// layers after it), so a tile reads only its 28 x 44 window of the noisy
+// image and writes only its pilot pixels.  Positions outside the image are
+// zero in every layer's output, as the zero "same" padding of the per-layer
+// form has them.
+//
+// One wave per SIMD, each software-pipelining its pixel blocks (the operands
+// of the next block are read from LDS and the previous block's results
+// written while the current block's products run); the next layer's weights
+// are loaded into registers while the current layer computes.
+//
+// LDS: the input window as (z, sigma) bf16 pairs, and two ping-pong
+// activation buffers (layers 0, 2, 4 | 1, 3) of 64 B per pixel.  A pixel's
+// 16-byte octet o holds channels 4o .. 4o+3 and 16+4o .. 16+4o+3: exactly
+// the eight values one lane holds after the products (output rows 4 grp + i
+// of both 16-channel halves), so a lane writes its pixel's results with one
+// 16-byte store, and the next layer takes its K dimension in that order (its
+// A operands are gathered to match).  Octet o of a pixel in region column x
+// sits at slot o ^ ((x >> 1) & 3): the eight consecutive pixels that one
+// 128-byte LDS cycle of a 16-byte access serves then hit eight different
+// 16-byte bank groups.  A layer's output pixels are taken in raster order,
+// 16 per MFMA column block; layer 0 packs its 9 taps x 2 input channels into
+// one K = 32 product, and layer 5 computes one 16-channel half (its single
+// output channel is row 0).  Bias enters as the initial accumulator.  Lanes
+// of a region's last block that fall past its end store into a spare pixel
+// at the end of the buffer, so the stores need no branch.
+// ---------------------------------------------------------------------------
+constexpr int kFY = 16, kFX = 32;                   // output tile
+constexpr int kFWaves = 4, kFThreads = 64 * kFWaves;
+constexpr int kZY = kFY + 2 * kPilotLayers, kZX = kFX + 2 * kPilotLayers;  // input window
+__host__ __device__ constexpr int f_ry(int l) { return kFY + 2 * (kPilotLayers - 1 - l); }
+__host__ __device__ constexpr int f_rx(int l) { return kFX + 2 * (kPilotLayers - 1 - l); }
+constexpr int kFBufA = f_ry(0) * f_rx(0), kFBufB = f_ry(1) * f_rx(1);  // pixels
+static_assert(kFBufA >= f_ry(2) * f_rx(2) && kFBufB >= f_ry(3) * f_rx(3), "ping-pong sizes");
+static_assert(kFX % 16 == 0, "output rows are whole 16-pixel blocks");
+
+__host__ __device__ inline int fused_tiles(int N, int H, int W) {
+  return N * ((H + kFY - 1) / kFY) * ((W + kFX - 1) / kFX);
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));  // round to nearest even
+}
+
+// A operands of one layer (HALVES = 1: the first 16 output channels only)
+template <int HALVES>
+struct FusedW {
+  bf16x8 A[kTaps][HALVES];
+};
+
+template <int HALVES>
+__device__ __forceinline__ void fused_load_w(const uint16_t* __restrict__ wf, int l, int col, int grp,
+                                             FusedW<HALVES>& w) {
+  // global address space, and opaque to the optimiser, so the loads stay
+  // where they are issued instead of being hoisted out of the tile loop (the
+  // weights of all layers at once do not fit in the registers)
+  typedef const uint16_t __attribute__((address_space(1))) * gptr;
+  gptr wl = (gptr)(wf + static_cast<size_t>(l) * kWmat);
+  asm volatile("" : "+s"(wl));
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+    for (int h = 0; h < HALVES; ++h) {
+      // K element 8 grp + e is input channel 4 grp + e (e < 4) or 16 + 4 grp + e - 4
+      gptr row = wl + (t * kC + h * 16 + col) * kC;
+      typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+      typedef const u32x2 __attribute__((address_space(1))) * gptr2;
+      const u32x2 lo = *(gptr2)(row + 4 * grp);
+      const u32x2 hi = *(gptr2)(row + 16 + 4 * grp);
+      w.A[t][h] = as_bf16x8(make_uint4(lo.x, lo.y, hi.x, hi.y));
+    }
+}
+
+// ReLU (all zero when keep is false: outside the image), bf16, into octet
+// grp of pixel i (region column c).  The ReLU acts on the rounded bf16 pairs
+// as signed 16-bit maxima: rounding keeps the sign, so this equals rounding
+// the ReLU of the float sums.
+__device__ __forceinline__ void fused_store(uint4* __restrict__ out, int i, int c, int grp, f32x4 a0, f32x4 a1,
+                                            bool keep) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  const s16x2 zero = {0, 0};
+  uint32_t q[4] = {pack_bf16(a0[0], a0[1]), pack_bf16(a0[2], a0[3]), pack_bf16(a1[0], a1[1]), pack_bf16(a1[2], a1[3])};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    q[k] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, q[k]), zero));
+    q[k] = keep ? q[k] : 0u;
+  }
+  out[i * 4 + (grp ^ ((c >> 1) & 3))] = make_uint4(q[0], q[1], q[2], q[3]);
+}
+
+struct Taps9 {
+  bf16x8 v[kTaps];
+};
+
+// A 3x3 layer over the NG pixel blocks g = wave, wave + kFWaves, ... of its
+// region (row width RX, input row stride RX + 2): after the products of tap
+// t of block g are issued, tap t of block g + kFWaves is read into the same
+// registers, and the results of block g are stored while the products of
+// the next block run.
+template <int RX, int NP, int HALVES, class Store>
+__device__ __forceinline__ void fused_conv(const uint4* __restrict__ in, const FusedW<HALVES>& w, f32x4 b0, f32x4 b1,
+                                           Store&& store) {
+  constexpr int S = RX + 2, NG = (NP + 15) / 16;
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  int g = threadIdx.x >> 6;
+  if (g >= NG) return;
+  auto addr = [&](int gg, int (&e)[3]) {
+    const int i = min(gg * 16 + col, NP - 1), r = i / RX, c = i - r * RX, pb = r * S + c;
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) e[kx] = (pb + kx) * 4 + (grp ^ (((c + kx) >> 1) & 3));
+  };
+  Taps9 B;
+  {
+    int e[3];
+    addr(g, e);
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) B.v[t] = as_bf16x8(in[e[t % 3] + (t / 3) * S * 4]);
+  }
+  f32x4 p0, p1;
+  {
+    int e[3];
+    addr(min(g + kFWaves, NG - 1), e);
+    p0 = b0;
+    p1 = b1;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      p0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.A[t][0], B.v[t], p0, 0, 0, 0);
+      if constexpr (HALVES == 2) p1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.A[t][HALVES - 1], B.v[t], p1, 0, 0, 0);
+      B.v[t] = as_bf16x8(in[e[t % 3] + (t / 3) * S * 4]);
+    }
+    g += kFWaves;
+  }
+  for (; g + kFWaves < NG; g += kFWaves) {
+    int e[3];
+    addr(g + kFWaves, e);
+    f32x4 a0 = b0, a1 = b1;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.A[t][0], B.v[t], a0, 0, 0, 0);
+      if constexpr (HALVES == 2) a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.A[t][HALVES - 1], B.v[t], a1, 0, 0, 0);
+      B.v[t] = as_bf16x8(in[e[t % 3] + (t / 3) * S * 4]);
+    }
+    store(g - kFWaves, p0, p1);
+    p0 = a0;
+    p1 = a1;
+  }
+  if (g < NG) {
+    f32x4 a0 = b0, a1 = b1;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.A[t][0], B.v[t], a0, 0, 0, 0);
+      if constexpr (HALVES == 2) a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.A[t][HALVES - 1], B.v[t], a1, 0, 0, 0);
+    }
+    store(g - kFWaves, p0, p1);
+    store(g, a0, a1);
+  } else {
+    store(g - kFWaves, p0, p1);
+  }
+}
+
+// layers 1 .. 4: 32 -> 32, ReLU
+template <int L, int DUMMY = (L & 1) ? kFBufB : kFBufA>
+__device__ __forceinline__ void fused_mid(const uint4* __restrict__ in, uint4* __restrict__ out,
+                                          const FusedW<2>& w, const f32x4* __restrict__ bias4, bool border, int y0,
+                                          int x0, int H, int W) {
+  constexpr int RX = f_rx(L), NP = f_ry(L) * RX, G = kPilotLayers - 1 - L;
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  fused_conv<RX, NP, 2>(in, w, bias4[L * 8 + grp], bias4[L * 8 + 4 + grp], [&](int g, f32x4 a0, f32x4 a1) {
+    const int iv = g * 16 + col, i = min(iv, NP - 1);
+    const int r = i / RX, c = i - r * RX;
+    bool keep = true;
+    if (border) {
+      const int y = y0 - G + r, x = x0 - G + c;
+      keep = static_cast<unsigned>(y) < static_cast<unsigned>(H) && static_cast<unsigned>(x) < static_cast<unsigned>(W);
+    }
+    fused_store(out, iv < NP ? i : DUMMY, c, grp, a0, a1, keep);
+  });
+}
+
+__global__ __launch_bounds__(kFThreads) void fused_infer_kernel(const uint16_t* __restrict__ noisy,
+                                                                const float* __restrict__ sigma,
+                                                                const uint16_t* __restrict__ wf,
+                                                                const float* __restrict__ bias, int N, int H, int W,
+                                                                float* __restrict__ pilot_f32,
+                                                                uint16_t* __restrict__ pilot_u16) {
+  __shared__ __align__(16) uint4 bufA[(kFBufA + 1) * 4];
+  __shared__ __align__(16) uint4 bufB[(kFBufB + 1) * 4];
+  __shared__ uint32_t zb[kZY * kZX];
+  __shared__ uint16_t zc[2][kFY * kFX];  // the tile's own noisy pixels (exact), current / next tile
+  __shared__ f32x4 bias4[kPilotLayers * 8];  // [layer][half * 4 + grp]: output channels 16 half + 4 grp + 0..3
+
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  const int tx_n = (W + kFX - 1) / kFX, ty_n = (H + kFY - 1) / kFY;
+  const int total = fused_tiles(N, H, W);
+
+  if (threadIdx.x < kPilotLayers * kC) {
+    const int l = threadIdx.x / kC, ch = threadIdx.x % kC;
+    bias4[l * 8 + ch / 4][ch % 4] = bias[l * kC + ch];
+  }
+  // layer 0 operands: K index 8 grp + e is tap (8 grp + e) / 2, input channel e % 2 (taps past 8 are zero)
+  FusedW<2> w0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int t = (8 * grp + e) >> 1, ci = e & 1;
+      w0.A[0][h][e] = t < kTaps ? __builtin_bit_cast(__bf16, wf[(t * kC + h * 16 + col) * kC + ci]) : __bf16(0.0f);
+    }
+  int zoff[4];  // window offset of the taps this lane's K octet holds (taps past 8: any finite entry)
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int t = 4 * grp + j;
+    zoff[j] = t < kTaps ? (t / 3) * kZX + t % 3 : 0;
+  }
+  // the next layer's operands are loaded while the current layer computes
+  FusedW<2> wa, wb;
+  FusedW<1> w5;
+
+  // the window of a tile: 28 x 44 (z, sigma) pairs, zero outside the image
+  constexpr int kZPer = (kZY * kZX + kFThreads - 1) / kFThreads;
+  uint32_t zr[kZPer];
+  uint16_t cr[kZPer];
+  auto fetch = [&](int item) {
+    const int n = item / (tx_n * ty_n), rem = item - n * tx_n * ty_n;
+    const int y0 = (rem / tx_n) * kFY - kPilotLayers, x0 = (rem % tx_n) * kFX - kPilotLayers;
+    const uint32_t s = f2bf(sigma[n]);
+    const uint16_t* src = noisy + static_cast<size_t>(n) * H * W;
+#pragma unroll
+    for (int k = 0; k < kZPer; ++k) {
+      const int pix = threadIdx.x + k * kFThreads;
+      const int r = pix / kZX, c = pix - r * kZX, y = y0 + r, x = x0 + c;
+      uint16_t v = 0;
+      const bool in = pix < kZY * kZX && y >= 0 && y < H && x >= 0 && x < W;
+      if (in) v = src[static_cast<size_t>(y) * W + x];
+      cr[k] = v;
+      zr[k] = in ? (static_cast<uint32_t>(f2bf(static_cast<float>(v) * (1.0f / 65535.0f))) | (s << 16)) : 0u;
+    }
+  };
+  auto park = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < kZPer; ++k) {
+      const int pix = threadIdx.x + k * kFThreads;
+      if (pix < kZY * kZX) {
+        zb[pix] = zr[k];
+        const int r = pix / kZX - kPilotLayers, c = pix % kZX - kPilotLayers;
+        if (r >= 0 && r < kFY && c >= 0 && c < kFX) zc[buf][r * kFX + c] = cr[k];
+      }
+    }
+  };
+
+  int buf = 0;
+  if (blockIdx.x < total) {
+    fetch(blockIdx.x);
+    park(0);
+  }
+  __syncthreads();
+  for (int item = blockIdx.x; item < total; item += gridDim.x, buf ^= 1) {
+    const int n = item / (tx_n * ty_n), rem = item - n * tx_n * ty_n;
+    const int y0 = (rem / tx_n) * kFY, x0 = (rem % tx_n) * kFX;
+    const bool border = y0 < kPilotLayers || x0 < kPilotLayers || y0 + kFY + kPilotLayers > H ||
+                        x0 + kFX + kPilotLayers > W;
+
+    fused_load_w(wf, 1, col, grp, wa);
+    {  // layer 0: 2 -> 32 from the window, im2col over the K dimension; four blocks per step
+      constexpr int RX = f_rx(0), NP = f_ry(0) * RX, NG = (NP + 15) / 16, G = kPilotLayers - 1;
+      constexpr int kSteps = (NG + 4 * kFWaves - 1) / (4 * kFWaves);
+      const f32x4 b0 = bias4[grp], b1 = bias4[4 + grp];
+      const int wave = threadIdx.x >> 6;
+      auto read = [&](int g) {
+        const int i = min(g * 16 + col, NP - 1), r = i / RX, pb = r * kZX + (i - r * RX);
+        return as_bf16x8(make_uint4(zb[pb + zoff[0]], zb[pb + zoff[1]], zb[pb + zoff[2]], zb[pb + zoff[3]]));
+      };
+      bf16x8 Bz[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bz[q] = read(wave + q * kFWaves);
+      for (int st = 0; st < kSteps; ++st) {
+        const int g0 = st * 4 * kFWaves + wave;
+        f32x4 a0[4], a1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a0[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0.A[0][0], Bz[q], b0, 0, 0, 0);
+          a1[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0.A[0][1], Bz[q], b1, 0, 0, 0);
+          if (st + 1 < kSteps) Bz[q] = read(g0 + (4 + q) * kFWaves);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = (g0 + q * kFWaves) * 16 + col;
+          if (i < NP) {
+            const int r = i / RX, c = i - r * RX;
+            bool keep = true;
+            if (border) {
+              const int y = y0 - G + r, x = x0 - G + c;
+              keep = static_cast<unsigned>(y) < static_cast<unsigned>(H) &&
+                     static_cast<unsigned>(x) < static_cast<unsigned>(W);
+            }
+            fused_store(bufA, i, c, grp, a0[q], a1[q], keep);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const int next = item + static_cast<int>(gridDim.x);
+    if (next < total) fetch(next);  // in flight during layers 1 .. 4
+    fused_load_w(wf, 2, col, grp, wb);
+    fused_mid<1>(bufA, bufB, wa, bias4, border, y0, x0, H, W);
+    __syncthreads();
+    fused_load_w(wf, 3, col, grp, wa);
+    fused_mid<2>(bufB, bufA, wb, bias4, border, y0, x0, H, W);
+    __syncthreads();
+    fused_load_w(wf, 4, col, grp, wb);
+    fused_mid<3>(bufA, bufB, wa, bias4, border, y0, x0, H, W);
+    __syncthreads();
+    fused_load_w(wf, 5, col, grp, w5);
+    fused_mid<4>(bufB, bufA, wb, bias4, border, y0, x0, H, W);
+    if (next < total) park(buf ^ 1);  // the window buffer is free since layer 0
+    __syncthreads();
+
+    {  // layer 5: 32 -> 1 (row 0 of the first half), pilot = z - f
+      constexpr int RX = f_rx(5), NP = f_ry(5) * RX;
+      const uint16_t* zcur = zc[buf];
+      fused_conv<RX, NP, 1>(bufA, w5, bias4[5 * 8 + grp], bias4[5 * 8 + grp], [&](int g, f32x4 a0, f32x4) {
+        const int i = g * 16 + col, r = i / RX, c = i - r * RX;
+        const int y = y0 + r, x = x0 + c;
+        if (grp == 0 && y < H && x < W) {
+          const size_t p = (static_cast<size_t>(n) * H + y) * W + x;
+          const float pil = static_cast<float>(zcur[i]) * (1.0f / 65535.0f) - a0[0];
+          if (pilot_f32) pilot_f32[p] = pil;
+          if (pilot_u16) {
+            const double d = static_cast<double>(fminf(fmaxf(pil, 0.0f), 1.0f));
+            pilot_u16[p] = static_cast<uint16_t>(floor(d * 65535.0 + 0.5));
+          }
+        }
+      });
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient: dW[t][ci][co] = sum_p x[p + off_t][ci] g[p][co], db[co] = sum_p g[p][co]
 // per-workgroup partials [grid][kWmat + kC]
 // ---------------------------------------------------------------------------
@@ -372,6 +716,17 @@ hipError_t launch_pilot_prep(const uint16_t* noisy, const float* sigma, int N, i
   const size_t total = static_cast<size_t>(N) * H * W;
   const unsigned blocks = static_cast<unsigned>(std::min<size_t>((total + 255) / 256, 16384));
   hipLaunchKernelGGL(prep_kernel, dim3(blocks), dim3(256), 0, st, noisy, sigma, N, H * W, x0);
+  return hipGetLastError();
+}
+
+int pilot_fused_tiles(int N, int H, int W) { return fused_tiles(N, H, W); }
+
+hipError_t launch_pilot_infer_fused(const uint16_t* noisy, const float* sigma, const uint16_t* wf, const float* bias,
+                                    int N, int H, int W, float* pilot_f32, uint16_t* pilot_u16, int grid_cap,
+                                    hipStream_t st) {
+  const int grid = std::max(1, std::min(fused_tiles(N, H, W), grid_cap));
+  hipLaunchKernelGGL(fused_infer_kernel, dim3(grid), dim3(kFThreads), 0, st, noisy, sigma, wf, bias, N, H, W,
+                     pilot_f32, pilot_u16);
   return hipGetLastError();
 }
 

@@ -82,6 +82,68 @@ def test_pilot_forward_parity(torch, G, ctx, shape):
     assert np.array_equal(pu.cpu().numpy(), q)
 
 
+@pytest.mark.parametrize("shape", [(2, 50, 100), (1, 64, 128), (1, 7, 5)])
+def test_pilot_fused_tiles_parity(torch, G, ctx, shape):
+    """Several 16 x 32 inference tiles, interior ones (no image border within
+    the receptive field) and ragged right / bottom ones, and an image smaller
+    than one tile, against the oracle."""
+    B, H, W = shape
+    say("pilot fused tiles", shape)
+    theta = _theta(5)
+    ctx.pilot_load(torch.from_numpy(theta).cuda())
+    Z, sig = _batch(B, H, W, 50)
+    pu, pf = ctx.pilot_infer(torch.from_numpy(Z).cuda(), torch.from_numpy(sig).cuda(), f32=True)
+    ref, _ = P.forward(theta.astype(np.float64), Z / 65535.0, sig, bf16=True)
+    err = np.abs(pf.cpu().numpy() - ref)
+    say("max", err.max(), "median", np.median(err))
+    assert err.max() <= 1e-2, err.max()
+    assert np.median(err) <= 1e-3
+    q = np.floor(np.clip(pf.cpu().numpy().astype(np.float64), 0, 1) * 65535 + 0.5).astype(np.uint16)
+    assert np.array_equal(pu.cpu().numpy(), q)
+
+
+def test_pilot_full_size_windows(torch, G, ctx):
+    """The 2 x 512^2 batch in the benchmark's launch shape: windows at the
+    corners, on edges and across interior tile boundaries, each checked
+    against the oracle run on the window grown by the 6-pixel receptive
+    radius (clipped at the image, where the zero padding is the image's
+    own), on the pixels whose receptive field lies inside that crop."""
+    B, H, W, R = 2, 512, 512, 6
+    theta = _theta(6)
+    ctx.pilot_load(torch.from_numpy(theta).cuda())
+    Z, sig = _batch(B, H, W, 60)
+    _, pf = ctx.pilot_infer(torch.from_numpy(Z).cuda(), torch.from_numpy(sig).cuda(), f32=True)
+    pf = pf.cpu().numpy()
+    wins = [(0, 0), (0, 480), (488, 0), (488, 472), (250, 250), (14, 30), (200, 0), (0, 301), (95, 159)]
+    for b in range(B):
+        for (y, x) in wins:
+            y1, x1 = min(H, y + 24), min(W, x + 40)
+            cy0, cx0, cy1, cx1 = max(0, y - R), max(0, x - R), min(H, y1 + R), min(W, x1 + R)
+            ref, _ = P.forward(theta.astype(np.float64), Z[b:b + 1, cy0:cy1, cx0:cx1] / 65535.0, sig[b:b + 1],
+                               bf16=True)
+            got = pf[b, y:y1, x:x1]
+            want = ref[0, y - cy0:y1 - cy0, x - cx0:x1 - cx0]
+            err = np.abs(got - want)
+            assert err.max() <= 1e-2, (b, y, x, err.max())
+            assert np.median(err) <= 1e-3, (b, y, x)
+    say("windows ok")
+
+
+def test_pilot_fused_agrees_with_layerwise_forward(torch, G, ctx):
+    """The fused inference and the per-layer forward of the training path give
+    the same pilot up to accumulation order: the training loss against the
+    fused pilot as target is their mean squared difference."""
+    B, H, W = 2, 48, 96
+    theta = _theta(7)
+    ctx.pilot_load(torch.from_numpy(theta).cuda())
+    Z, sig = _batch(B, H, W, 80)
+    Zt, st = torch.from_numpy(Z).cuda(), torch.from_numpy(sig).cuda()
+    _, pf = ctx.pilot_infer(Zt, st, f32=True)
+    _, loss = ctx.pilot_grad(Zt, pf.contiguous(), st)
+    say("mean squared difference", loss.item())
+    assert loss.item() <= 1e-7
+
+
 @pytest.mark.parametrize("weight", [None, [0.25, 3.0]])
 def test_pilot_gradient_parity(torch, G, ctx, weight):
     B, H, W = 2, 16, 40
