@@ -592,6 +592,8 @@ def main():
                     help="only time the 64-image batch under graph replay (for profiling the batch path)")
     ap.add_argument("--global-only", action="store_true",
                     help="only time the volume form of stage 1 beside the grouped stage 1 (for profiling it)")
+    ap.add_argument("--pilot-only", action="store_true",
+                    help="only time the learned pilot's fused inference on 32 x 512^2 (for profiling it)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -600,6 +602,16 @@ def main():
         from paper_2103_10765_amd import gbm3d
         ctx = gbm3d.Context(0)
         print(json.dumps(batch_bench(ctx, reps=args.steps)), flush=True)
+        ctx.close()
+        return
+    if args.pilot_only:
+        import numpy as np
+        import torch
+        from paper_2103_10765_amd import gbm3d, pilot
+        ctx = gbm3d.Context(0)
+        with np.load(pilot.DEFAULT_WEIGHTS, allow_pickle=False) as f:
+            ctx.pilot_load(torch.from_numpy(f["master"]).cuda())
+        print(json.dumps(pilot_conv_rate(ctx)), flush=True)
         ctx.close()
         return
     if args.global_only:
