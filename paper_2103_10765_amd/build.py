@@ -37,6 +37,9 @@ EXTRA = {
     "bm.hip": ["-fno-honor-nans"],
     "bm_corr.hip": ["-fno-honor-nans"],
     "pilot.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    # the peak-rate probes' accumulator chains stay put in VGPRs instead of
+    # being shuffled between AGPRs every iteration
+    "microbench.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 
