@@ -554,6 +554,9 @@ def per_kernel(ctx, Zt, sigma, p, steps, variants=None):
         k["bound"] = bound
         k["work_per_launch"] = amount
         k["work_unit"] = unit
+        # `frac` is algorithmic work over time against the spec peak; what the
+        # HBM counters saw is `hbm_counted_frac` (null without a current summary)
+        k["work_basis"] = "algorithmic"
         k["achieved"] = amount / (k["avg_us"] * 1e-6) / scale
         k["peak"] = peak
         k["unit"] = punit
