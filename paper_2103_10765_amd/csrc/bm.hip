@@ -80,8 +80,10 @@ __host__ __device__ constexpr int bm_items(int H, int W) {
 
 // One work item: reference rows [RPW*pb, RPW*pb + RPW) x 62 reference columns.
 template <int K, int RPW, int SPLIT>
-__device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __restrict__ img,
-                                        int16_t* __restrict__ idx, int H, int W, int R, int item) {
+__device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __restrict__ img_,
+                                        int16_t* __restrict__ idx_, int H, int W, int R, int item) {
+  const auto img = to_global(img_);
+  const auto idx = to_global(idx_);
   static_assert(RPW * SPLIT == 4, "four waves per workgroup");
   using Smem = BmSmem<K, RPW, SPLIT>;
   constexpr int L = K - 1;
@@ -261,7 +263,7 @@ __device__ __forceinline__ void bm_body(unsigned char* smem, const uint16_t* __r
 
   const int q = q0 + lane;
   if (lane < kLanesOut && q < nRx && p < nRy) {
-    int16_t* out = idx + (static_cast<size_t>(p) * nRx + q) * K;
+    const auto out = idx + (static_cast<size_t>(p) * nRx + q) * K;
     out[0] = static_cast<int16_t>(r_center);
 #pragma unroll
     for (int i = 0; i < L; ++i) {

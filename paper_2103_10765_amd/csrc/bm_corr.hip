@@ -99,8 +99,10 @@ __host__ __device__ constexpr int norm_items(int H, int W) {
   return ((H + 2 * kNormPad + kNTy - 1) / kNTy) * ((W + 2 * kNormPad + kNTx - 1) / kNTx);
 }
 
-__device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img, double* __restrict__ norm, int H, int W,
+__device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img_, double* __restrict__ norm_, int H, int W,
                                           int R, int item, int* zt, double* hs) {
+  const auto img = to_global(img_);
+  const auto norm = to_global(norm_);
   const int He = H + 2 * kNormPad, We = norm_pitch(W);
   const int tiles_x = (We + kNTx - 1) / kNTx;
   const int ty0 = (item / tiles_x) * kNTy, tx0 = (item % tiles_x) * kNTx;
@@ -201,9 +203,12 @@ __device__ __forceinline__ void load_operand(const unsigned char* hp, const unsi
 
 // One work item: reference rows [4 pb, 4 pb + 4) x columns [4 TPW qb, 4 TPW (qb + 1)).
 template <int K, int TPW, int SPLIT>
-__device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* __restrict__ img,
-                                          const double* __restrict__ norm, int16_t* __restrict__ idx, int H, int W,
+__device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* __restrict__ img_,
+                                          const double* __restrict__ norm_, int16_t* __restrict__ idx_, int H, int W,
                                           int R, int item) {
+  const auto img = to_global(img_);
+  const auto norm = to_global(norm_);
+  const auto idx = to_global(idx_);
   static_assert(TPW * SPLIT == 4, "four waves per workgroup");
   using Smem = CorrSmem<K, TPW, SPLIT>;
   constexpr int L = K - 1;
@@ -269,7 +274,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       qt < nRx ? norm[static_cast<size_t>(kStep * (p0 + u) + kNormPad) * We + cr] - static_cast<double>((cr + R) & 3)
                : 0.0;
   // table entries of this lane's result candidates: block (br, bc) row g, columns 0..3
-  const double* ncand = norm + static_cast<size_t>(y0 + g + kNormPad) * We + (x0 + 12 * t + kNormPad);
+  const auto ncand = norm + static_cast<size_t>(y0 + g + kNormPad) * We + (x0 + 12 * t + kNormPad);
 
   double list[L];
 #pragma unroll
@@ -319,7 +324,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       if (j < nblk) {
         const int b = kOrder.b[nb][j];
         const int br = b >> 8, bc = b & 255;
-        const double* nc = ncand + static_cast<size_t>(4 * br) * We + 4 * bc;
+        const auto nc = ncand + static_cast<size_t>(4 * br) * We + 4 * bc;
 #pragma unroll
         for (int i = 0; i < 4; ++i) nv[i] = nc[i];
       }
@@ -445,7 +450,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 
   const int p = p0 + u, q = qt + v;
   if (g == 0 && p < nRy && q < nRx) {
-    int16_t* out = idx + (static_cast<size_t>(p) * nRx + q) * K;
+    const auto out = idx + (static_cast<size_t>(p) * nRx + q) * K;
     out[0] = static_cast<int16_t>(r_center);
 #pragma unroll
     for (int i = 0; i < L; ++i) {

@@ -271,6 +271,19 @@ struct WorkList {
   int total;           // begin[n]
 };
 
+// Image buffers in the global address space.  A batch kernel reads each
+// image's descriptor from its work list, and the compiler cannot tell that
+// pointers loaded from memory address global memory: it would use flat
+// instructions, which also count against the LDS wait counter, so that each
+// wait for an LDS result would wait for outstanding global loads and stores
+// as well.  The kernels cast the descriptor's pointers at their use.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> to_global(T* p) {
+  return (global_ptr<T>)p;
+}
+
 // Runs body(rec, local_item) for this workgroup's items: the single image's
 // item blockIdx.x, or every batch item blockIdx.x + k * gridDim.x.  A
 // workgroup's batch items increase, so the image owning the next one is found

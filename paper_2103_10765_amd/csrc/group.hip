@@ -197,7 +197,8 @@ __device__ __forceinline__ void accumulate(acc_t* acc, const GroupArgs& g, int f
 template <int K>
 __device__ __forceinline__ void add_block_weights(acc_t* bw, int pos_v, float w, int lane) {
   if (lane < K)
-    __hip_atomic_fetch_add(bw + pos_v, static_cast<acc_t>(to_fixed(w)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(to_global(bw) + pos_v, static_cast<acc_t>(to_fixed(w)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void zero_acc(acc_t* acc, int n) {
@@ -207,7 +208,8 @@ __device__ __forceinline__ void zero_acc(acc_t* acc, int n) {
 
 __device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __restrict__ dst) {
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = acc[i];
+  const auto gdst = to_global(dst);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) gdst[i] = acc[i];
   __syncthreads();  // the accumulator is reused by the next item
 }
 
@@ -231,7 +233,7 @@ struct GroupWalk {
   __device__ __forceinline__ int rank(int j) const {
     int p, q;
     if (!ref_of(j, p, q) || lane >= K) return 0;
-    return idx[(static_cast<size_t>(p) * g.nRx + q) * K + lane];
+    return to_global(idx)[(static_cast<size_t>(p) * g.nRx + q) * K + lane];
   }
   // stack rows of group j from its ranks: v[k] = stack[pos_k * 64 + lane];
   // lane k < K returns slot k's pixel index and footprint offset
@@ -266,7 +268,7 @@ struct GroupWalk {
       const int pos = __builtin_amdgcn_readlane(pos_v, k);
       const int y = pos / g.W, x = pos - y * g.W;
       const int yy = y + a >= g.H ? y + a - g.H : y + a, xx = x + b >= g.W ? x + b - g.W : x + b;
-      v[0][k] = static_cast<float>(img[static_cast<size_t>(yy) * g.W + xx]) * (1.0f / 65535.0f);
+      v[0][k] = static_cast<float>(to_global(img)[static_cast<size_t>(yy) * g.W + xx]) * (1.0f / 65535.0f);
     }
     return true;
   }
@@ -544,10 +546,11 @@ __device__ __forceinline__ int fdiv(int a, int b) { return (a >= 0) ? a / b : -(
 // weights, then normalise.
 __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int R, int final_stage, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
-  const acc_t* __restrict__ bw = r.partials;
-  const acc_t* __restrict__ partials = tile_sums(r);
-  float* __restrict__ out = final_stage ? r.out : r.basic;
-  uint16_t* __restrict__ q = final_stage ? nullptr : r.q;
+  const auto bw = to_global(static_cast<const acc_t*>(r.partials));
+  const auto partials = to_global(static_cast<const acc_t*>(tile_sums(r)));
+  const auto out = to_global(final_stage ? r.out : r.basic);
+  const bool with_q = !final_stage && r.q != nullptr;
+  const auto q = to_global(r.q);
   const int TY = kStep * kTPY, TX = kStep * kTPX;
   const int xb = (g.W + kReduceThreads - 1) / kReduceThreads;
   const int y = item / xb;
@@ -583,7 +586,7 @@ __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int 
     }
   }
   const size_t plane = static_cast<size_t>(g.FY) * g.FXP;
-  auto at = [&](int i, int j) -> const acc_t* {
+  auto at = [&](int i, int j) -> global_ptr<const acc_t> {
     return partials + (static_cast<size_t>(cty[i]) * g.nTx + ctx[j]) * plane + static_cast<size_t>(cly[i]) * g.FXP +
            clx[j];
   };
@@ -639,7 +642,7 @@ __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int 
                                        static_cast<double>(static_cast<long long>(den)));
     const size_t o = static_cast<size_t>(y) * g.W + x;
     out[o] = v;
-    if (q) {
+    if (with_q) {
       const double d = static_cast<double>(fminf(fmaxf(v, 0.0f), 1.0f));
       q[o] = static_cast<uint16_t>(floor(d * 65535.0 + 0.5));
     }

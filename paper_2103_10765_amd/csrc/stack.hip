@@ -63,8 +63,11 @@ __host__ __device__ constexpr int stack_items(int H, int W) {
 
 template <int KIND>
 __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*stage)[kHalf * kStagePitch],
-                                           const uint16_t* __restrict__ img, float* __restrict__ out,
-                                           unsigned long long* __restrict__ block_weights, int H, int W, int item) {
+                                           const uint16_t* __restrict__ img_, float* __restrict__ out_,
+                                           unsigned long long* __restrict__ block_weights_, int H, int W, int item) {
+  const auto img = to_global(img_);
+  const auto out = to_global(out_);
+  const auto block_weights = to_global(block_weights_);
   const int xt = (W + kWave - 1) / kWave;
   const int y0 = (item / xt) * kRowsPerWg;
   const int x0 = (item % xt) * kWave;
@@ -88,7 +91,8 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
   const int n_pos = min(kWave, W - x0);  // positions of this row in the tile
   // the aggregation that follows adds into the block-start weights
   if (block_weights && y < H && lane < n_pos) block_weights[static_cast<size_t>(y) * W + x0 + lane] = 0;
-  float4* dst = reinterpret_cast<float4*>(out + (static_cast<size_t>(y) * W + x0) * 64);
+  typedef float f32x4v __attribute__((ext_vector_type(4)));
+  const auto dst = (global_ptr<f32x4v>)(out + (static_cast<size_t>(y) * W + x0) * 64);
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     wave_lds_sync();  // the previous half's reads are done
@@ -108,7 +112,7 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
         const int blk = g >> 4, c = (g & 15) * 4;
         if (half * kHalf + blk < n_pos) {
           const float* s = stage[w] + blk * kStagePitch + c;
-          dst[half * kHalf * 16 + g] = make_float4(s[0], s[1], s[2], s[3]);
+          dst[half * kHalf * 16 + g] = f32x4v{s[0], s[1], s[2], s[3]};
         }
       }
     }
