@@ -469,7 +469,7 @@ def batch_bench(ctx, reps=5):
     ms = e0.elapsed_time(e1) / reps
     mpx = sum(h * w for (h, w, _, _) in specs) / 1e6
     return {"images": len(specs), "mpixels": mpx, "ms_per_batch": ms, "mpix_s": mpx / (ms * 1e-3),
-            "mode": "hipGraph replay, persistent kernels over per-image work lists"}
+            "mode": "hipGraph replay, one workgroup per work item of the whole batch"}
 
 
 def size_bench(ctx, p):

@@ -254,7 +254,8 @@ int gbm3d_denoise_noalloc(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, f
  * stage 1, Q and stage 2 as in gbm3d_denoise; otherwise stage 2 with the given
  * pilot.  With GBM3D_BATCH_BASIC_ONLY, stage 1 only (pilot must be NULL) and
  * out receives the basic estimate.  All images run in one sequence of ~9
- * persistent kernel launches that walk per-image work lists; with
+ * kernel launches over the work items of the whole batch (one workgroup per
+ * item, its image found from per-image work lists); with
  * GBM3D_BATCH_GRAPH the sequence is captured once into a hipGraph and replayed
  * while image count, sizes, parameters and flags are unchanged (pointers may
  * change between calls).  Results equal the single-image calls bit for bit.

@@ -1,6 +1,6 @@
 // C ABI of the G-BM3D library: argument validation, device workspace, the
-// stage pipelines for one image and for batches (work lists, persistent
-// launches, hipGraph capture).  Every compute step runs in the library's HIP
+// stage pipelines for one image and for batches (work lists, launches over
+// all of a batch's items, hipGraph capture).  Every compute step runs in the library's HIP
 // kernels.
 #include <hip/hip_runtime.h>
 
@@ -73,6 +73,7 @@ enum Phase { kNorm1, kBm1, kStack1, kGroup1, kReduce1, kNorm2, kBm2, kStack2, kG
 struct BatchPlan {
   std::vector<ImgRec> recs;
   std::vector<int> begin[kPhases];  // n + 1 each
+  std::vector<int> start[kPhases];  // total / kItemBlock + 1 each: the image owning item kItemBlock * b
   int bm_method1 = GBM3D_BM_SHIFT, bm_method2 = GBM3D_BM_SHIFT;
   int bm_split1 = 1, bm_split2 = 1;
   int ht_shape = 0;  // stage-1 group kernel shape
@@ -467,8 +468,16 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
 // batches
 // ---------------------------------------------------------------------------
 
-// Device table layout: recs[n], then kPhases prefix arrays of n + 1 ints.
-size_t table_bytes(int n) { return align256(sizeof(ImgRec) * n) + sizeof(int) * kPhases * (n + 1); }
+// Device table layout: recs[n], then kPhases prefix arrays of n + 1 ints,
+// then each phase's item-block start table.
+size_t start_offset(const BatchPlan& plan, int n, int phase) {
+  size_t o = kPhases * (n + 1);
+  for (int ph = 0; ph < phase; ++ph) o += plan.start[ph].size();
+  return o;
+}
+size_t table_bytes(const BatchPlan& plan, int n) {
+  return align256(sizeof(ImgRec) * n) + sizeof(int) * start_offset(plan, n, kPhases);
+}
 
 int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_params& p, int flags, BatchPlan& plan) {
   const int R = p.search / 2;
@@ -573,6 +582,17 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
     };
     for (int ph = 0; ph < kPhases; ++ph) plan.begin[ph][i + 1] = plan.begin[ph][i] + items[ph];
   }
+  // the image owning the first item of each block of kItemBlock items
+  for (int ph = 0; ph < kPhases; ++ph) {
+    const std::vector<int>& b = plan.begin[ph];
+    plan.start[ph].assign(b[n] / gbm3d::kItemBlock + 1, 0);
+    int i = 0;
+    for (size_t blk = 0; blk < plan.start[ph].size(); ++blk) {
+      const int item = static_cast<int>(blk) * gbm3d::kItemBlock;
+      while (i < n - 1 && b[i + 1] <= item) ++i;
+      plan.start[ph][blk] = i;
+    }
+  }
   return GBM3D_OK;
 }
 
@@ -581,53 +601,55 @@ WorkList worklist(const gbm3d_ctx* ctx, const BatchPlan& plan, int n, int phase)
   WorkList w;
   w.recs = reinterpret_cast<const ImgRec*>(t);
   w.begin = reinterpret_cast<const int*>(t + align256(sizeof(ImgRec) * n)) + phase * (n + 1);
+  w.start = reinterpret_cast<const int*>(t + align256(sizeof(ImgRec) * n)) + start_offset(plan, n, phase);
   w.n = n;
   w.total = plan.begin[phase][n];
   return w;
 }
 
+// Grid cap of the batch launches: none (one workgroup per item).
+constexpr int kFullGrid = 1 << 30;
+
 // Batch matching phase: norm tables first when the correlation kernel runs.
 int launch_batch_match(gbm3d_ctx* ctx, const WorkList& nm, const WorkList& bm, int R, int K, int method, int split,
                        int use_pilot, hipStream_t st) {
   const ImgRec none = blank_rec(0, 0, 0.0f);
-  const int cu = ctx->n_cu;
   if (method == GBM3D_BM_CORR) {
-    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(none, &nm, R, use_pilot, 4 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(none, &nm, R, use_pilot, kFullGrid, st); }),
             "batch norm tables");
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
-              return gbm3d::launch_bm_corr(none, &bm, R, K, split, use_pilot, 4 * cu, st);
+              return gbm3d::launch_bm_corr(none, &bm, R, K, split, use_pilot, kFullGrid, st);
             }),
             "batch block matching");
   } else {
-    HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(none, &bm, R, K, split, use_pilot, 2 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(none, &bm, R, K, split, use_pilot, kFullGrid, st); }),
             "batch block matching");
   }
   return GBM3D_OK;
 }
 
-// The batch launch sequence (also what a graph captures).  Persistent grids
-// of as many workgroups as fit each compute unit together: four matching
-// (correlation) or stack workgroups, two shift-wise matching ones, two
-// hard-threshold group tiles (groups up to 16) or one, and eight reduction
-// workgroups.
+// The batch launch sequence (also what a graph captures).  Every launch has
+// one workgroup per work item of the whole batch (not a persistent grid
+// walking several items): a workgroup's global stores then never hold up
+// the loads of its next item (both count against the one vector-memory
+// counter), and a finished workgroup's slot is refilled at once.
 int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_params& p, hipStream_t st) {
   const int R = p.search / 2;
   const ImgRec none = blank_rec(0, 0, 0.0f);
-  const int cu = ctx->n_cu;
   if (plan.any_stage1) {
     const WorkList nm = worklist(ctx, plan, n, kNorm1), bm = worklist(ctx, plan, n, kBm1);
     const WorkList sk = worklist(ctx, plan, n, kStack1);
     const WorkList gr = worklist(ctx, plan, n, kGroup1), rd = worklist(ctx, plan, n, kReduce1);
     CHECK(launch_batch_match(ctx, nm, bm, R, p.k_ht, plan.bm_method1, plan.bm_split1, 0, st));
-    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, 4 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, kFullGrid, st); }),
             "batch stack");
     HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
               return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0,
-                                            plan.ht_shape, gbm3d::group_ht_tiles_per_cu(p.k_ht, plan.ht_shape) * cu,
+                                            plan.ht_shape, kFullGrid,
                                             st);
             }),
             "batch hard-threshold groups");
-    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 0, 8 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 0, kFullGrid, st); }),
             "batch aggregation");
   }
   if (plan.any_stage2) {
@@ -635,15 +657,15 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
     const WorkList sk = worklist(ctx, plan, n, kStack2);
     const WorkList gr = worklist(ctx, plan, n, kGroup2), rd = worklist(ctx, plan, n, kReduce2);
     CHECK(launch_batch_match(ctx, nm, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
-    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, 4 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, kFullGrid, st); }),
             "batch stack");
-    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, 4 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, kFullGrid, st); }),
             "batch pilot stack");
     HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
-              return gbm3d::launch_group_wiener(none, &gr, R, p.k_wiener, cu, st);
+              return gbm3d::launch_group_wiener(none, &gr, R, p.k_wiener, kFullGrid, st);
             }),
             "batch Wiener groups");
-    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 1, 8 * cu, st); }),
+    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 1, kFullGrid, st); }),
             "batch aggregation");
   }
   return GBM3D_OK;
@@ -651,7 +673,7 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
 
 // Copies the plan's table to the device (stream-ordered, from pinned memory).
 int upload_table(gbm3d_ctx* ctx, const BatchPlan& plan, int n, hipStream_t st) {
-  const size_t bytes = table_bytes(n);
+  const size_t bytes = table_bytes(plan, n);
   CHECK(ensure(ctx, ctx->batch_table, bytes, "batch table"));
   if (ctx->host_stage_bytes < bytes) {
     if (ctx->host_stage) {
@@ -669,7 +691,10 @@ int upload_table(gbm3d_ctx* ctx, const BatchPlan& plan, int n, hipStream_t st) {
   char* h = static_cast<char*>(ctx->host_stage);
   std::memcpy(h, plan.recs.data(), sizeof(ImgRec) * n);
   int* b = reinterpret_cast<int*>(h + align256(sizeof(ImgRec) * n));
-  for (int ph = 0; ph < kPhases; ++ph) std::memcpy(b + ph * (n + 1), plan.begin[ph].data(), sizeof(int) * (n + 1));
+  for (int ph = 0; ph < kPhases; ++ph) {
+    std::memcpy(b + ph * (n + 1), plan.begin[ph].data(), sizeof(int) * (n + 1));
+    std::memcpy(b + start_offset(plan, n, ph), plan.start[ph].data(), sizeof(int) * plan.start[ph].size());
+  }
   HIP_TRY(ctx, hipMemcpyAsync(ctx->batch_table.p, h, bytes, hipMemcpyHostToDevice, st), "table copy");
   HIP_TRY(ctx, hipEventRecord(ctx->table_copied, st), "hipEventRecord");
   return GBM3D_OK;

@@ -267,6 +267,7 @@ struct ImgRec {
 struct WorkList {
   const ImgRec* recs;  // device array [n]
   const int* begin;    // device array [n + 1]: first item of each image
+  const int* start;    // device array [total / kItemBlock + 1]: the image owning item kItemBlock * b
   int n;
   int total;           // begin[n]
 };
@@ -279,32 +280,56 @@ struct WorkList {
 // as well.  The kernels cast the descriptor's pointers at their use.
 template <typename T>
 using global_ptr = __attribute__((address_space(1))) T*;
+
+// Granularity of a batch work list's item -> image lookup table.
+constexpr int kItemBlock = 64;
 template <typename T>
 __device__ __forceinline__ global_ptr<T> to_global(T* p) {
   return (global_ptr<T>)p;
 }
 
 // Runs body(rec, local_item) for this workgroup's items: the single image's
-// item blockIdx.x, or every batch item blockIdx.x + k * gridDim.x.  A
-// workgroup's batch items increase, so the image owning the next one is found
-// by stepping forward from the current one through the per-image prefix
-// offsets (begin is non-decreasing, begin[0] = 0, begin[n] = total; wave-
-// uniform scalar loads), and its descriptor is reloaded only when it changes.
+// item blockIdx.x, or every batch item blockIdx.x + k * gridDim.x.  The image
+// owning a batch item is found from the image owning the first item of its
+// block of kItemBlock items (start) by stepping forward through the
+// per-image prefix offsets (begin is non-decreasing, begin[0] = 0,
+// begin[n] = total; wave-uniform scalar loads); the descriptor is reloaded
+// only when the image changes.
 template <bool BATCH, typename F>
 __device__ __forceinline__ void for_each_item(const ImgRec& one, const WorkList& wl, F&& body) {
   if constexpr (!BATCH) {
     body(one, static_cast<int>(blockIdx.x));
   } else {
+    // the work list is read-only for the launch: through constant-space
+    // pointers its uniform loads are scalar loads, which wait on the LDS /
+    // scalar counter and not behind the previous item's global stores
+    typedef const __attribute__((address_space(4))) int* const_int_ptr;
+    typedef const __attribute__((address_space(4))) ImgRec* const_rec_ptr;
+    const const_int_ptr begin = (const_int_ptr)wl.begin;
+    const const_int_ptr start = (const_int_ptr)wl.start;
+    const const_rec_ptr recs = (const_rec_ptr)wl.recs;
     int i = -1, lo = 0, hi = 0;  // image i owns items [lo, hi)
     ImgRec r;
     for (int item = blockIdx.x; item < wl.total; item += gridDim.x) {
       if (item >= hi) {
-        do {
-          ++i;
-          lo = hi;
-          hi = wl.begin[i + 1];
-        } while (item >= hi);
-        r = wl.recs[i];
+        i = start[item / kItemBlock];
+        while (begin[i + 1] <= item) ++i;
+        lo = begin[i];
+        hi = begin[i + 1];
+        r.noisy = recs[i].noisy;
+        r.pilot = recs[i].pilot;
+        r.out = recs[i].out;
+        r.basic = recs[i].basic;
+        r.q = recs[i].q;
+        r.stack_a = recs[i].stack_a;
+        r.stack_b = recs[i].stack_b;
+        r.idx = recs[i].idx;
+        r.partials = recs[i].partials;
+        r.norm = recs[i].norm;
+        r.H = recs[i].H;
+        r.W = recs[i].W;
+        r.sigma = recs[i].sigma;
+        r.eps = recs[i].eps;
       }
       body(r, item - lo);
       __syncthreads();  // LDS is reused by the next item
