@@ -501,6 +501,35 @@ def test_batch_equals_single_calls(torch, G, ctx):
         assert np.array_equal(basic[i].cpu().numpy(), ctx.basic(imgs[i], sig[i]).cpu().numpy())
 
 
+def test_batch_many_small_images_equal_single_calls(torch, G, ctx):
+    """Many images of 39..64 px (several images share each 64-item block of
+    every phase's item -> image table) around two larger ones, some with a
+    pilot (no stage-1 items, also as the first and the last image): every
+    batch output equals the single-image call bit for bit, eager and under
+    graph replay."""
+    say("batch many small")
+    imgs, sig = _batch_inputs(torch, 46, 39, 64, 1300)
+    big, bsig = _batch_inputs(torch, 2, 200, 260, 1400)
+    imgs = imgs[:20] + big[:1] + imgs[20:] + big[1:]
+    sig = sig[:20] + bsig[:1] + sig[20:] + bsig[1:]
+    rng = np.random.default_rng(1500)
+    pil = [None] * len(imgs)
+    for i in (0, 7, 8, 30, len(imgs) - 1):
+        pil[i] = up(torch, synth.to_u16(rng.random(tuple(imgs[i].shape))))
+    refs = [(ctx.denoise(x, s) if pl is None else ctx.wiener(x, pl, s)).cpu().numpy()
+            for x, s, pl in zip(imgs, sig, pil)]
+    outs = ctx.denoise_batch(imgs, sig, pilots=pil)
+    torch.cuda.synchronize()
+    for i in range(len(imgs)):
+        assert np.array_equal(outs[i].cpu().numpy(), refs[i]), i
+    outs = [torch.full(tuple(x.shape), -1.0, device="cuda") for x in imgs]
+    for rep in range(2):
+        ctx.denoise_batch(imgs, sig, pilots=pil, outs=outs, graph=True)
+        torch.cuda.synchronize()
+        for i in range(len(imgs)):
+            assert np.array_equal(outs[i].cpu().numpy(), refs[i]), (rep, i)
+
+
 def test_batch_graph_replays_match_eager(torch, G, ctx):
     """Captured once, replayed several times with eager work and syncs in
     between; every replay equals the eager batch."""
