@@ -17,6 +17,7 @@ namespace gbm3d {
 namespace {
 
 constexpr int kRowsPerWg = 4;
+constexpr int kStackThreads = kRowsPerWg * kWave;  // one wave per output row
 constexpr int kPixRows = kRowsPerWg + kPatch - 1;  // 11
 constexpr int kPixCols = kWave + kPatch - 1;       // 71
 constexpr int kStagePitch = 65;                    // floats per parked block (odd: conflict-free)
@@ -122,7 +123,7 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
 
 // src_sel: 0 = noisy, 1 = pilot; dst_sel: 0 = stack_a, 1 = stack_b
 template <int KIND, bool BATCH>
-__global__ __launch_bounds__(256) void stack_kernel(ImgRec one, WorkList wl, int src_sel, int dst_sel) {
+__global__ __launch_bounds__(kStackThreads) void stack_kernel(ImgRec one, WorkList wl, int src_sel, int dst_sel) {
   __shared__ float pix[kPixRows][kPixCols + 1];
   __shared__ float stage[kRowsPerWg][kHalf * kStagePitch];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
@@ -140,16 +141,16 @@ hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src
   if (!wl) {
     const int items = stack_items(one.H, one.W);
     if (kind == 0)
-      hipLaunchKernelGGL((stack_kernel<0, false>), dim3(items), dim3(256), 0, st, one, WorkList{}, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<0, false>), dim3(items), dim3(kStackThreads), 0, st, one, WorkList{}, src_sel, dst_sel);
     else
-      hipLaunchKernelGGL((stack_kernel<1, false>), dim3(items), dim3(256), 0, st, one, WorkList{}, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<1, false>), dim3(items), dim3(kStackThreads), 0, st, one, WorkList{}, src_sel, dst_sel);
   } else {
     if (wl->total <= 0) return hipSuccess;
     const int grid = std::min(wl->total, grid_cap);
     if (kind == 0)
-      hipLaunchKernelGGL((stack_kernel<0, true>), dim3(grid), dim3(256), 0, st, one, *wl, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<0, true>), dim3(grid), dim3(kStackThreads), 0, st, one, *wl, src_sel, dst_sel);
     else
-      hipLaunchKernelGGL((stack_kernel<1, true>), dim3(grid), dim3(256), 0, st, one, *wl, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<1, true>), dim3(grid), dim3(kStackThreads), 0, st, one, *wl, src_sel, dst_sel);
   }
   return hipGetLastError();
 }
