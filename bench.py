@@ -34,28 +34,22 @@ def algorithmic_work(H, W, search, k1, k2):
     fp64 vector ALU."""
     from paper_2103_10765_amd import gbm3d
     nref = gbm3d.n_refs(H, W, 3)
-    R = search // 2
-    TPY = TPX = 8
-    nRy, nRx = (H + 2) // 3, (W + 2) // 3
-    FY = 3 * (TPY - 1) + 8 + 2 * R
-    FX = 3 * (TPX - 1) + 8 + 2 * R
-    FXP = FX + ((8 - FX) % 32 + 32) % 32
-    n_tiles = ((nRy + TPY - 1) // TPY) * ((nRx + TPX - 1) // TPX)
-    partial_bytes = n_tiles * FY * FXP * 8  # 64-bit fixed-point numerator footprints
     weight_bytes = H * W * 8  # 64-bit block-start weights
+    num_bytes = H * W * 8  # 64-bit numerator sums
     S2 = search * search
     return {
         "bm": ("alu", BM_FLOP_PER_PAIR * H * W * (S2 - 1), "FLOP"),
         # pixels in; one float64 table entry out per bordered position
         "bm_norm": ("hbm", H * W * 2 + (H + 64) * (W + 64) * 8, "B"),
-        # the bior launch and the first of the two DCT launches clear the weights
-        "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes, "B"),
-        "stack_dct": ("hbm", H * W * (2 + 256) + weight_bytes / 2, "B"),
-        # spectra gathered, ranks read, numerator footprints written, one
-        # 8-byte weight added per block
-        "group_ht": ("hbm", nref * (k1 * 256 + 2 * k1 + 8 * k1) + partial_bytes, "B"),
-        "group_wiener": ("hbm", nref * (2 * k2 * 256 + 2 * k2 + 8 * k2) + partial_bytes, "B"),
-        "reduce": ("hbm", partial_bytes + weight_bytes + H * W * 6, "B"),
+        # the bior launch and the first of the two DCT launches clear the
+        # weights and numerator sums
+        "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes + num_bytes, "B"),
+        "stack_dct": ("hbm", H * W * (2 + 256) + (weight_bytes + num_bytes) / 2, "B"),
+        # spectra gathered, ranks read, one 8-byte weight added per block, the
+        # image's numerator sums added into once
+        "group_ht": ("hbm", nref * (k1 * 256 + 2 * k1 + 8 * k1) + num_bytes, "B"),
+        "group_wiener": ("hbm", nref * (2 * k2 * 256 + 2 * k2 + 8 * k2) + num_bytes, "B"),
+        "reduce": ("hbm", num_bytes + weight_bytes + H * W * 6, "B"),
     }
 
 

@@ -257,12 +257,25 @@ struct ImgRec {
   float* stack_b;                  // f32 [H*W][64]
   int16_t* idx;                    // i16 [n_ref][K]
   unsigned long long* partials;    // 64-bit fixed-point aggregation sums: H*W block-start
-                                   // weights (cleared by the stack launch into stack_a),
-                                   // then the tiles' numerator footprints
+                                   // weights, then H*W numerator sums (both cleared by the
+                                   // stack launch into stack_a)
   double* norm;                    // block norms with a periodic border (correlation matching)
   int H, W;
   float sigma, eps;
 };
+
+// Layout of an image's aggregation buffer (ImgRec::partials): the block-start
+// weights [H][W], padded to a multiple of 32 entries, then the numerator sums
+// [H][W].
+__host__ __device__ inline size_t block_weight_entries(int H, int W) {
+  return (static_cast<size_t>(H) * W + 31) / 32 * 32;
+}
+__host__ __device__ inline size_t aggregation_entries(int H, int W) {
+  return block_weight_entries(H, W) + static_cast<size_t>(H) * W;
+}
+__device__ __forceinline__ unsigned long long* numerator_sums(const ImgRec& r) {
+  return r.partials + block_weight_entries(r.H, r.W);
+}
 
 struct WorkList {
   const ImgRec* recs;  // device array [n]

@@ -84,13 +84,6 @@ struct GroupCfg {
                 "LDS of the tiles sharing a CU");
 };
 
-// Layout of an image's aggregation buffer (ImgRec::partials): the H*W
-// block-start weights, then one footprint plane of numerator sums per tile.
-__host__ __device__ inline size_t block_weight_entries(int H, int W) {
-  return (static_cast<size_t>(H) * W + 31) / 32 * 32;
-}
-__device__ __forceinline__ acc_t* tile_sums(const ImgRec& r) { return r.partials + block_weight_entries(r.H, r.W); }
-
 struct GroupArgs {
   int H, W, R, S, nRy, nRx, nTx, nTy;
   int FY, FX, FXP;
@@ -206,10 +199,39 @@ __device__ __forceinline__ void zero_acc(acc_t* acc, int n) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void flush_acc(const acc_t* acc, int n, acc_t* __restrict__ dst) {
+// The tile's footprint (origin fy0, fx0 in unwrapped image coordinates) added
+// into the image's numerator sums at the periodic positions it covers, one
+// agent-scope integer atomic per nonzero cell: integer addition, so the sums
+// do not depend on the order in which tiles arrive.  A wave takes whole
+// footprint rows, a lane the same columns of each.
+__device__ __forceinline__ void flush_acc(const acc_t* acc, const GroupArgs& g, int fy0, int fx0,
+                                          acc_t* __restrict__ num) {
   __syncthreads();
-  const auto gdst = to_global(dst);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) gdst[i] = acc[i];
+  const auto gnum = to_global(num);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int waves = static_cast<int>(blockDim.x) / kWave;
+  // -R <= fy0 and fy0 + FY <= H + FY - R + 1: with H > FY every footprint row
+  // is at most one period away (same for the columns)
+  const bool once = g.H > g.FY && g.W > g.FX;
+  constexpr int kPasses = (Foot::FXmax + kWave - 1) / kWave;
+  int xs[kPasses];
+#pragma unroll
+  for (int p = 0; p < kPasses; ++p) {
+    const int x = fx0 + p * kWave + lane;
+    xs[p] = once ? x + (x < 0 ? g.W : (x >= g.W ? -g.W : 0)) : pmod(x, g.W);
+  }
+  for (int fy = wave_id(); fy < g.FY; fy += waves) {
+    int y = fy0 + fy;
+    y = once ? y + (y < 0 ? g.H : (y >= g.H ? -g.H : 0)) : pmod(y, g.H);
+    const auto row = gnum + static_cast<size_t>(y) * g.W;
+    const acc_t* cells = acc + fy * g.FXP;
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+      const int fx = p * kWave + lane;
+      const acc_t v = fx < g.FX ? cells[fx] : 0;
+      if (v != 0) __hip_atomic_fetch_add(row + xs[p], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
   __syncthreads();  // the accumulator is reused by the next item
 }
 
@@ -433,7 +455,7 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc,
   } else {
     for_each_group<K, 1, Cfg::prefetch>(walk, stacks, filter);
   }
-  flush_acc(acc, n_acc, tile_sums(r) + static_cast<size_t>(item) * n_acc);
+  flush_acc(acc, g, fy0, fx0, numerator_sums(r));
 }
 
 // One work item = one tile of references: stage-2 groups.
@@ -502,7 +524,7 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc,
     }
     add_block_weights<K>(bw, pos_v, w, lane);
   });
-  flush_acc(acc, n_acc, tile_sums(r) + static_cast<size_t>(item) * n_acc);
+  flush_acc(acc, g, fy0, fx0, numerator_sums(r));
 }
 
 // (the second launch bound is the minimum number of waves per SIMD)
@@ -520,8 +542,8 @@ __global__ __launch_bounds__((GroupCfg<K, true, BATCH, WIDE>::threads),
   });
 }
 
-// the block-start weights the aggregation adds into (the bior1.5 stack
-// launch clears them otherwise)
+// the block-start weights and numerator sums the aggregation adds into (the
+// bior1.5 stack launch clears them otherwise)
 __global__ void clear_weights_kernel(acc_t* __restrict__ w, size_t n) {
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x)
@@ -538,84 +560,39 @@ __global__ __launch_bounds__((GroupCfg<K, false, BATCH>::threads)) void group_wi
                        [&](const ImgRec& r, int item) { group_wiener_body<K, BATCH>(acc, scratch, r, R, item); });
 }
 
-// floor(a / b) for b > 0
-__device__ __forceinline__ int fdiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
-
-// One work item = 256 pixels of one row: sum of the partial footprints
-// covering each pixel (periodic), the 8 x 8 box sum of the block-start
-// weights, then normalise.
-__device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int R, int final_stage, int item) {
-  const GroupArgs g = make_args(r.H, r.W, R);
+// One work item = 256 pixels of one row: the numerator sum of each pixel over
+// the 8 x 8 box sum of the block-start weights ending at it, then normalise.
+__device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int final_stage, int item) {
   const auto bw = to_global(static_cast<const acc_t*>(r.partials));
-  const auto partials = to_global(static_cast<const acc_t*>(tile_sums(r)));
+  const auto nums = to_global(static_cast<const acc_t*>(numerator_sums(r)));
   const auto out = to_global(final_stage ? r.out : r.basic);
   const bool with_q = !final_stage && r.q != nullptr;
   const auto q = to_global(r.q);
-  const int TY = kStep * kTPY, TX = kStep * kTPX;
-  const int xb = (g.W + kReduceThreads - 1) / kReduceThreads;
+  const int H = r.H, W = r.W;
+  const int xb = (W + kReduceThreads - 1) / kReduceThreads;
   const int y = item / xb;
   const int xs = (item % xb) * kReduceThreads;
   const int x = xs + static_cast<int>(threadIdx.x);
-  const bool active = x < g.W;
-  // candidate (tile row, local row) pairs for y; the footprint of tile row t
-  // covers unwrapped rows [t*TY - R, t*TY - R + FY)
-  int cty[16], cly[16], ny = 0;
-  int ctx[16], clx[16], nx = 0;
-  if (active) {
-    {
-      const int lo = -R, hi = (g.nTy - 1) * TY - R + g.FY;
-      for (int yy = y + fdiv(lo - y + g.H - 1, g.H) * g.H; yy < hi; yy += g.H) {
-        const int t0 = max(0, fdiv(yy + R - g.FY, TY) + 1), t1 = min(g.nTy - 1, fdiv(yy + R, TY));
-        for (int t = t0; t <= t1 && ny < 16; ++t) {
-          cty[ny] = t;
-          cly[ny] = yy - (t * TY - R);
-          ++ny;
-        }
-      }
-    }
-    {
-      const int lo = -R, hi = (g.nTx - 1) * TX - R + g.FX;
-      for (int xx = x + fdiv(lo - x + g.W - 1, g.W) * g.W; xx < hi; xx += g.W) {
-        const int t0 = max(0, fdiv(xx + R - g.FX, TX) + 1), t1 = min(g.nTx - 1, fdiv(xx + R, TX));
-        for (int t = t0; t <= t1 && nx < 16; ++t) {
-          ctx[nx] = t;
-          clx[nx] = xx - (t * TX - R);
-          ++nx;
-        }
-      }
-    }
-  }
-  const size_t plane = static_cast<size_t>(g.FY) * g.FXP;
-  auto at = [&](int i, int j) -> global_ptr<const acc_t> {
-    return partials + (static_cast<size_t>(cty[i]) * g.nTx + ctx[j]) * plane + static_cast<size_t>(cly[i]) * g.FXP +
-           clx[j];
-  };
-  // The usual case, at most 4 x 4 footprints (3 per axis inside the image,
-  // 4 where the last tiles' footprints wrap over the first rows or columns):
-  // their loads are issued before the weights' column sums below, so the two
-  // round trips overlap.
-  constexpr int kFew = 4;
-  const bool few = ny <= kFew && nx <= kFew;
-  acc_t vn[kFew][kFew];
-#pragma unroll
-  for (int i = 0; i < kFew; ++i)
-#pragma unroll
-    for (int j = 0; j < kFew; ++j) vn[i][j] = (few && i < ny && j < nx) ? *at(i, j) : 0;
+  const bool active = x < W;
+  const size_t o = static_cast<size_t>(y) * W + x;
+  // the numerator's load is issued before the weights' column sums below, so
+  // the two round trips overlap
+  const acc_t num = active ? nums[o] : 0;
   // colsum[c] = sum over rows y-7..y of the weights at column xs - 7 + c
   // (H, W >= 8, so a row index wraps at most once; so does a column index
   // when W covers a chunk and its 7-column margin)
-  const bool wide = g.W >= kReduceThreads + 7;
+  const bool wide = W >= kReduceThreads + 7;
   for (int c = threadIdx.x; c < kReduceThreads + 7; c += blockDim.x) {
     int xi = xs - 7 + c;
     if (wide)
-      xi += xi < 0 ? g.W : (xi >= g.W ? -g.W : 0);
+      xi += xi < 0 ? W : (xi >= W ? -W : 0);
     else
-      xi = pmod(xi, g.W);
+      xi = pmod(xi, W);
     acc_t v[8];
 #pragma unroll
     for (int dy = 0; dy < 8; ++dy) {
-      const int yy = y - dy < 0 ? y - dy + g.H : y - dy;
-      v[dy] = bw[static_cast<size_t>(yy) * g.W + xi];
+      const int yy = y - dy < 0 ? y - dy + H : y - dy;
+      v[dy] = bw[static_cast<size_t>(yy) * W + xi];
     }
     acc_t sum = 0;
 #pragma unroll
@@ -624,23 +601,11 @@ __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int 
   }
   __syncthreads();
   if (active) {
-    acc_t num = 0;
-    if (few) {
-#pragma unroll
-      for (int i = 0; i < kFew; ++i)
-#pragma unroll
-        for (int j = 0; j < kFew; ++j) num += vn[i][j];
-    } else {
-      // small images whose footprints wrap around more than once
-      for (int i = 0; i < ny; ++i)
-        for (int j = 0; j < nx; ++j) num += *at(i, j);
-    }
     acc_t den = 0;
 #pragma unroll
     for (int dx = 0; dx < 8; ++dx) den += colsum[threadIdx.x + 7 - dx];
     const float v = static_cast<float>(static_cast<double>(static_cast<long long>(num)) /
                                        static_cast<double>(static_cast<long long>(den)));
-    const size_t o = static_cast<size_t>(y) * g.W + x;
     out[o] = v;
     if (with_q) {
       const double d = static_cast<double>(fminf(fmaxf(v, 0.0f), 1.0f));
@@ -650,9 +615,9 @@ __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int 
 }
 
 template <bool BATCH>
-__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ImgRec one, WorkList wl, int R, int final_stage) {
+__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ImgRec one, WorkList wl, int final_stage) {
   __shared__ acc_t colsum[kReduceThreads + 8];
-  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { reduce_body(colsum, r, R, final_stage, item); });
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) { reduce_body(colsum, r, final_stage, item); });
 }
 
 __global__ void quantize_kernel(const float* __restrict__ in, uint16_t* __restrict__ out, size_t n) {
@@ -666,8 +631,8 @@ __global__ void quantize_kernel(const float* __restrict__ in, uint16_t* __restri
 }  // namespace
 
 size_t partials_bytes(int H, int W, int R) {
-  const GroupArgs g = make_args(H, W, R);
-  return (block_weight_entries(H, W) + static_cast<size_t>(g.nTy) * g.nTx * g.FY * g.FXP) * sizeof(acc_t);
+  (void)R;
+  return aggregation_entries(H, W) * sizeof(acc_t);
 }
 
 int group_items_for(int H, int W, int R) {
@@ -720,7 +685,7 @@ hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, 
 }
 
 hipError_t launch_clear_weights(const ImgRec& one, hipStream_t st) {
-  const size_t n = block_weight_entries(one.H, one.W);
+  const size_t n = aggregation_entries(one.H, one.W);
   const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(clear_weights_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, one.partials, n);
   return hipGetLastError();
@@ -754,11 +719,11 @@ hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int R, int final
                          hipStream_t st) {
   if (!wl) {
     hipLaunchKernelGGL((reduce_kernel<false>), dim3(reduce_items(one.H, one.W)), dim3(kReduceThreads), 0, st, one,
-                       WorkList{}, R, final_stage);
+                       WorkList{}, final_stage);
   } else {
     if (wl->total <= 0) return hipSuccess;
     hipLaunchKernelGGL((reduce_kernel<true>), dim3(std::min(wl->total, grid_cap)), dim3(kReduceThreads), 0, st,
-                       one, *wl, R, final_stage);
+                       one, *wl, final_stage);
   }
   return hipGetLastError();
 }

@@ -46,7 +46,8 @@ hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src
 int stack_items_for(int H, int W);
 
 // bytes of the aggregation buffer (64-bit fixed point) of the group kernels:
-// block-start weights of the image, then one numerator footprint per tile
+// block-start weights of the image, then its numerator sums (R: unused, the
+// size does not depend on the search window)
 size_t partials_bytes(int H, int W, int R);
 int group_items_for(int H, int W, int R);
 
@@ -59,15 +60,14 @@ int group_items_for(int H, int W, int R);
 hipError_t launch_group_ht(const ImgRec& one, const WorkList* wl, int R, int K, float ht_a, float ht_b,
                            int weight_mode, int keep_dc, int recompute, int shape, int grid_cap, hipStream_t st);
 int group_ht_tiles_per_cu(int K, int shape);
-// zeroes the block-start weights of rec.partials (what the bior1.5 stack
-// launch does when the stage-1 groups read the stack)
+// zeroes the block-start weights and numerator sums of rec.partials (what the
+// bior1.5 stack launch does when the stage-1 groups read the stack)
 hipError_t launch_clear_weights(const ImgRec& one, hipStream_t st);
 
 // stage-2 groups: stack_a (noisy DCT) + stack_b (pilot DCT) + idx -> partials
 hipError_t launch_group_wiener(const ImgRec& one, const WorkList* wl, int R, int K, int grid_cap, hipStream_t st);
 
-// sum(num) over the overlapping tile footprints / 8 x 8 box sum of the
-// block-start weights into rec.basic
+// numerator sum / 8 x 8 box sum of the block-start weights into rec.basic
 // (+ its quantisation into rec.q when set) or, with final_stage, rec.out
 hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int R, int final_stage, int grid_cap,
                          hipStream_t st);

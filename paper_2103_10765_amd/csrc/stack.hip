@@ -90,8 +90,13 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
   forward2d<KIND>(x);
   const int y = y0 + w;
   const int n_pos = min(kWave, W - x0);  // positions of this row in the tile
-  // the aggregation that follows adds into the block-start weights
-  if (block_weights && y < H && lane < n_pos) block_weights[static_cast<size_t>(y) * W + x0 + lane] = 0;
+  // the aggregation that follows adds into the block-start weights and the
+  // numerator sums
+  if (block_weights && y < H && lane < n_pos) {
+    const size_t o = static_cast<size_t>(y) * W + x0 + lane;
+    block_weights[o] = 0;
+    block_weights[block_weight_entries(H, W) + o] = 0;
+  }
   typedef float f32x4v __attribute__((ext_vector_type(4)));
   const auto dst = (global_ptr<f32x4v>)(out + (static_cast<size_t>(y) * W + x0) * 64);
 #pragma unroll
