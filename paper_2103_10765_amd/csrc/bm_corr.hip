@@ -318,30 +318,40 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 
   if (qt < nRx) {
     const int nblk = nb * nb;
-    // norms of this lane's four candidates of block number j (global loads,
-    // issued one block ahead of their use)
-    auto norms = [&](int j, double (&nv)[4]) {
-      if (j < nblk) {
-        const int b = kOrder.b[nb][j];
-        const int br = b >> 8, bc = b & 255;
-        const auto nc = ncand + static_cast<size_t>(4 * br) * We + 4 * bc;
+    // Block j of the walk: its entry in the walk order (row << 8 | column,
+    // a scalar load), this lane's four candidate norms (global loads), its
+    // operands (LDS) and its products (matrix cores).  Past the end of the
+    // walk the last block's entry is read and what follows from it is never
+    // used, so every load is unconditional and the wait before a block's use
+    // covers its own loads only.
+    auto order = [&](int j) { return kOrder.b[nb][j < nblk ? j : nblk - 1]; };
+    auto load_norms = [&](int b, double (&nv)[4]) {
+      const auto nc = ncand + static_cast<size_t>(4 * (b >> 8)) * We + 4 * (b & 255);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) nv[i] = nc[i];
-      }
+      for (int i = 0; i < 4; ++i) nv[i] = nc[i];
     };
-    // WARM: return the four keys (+inf for a position outside the window or
-    // the reference itself) instead of buffering those below the bound
-    auto block = [&](int j, const double (&nv)[4], auto warm, double (&keys)[4]) {
-      const int b = kOrder.b[nb][j];
-      const int br = b >> 8, bc = b & 255;
-      // operand: candidate m = n -> block row n / 4, column n % 4
+    struct Ops {
       i32x4 ch, cl;
-      load_operand(hp, lp, 4 * br + (n >> 2), 12 * t + 4 * bc + (n & 3), g, ch, cl);
+    };
+    // operand: candidate m = n -> block row n / 4, column n % 4
+    auto operands = [&](int b, Ops& o) {
+      load_operand(hp, lp, 4 * (b >> 8) + (n >> 2), 12 * t + 4 * (b & 255) + (n & 3), g, o.ch, o.cl);
+    };
+    struct Prod {
+      i32x4 hh, cc, ll;
+    };
+    // the block's four exact byte-plane products
+    auto products = [&](const Ops& o, Prod& pr) {
       const i32x4 zero = {0, 0, 0, 0};
-      const i32x4 hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ch, rh, zero, 0, 0, 0);
-      i32x4 cc = __builtin_amdgcn_mfma_i32_16x16x64_i8(ch, rl, zero, 0, 0, 0);
-      cc = __builtin_amdgcn_mfma_i32_16x16x64_i8(cl, rh, cc, 0, 0, 0);
-      const i32x4 ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(cl, rl, zero, 0, 0, 0);
+      pr.hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.ch, rh, zero, 0, 0, 0);
+      pr.cc = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.ch, rl, zero, 0, 0, 0);
+      pr.cc = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.cl, rh, pr.cc, 0, 0, 0);
+      pr.ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(o.cl, rl, zero, 0, 0, 0);
+    };
+    // the block's keys from its norms and products
+    auto keys_of = [&](int b, const double (&nv)[4], const Prod& pr, auto warm, double (&keys)[4]) {
+      const int br = b >> 8, bc = b & 255;
+      const i32x4 hh = pr.hh, cc = pr.cc, ll = pr.ll;
       // result lane (g, n): candidates (4 br + g, 4 bc + i) vs reference (3u, 3v), in window units
       const int ey = 4 * br + g - 3 * u;     // dy + R
       const int ex0 = 4 * bc - 3 * v;        // dx + R for i = 0
@@ -388,9 +398,14 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
         double k4[4] = {kInf, kInf, kInf, kInf};
         const int jw = part + w * SPLIT;
         if (jw < nblk) {
+          const int bw = order(jw);
           double nvw[4];
-          norms(jw, nvw);
-          block(jw, nvw, std::true_type{}, k4);
+          Ops ow;
+          Prod pw;
+          load_norms(bw, nvw);
+          operands(bw, ow);
+          products(ow, pw);
+          keys_of(bw, nvw, pw, std::true_type{}, k4);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) seed[4 * w + i] = k4[i];
@@ -401,19 +416,38 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       publish();
     }
     double unused[4];
-    // two norm buffers in turn: the loads for the next block are in flight
-    // while this one is processed
+    // Software pipeline over the rest of the walk, in steps of SPLIT blocks:
+    // while block j's keys are formed, block j + 2 SPLIT's operands are read
+    // from LDS, and its products and norms are issued right after, two steps
+    // ahead of their use.  Two register sets of norms and products alternate.
     const int jb = part + kWarm * SPLIT;
-    double na[4], nb4[4];
-    norms(jb, na);
-    norms(jb + SPLIT, nb4);
+    int b0 = order(jb), b1 = order(jb + SPLIT), b2 = order(jb + 2 * SPLIT);
+    double nv0[4], nv1[4];
+    Prod p0, p1;
+    Ops op;
+    // (issued in walk order: the waits in the loop count on the older loads
+    // landing first)
+    load_norms(b0, nv0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_norms(b1, nv1);
+    operands(b0, op);
+    products(op, p0);
+    operands(b1, op);
+    products(op, p1);
+    auto step = [&](int j, double (&nvc)[4], Prod& pc) {
+      operands(b2, op);
+      keys_of(b0, nvc, pc, std::false_type{}, unused);
+      products(op, pc);
+      load_norms(b2, nvc);
+      b0 = b1;
+      b1 = b2;
+      b2 = order(j + 3 * SPLIT);
+    };
 #pragma unroll 1
     for (int j = jb; j < nblk; j += 2 * SPLIT) {
-      block(j, na, std::false_type{}, unused);
-      norms(j + 2 * SPLIT, na);
+      step(j, nv0, p0);
       if (j + SPLIT >= nblk) break;
-      block(j + SPLIT, nb4, std::false_type{}, unused);
-      norms(j + 3 * SPLIT, nb4);
+      step(j + SPLIT, nv1, p1);
     }
   }
   if (wave_any(cnt > 0)) flush();
@@ -459,8 +493,14 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   }
 }
 
+// The second launch bound is the waves per SIMD that the registers must
+// allow: what the LDS of a workgroup allows for K = 16 (four workgroups of
+// four waves per CU) and K = 32 (three); smaller groups are held by neither.
+template <int K>
+constexpr int kCorrWaves = K == 16 ? 4 : K == 32 ? 3 : 2;
+
 template <int K, int TPW, int SPLIT, bool BATCH>
-__global__ __launch_bounds__(256, 2) void bm_corr_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
+__global__ __launch_bounds__(256, kCorrWaves<K>) void bm_corr_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
   __shared__ __align__(16) unsigned char smem[CorrSmem<K, TPW, SPLIT>::bytes];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
     corr_body<K, TPW, SPLIT>(smem, use_pilot ? r.pilot : r.noisy, r.norm, r.idx, r.H, r.W, R, item);
