@@ -41,10 +41,10 @@ def algorithmic_work(H, W, search, k1, k2):
         "bm": ("alu", BM_FLOP_PER_PAIR * H * W * (S2 - 1), "FLOP"),
         # pixels in; one float64 table entry out per bordered position
         "bm_norm": ("hbm", H * W * 2 + (H + 64) * (W + 64) * 8, "B"),
-        # the bior launch and the first of the two DCT launches clear the
-        # weights and numerator sums
+        # the bior launch and the DCT launch (both stage-2 stacks, of the
+        # noisy image and of the pilot) clear the weights and numerator sums
         "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes + num_bytes, "B"),
-        "stack_dct": ("hbm", H * W * (2 + 256) + (weight_bytes + num_bytes) / 2, "B"),
+        "stack_dct": ("hbm", 2 * H * W * (2 + 256) + weight_bytes + num_bytes, "B"),
         # spectra gathered, ranks read, one 8-byte weight added per block, the
         # image's numerator sums added into once
         "group_ht": ("hbm", nref * (k1 * 256 + 2 * k1 + 8 * k1) + num_bytes, "B"),
@@ -692,7 +692,7 @@ def main():
         s = t["split"]
         return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
     variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
-                "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"] * 2,
+                "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"],
                 "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false, "
                              f"{'false' if tuned.get('stage1_groups', {}).get('shape', '').startswith('one') else 'true'}>"],
                 "group_wiener": [f"group_wiener_kernel<{p.k_wiener}, false>"], "reduce": ["reduce_kernel<false>"] * 2}

@@ -324,7 +324,8 @@ int gbm3d_pilot_adam(gbm3d_ctx* ctx, float* master, float* m, float* v, const fl
  * gbm3d_timing_read synchronises the pending events and returns, for one
  * kernel name ("bm", "bm_norm", "stack_bior", "stack_dct", "group_ht",
  * "group_wiener", "reduce"), the summed elapsed milliseconds and the number of
- * launches since the last reset.  Off by default. */
+ * launches since the last reset ("stack_dct" is one launch that forms both
+ * stage-2 stacks, of the noisy image and of the pilot).  Off by default. */
 int gbm3d_timing_enable(gbm3d_ctx* ctx, int on);
 int gbm3d_timing_read(gbm3d_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 int gbm3d_timing_reset(gbm3d_ctx* ctx);

@@ -469,10 +469,9 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
   r.partials = w.partials;
   r.norm = w.norm;
   CHECK(run_match(ctx, r, R, p.k_wiener, p, 1, st));
-  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 0, 0, 0, st); }),
+  // the noisy and the pilot's DCT stacks in one launch
+  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, -1, -1, 0, st); }),
           "stack launch");
-  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, 1, 1, 0, st); }),
-          "pilot stack launch");
   HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
             return gbm3d::launch_group_wiener(r, nullptr, R, p.k_wiener, 0, st);
           }),
@@ -677,10 +676,8 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
     const WorkList sk = worklist(ctx, plan, n, kStack2);
     const WorkList gr = worklist(ctx, plan, n, kGroup2), rd = worklist(ctx, plan, n, kReduce2);
     CHECK(launch_batch_match(ctx, nm, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
-    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 0, 0, kFullGrid, st); }),
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, -1, -1, kFullGrid, st); }),
             "batch stack");
-    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, 1, 1, kFullGrid, st); }),
-            "batch pilot stack");
     HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
               return gbm3d::launch_group_wiener(none, &gr, R, p.k_wiener, kFullGrid, st);
             }),

@@ -40,7 +40,10 @@ long corr_tiles(int H, int W);
 int corr_auto_split(long tiles);
 
 // 2-D transform (kind 0 = bior1.5 Mallat, 1 = DCT) of every block of noisy
-// (src_sel 0) or pilot (1) into stack_a (dst_sel 0) or stack_b (1), [H*W][64].
+// (src_sel 0) or pilot (1) into stack_a (dst_sel 0) or stack_b (1), [H*W][64];
+// src_sel = dst_sel = -1: noisy -> stack_a and pilot -> stack_b in one launch.
+// The launch into stack_a clears the aggregation sums of rec.partials (when
+// set).
 hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src_sel, int dst_sel, int grid_cap,
                         hipStream_t st);
 int stack_items_for(int H, int W);

@@ -126,14 +126,17 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
   __syncthreads();  // the pixel tile and the staging area are reused
 }
 
-// src_sel: 0 = noisy, 1 = pilot; dst_sel: 0 = stack_a, 1 = stack_b
+// src_sel: 0 = noisy, 1 = pilot; dst_sel: 0 = stack_a, 1 = stack_b; both
+// negative: blockIdx.y selects (noisy -> stack_a, pilot -> stack_b)
 template <int KIND, bool BATCH>
 __global__ __launch_bounds__(kStackThreads) void stack_kernel(ImgRec one, WorkList wl, int src_sel, int dst_sel) {
   __shared__ float pix[kPixRows][kPixCols + 1];
   __shared__ float stage[kRowsPerWg][kHalf * kStagePitch];
+  const int src = src_sel < 0 ? static_cast<int>(blockIdx.y) : src_sel;
+  const int dst = dst_sel < 0 ? static_cast<int>(blockIdx.y) : dst_sel;
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    stack_body<KIND>(pix, stage, src_sel ? r.pilot : r.noisy, dst_sel ? r.stack_b : r.stack_a,
-                     dst_sel ? nullptr : r.partials, r.H, r.W, item);
+    stack_body<KIND>(pix, stage, src ? r.pilot : r.noisy, dst ? r.stack_b : r.stack_a, dst ? nullptr : r.partials,
+                     r.H, r.W, item);
   });
 }
 
@@ -143,19 +146,21 @@ int stack_items_for(int H, int W) { return stack_items(H, W); }
 
 hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src_sel, int dst_sel, int grid_cap,
                         hipStream_t st) {
+  if ((src_sel < 0) != (dst_sel < 0)) return hipErrorInvalidValue;
+  const unsigned planes = src_sel < 0 ? 2u : 1u;  // both stacks in one launch
   if (!wl) {
-    const int items = stack_items(one.H, one.W);
+    const dim3 grid(static_cast<unsigned>(stack_items(one.H, one.W)), planes);
     if (kind == 0)
-      hipLaunchKernelGGL((stack_kernel<0, false>), dim3(items), dim3(kStackThreads), 0, st, one, WorkList{}, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<0, false>), grid, dim3(kStackThreads), 0, st, one, WorkList{}, src_sel, dst_sel);
     else
-      hipLaunchKernelGGL((stack_kernel<1, false>), dim3(items), dim3(kStackThreads), 0, st, one, WorkList{}, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<1, false>), grid, dim3(kStackThreads), 0, st, one, WorkList{}, src_sel, dst_sel);
   } else {
     if (wl->total <= 0) return hipSuccess;
-    const int grid = std::min(wl->total, grid_cap);
+    const dim3 grid(static_cast<unsigned>(std::min(wl->total, grid_cap)), planes);
     if (kind == 0)
-      hipLaunchKernelGGL((stack_kernel<0, true>), dim3(grid), dim3(kStackThreads), 0, st, one, *wl, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<0, true>), grid, dim3(kStackThreads), 0, st, one, *wl, src_sel, dst_sel);
     else
-      hipLaunchKernelGGL((stack_kernel<1, true>), dim3(grid), dim3(kStackThreads), 0, st, one, *wl, src_sel, dst_sel);
+      hipLaunchKernelGGL((stack_kernel<1, true>), grid, dim3(kStackThreads), 0, st, one, *wl, src_sel, dst_sel);
   }
   return hipGetLastError();
 }
