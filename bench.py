@@ -26,25 +26,28 @@ PEAKS = {"hbm": (HBM_PEAK_GBS, "GB/s", 1e9), "alu": (FP64_VALU_PEAK_TFLOPS, "TFL
          "mfma": (INT8_MFMA_PEAK_TOPS, "TOP/s", 1e12), "mfma_bf16": (BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", 1e12)}
 
 
-def algorithmic_work(H, W, search, k1, k2):
+def algorithmic_work(H, W, search, k1, k2, norm_in_stacks=False):
     """Per-launch algorithmic work of each kernel: bytes for the HBM-bound
     ones; for block matching (either kernel) 5 FLOP of exact arithmetic per
     (pixel, displacement) pair -- one difference, one fused square-accumulate
     (2 FLOP) and the two running-sum additions of the box filter -- on the
-    fp64 vector ALU."""
+    fp64 vector ALU.  norm_in_stacks: the correlation matcher's norm table is
+    formed in each stage's stack launch (no norm launch of its own)."""
     from paper_2103_10765_amd import gbm3d
     nref = gbm3d.n_refs(H, W, 3)
     weight_bytes = H * W * 8  # 64-bit block-start weights
     num_bytes = H * W * 8  # 64-bit numerator sums
     S2 = search * search
+    norm_bytes = H * W * 2 + (H + 64) * (W + 64) * 8  # pixels in, bordered table out
+    in_stack = norm_bytes if norm_in_stacks else 0
     return {
         "bm": ("alu", BM_FLOP_PER_PAIR * H * W * (S2 - 1), "FLOP"),
         # pixels in; one float64 table entry out per bordered position
-        "bm_norm": ("hbm", H * W * 2 + (H + 64) * (W + 64) * 8, "B"),
+        "bm_norm": ("hbm", norm_bytes, "B"),
         # the bior launch and the DCT launch (both stage-2 stacks, of the
         # noisy image and of the pilot) clear the weights and numerator sums
-        "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes + num_bytes, "B"),
-        "stack_dct": ("hbm", 2 * H * W * (2 + 256) + weight_bytes + num_bytes, "B"),
+        "stack_bior": ("hbm", H * W * (2 + 256) + weight_bytes + num_bytes + in_stack, "B"),
+        "stack_dct": ("hbm", 2 * H * W * (2 + 256) + weight_bytes + num_bytes + in_stack, "B"),
         # spectra gathered, ranks read, one 8-byte weight added per block, the
         # image's numerator sums added into once
         "group_ht": ("hbm", nref * (k1 * 256 + 2 * k1 + 8 * k1) + num_bytes, "B"),
@@ -70,8 +73,8 @@ def bm_int8_view(H, W, search, avg_us):
 TRAFFIC_FILES = {512: os.path.join(ROOT, "profiles", "hbm_traffic_denoise_512.txt"),
                  4096: os.path.join(ROOT, "profiles", "hbm_traffic_denoise_4096.txt")}
 KERNEL_SOURCES = {
-    "bm": ["bm.hip", "bm_corr.hip", "common.h", "topk.h"], "bm_norm": ["bm_corr.hip", "common.h"],
-    "stack_bior": ["stack.hip", "common.h"], "stack_dct": ["stack.hip", "common.h"],
+    "bm": ["bm.hip", "bm_corr.hip", "common.h", "norm.h", "topk.h"], "bm_norm": ["bm_corr.hip", "common.h", "norm.h"],
+    "stack_bior": ["stack.hip", "common.h", "norm.h"], "stack_dct": ["stack.hip", "common.h", "norm.h"],
     "group_ht": ["group.hip", "common.h"], "group_wiener": ["group.hip", "common.h"], "reduce": ["group.hip", "common.h"],
 }
 
@@ -541,7 +544,9 @@ def per_kernel(ctx, Zt, sigma, p, steps, variants=None):
         if n:
             kernels[name] = {"avg_us": 1e3 * tot / n, "launches_per_step": n / steps, "ms_per_step": tot / steps}
     ctx.timing(False)
-    work = algorithmic_work(H, W, p.search, p.k_ht, p.k_wiener)
+    # no norm launch of its own: the stack launches formed the norm tables
+    work = algorithmic_work(H, W, p.search, p.k_ht, p.k_wiener,
+                            norm_in_stacks="bm_norm" not in kernels and "bm" in kernels)
     for name, k in kernels.items():
         bound, amount, unit = work[name]
         peak, punit, scale = PEAKS[bound]
@@ -691,8 +696,11 @@ def main():
             return None
         s = t["split"]
         return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
+    def stack_variant(K, kind):  # the stack launch carries the norm table when the correlation kernel matches
+        t = tuned.get(f"K{K}")
+        return f"stack{'_norm' if t and t['method'] == 'corr' else ''}_kernel<{kind}, false>"
     variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
-                "stack_bior": ["stack_kernel<0, false>"], "stack_dct": ["stack_kernel<1, false>"],
+                "stack_bior": [stack_variant(p.k_ht, 0)], "stack_dct": [stack_variant(p.k_wiener, 1)],
                 "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false, "
                              f"{'false' if tuned.get('stage1_groups', {}).get('shape', '').startswith('one') else 'true'}>"],
                 "group_wiener": [f"group_wiener_kernel<{p.k_wiener}, false>"], "reduce": ["reduce_kernel<false>"] * 2}

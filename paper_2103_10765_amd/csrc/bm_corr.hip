@@ -31,13 +31,13 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "norm.h"
 #include "topk.h"
 
 namespace gbm3d {
 
 namespace {
 
-constexpr int kNormPad = 32;                       // periodic border of the norm table
 constexpr int kPitch = 96;                         // bytes per LDS plane row
 constexpr int kMaxNb = (2 * kMaxR + 10 + 3) / 4;   // candidate blocks per axis
 constexpr int kRows = 4 * kMaxNb + 7;              // LDS plane rows
@@ -49,7 +49,6 @@ template <int K>
 constexpr int kBuf = K >= 32 ? 16 : K >= 16 ? 12 : 8;
 template <int K>
 constexpr int kFlushAt = kBuf<K> - 4;  // a block appends at most 4
-constexpr int kZShift = 32896;
 constexpr double kInf = __builtin_huge_val();
 
 static_assert(12 * 3 + 4 * kMaxNb + 12 <= kPitch, "plane rows too short");
@@ -81,73 +80,12 @@ constexpr BlockOrder make_block_order() {
 
 __constant__ BlockOrder kOrder = make_block_order();
 
-__device__ __forceinline__ int norm_pitch(int W) { return W + 2 * kNormPad; }
-
-// ---------------------------------------------------------------------------
-// Norm table: T[ey][ex] = 2048 N + ((ex + R) mod 4), N the sum over the
-// 8 x 8 block at image position ((ey - pad) mod H, (ex - pad) mod W) of
-// (Z - 32896)^2, for ey < H + 2 pad, ex < W + 2 pad (exact: 2048 N < 2^50).
-// The matching kernel's candidate blocks start at table columns
-// congruent to -R mod 4, so (ex + R) mod 4 is the candidate's column in its
-// block, the part of its rank that varies inside a block: the key's
-// candidate term is one load.  Items are 8 x 64 output tiles (small tiles:
-// many workgroups in flight for what is a short, latency-bound pass).
-// ---------------------------------------------------------------------------
-constexpr int kNTy = 8, kNTx = 64;
-
-__host__ __device__ constexpr int norm_items(int H, int W) {
-  return ((H + 2 * kNormPad + kNTy - 1) / kNTy) * ((W + 2 * kNormPad + kNTx - 1) / kNTx);
-}
-
-__device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img_, double* __restrict__ norm_, int H, int W,
-                                          int R, int item, int* zt, double* hs) {
-  const auto img = to_global(img_);
-  const auto norm = to_global(norm_);
-  const int He = H + 2 * kNormPad, We = norm_pitch(W);
-  const int tiles_x = (We + kNTx - 1) / kNTx;
-  const int ty0 = (item / tiles_x) * kNTy, tx0 = (item % tiles_x) * kNTx;
-  constexpr int ZR = kNTy + 7, ZC = kNTx + 7;
-  // table rows and columns lie within one period of the image when it is at
-  // least as large as the border plus a tile; else the general modulo
-  const bool near = H >= kNormPad + kNTy + 7 && W >= kNormPad + kNTx + 7;
-  for (int i = threadIdx.x; i < ZR * ZC; i += blockDim.x) {
-    const int r = i / ZC, c = i - r * ZC;
-    int y = ty0 + r - kNormPad, x = tx0 + c - kNormPad;
-    if (near) {
-      y += y < 0 ? H : (y >= H ? -H : 0);
-      x += x < 0 ? W : (x >= W ? -W : 0);
-    } else {
-      y = pmod(y, H);
-      x = pmod(x, W);
-    }
-    zt[i] = static_cast<int>(img[static_cast<size_t>(y) * W + x]) - kZShift;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < ZR * kNTx; i += blockDim.x) {
-    const int r = i / kNTx, c = i - r * kNTx;
-    double h = 0.0;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int v = zt[r * ZC + c + b];
-      h += static_cast<double>(v * v);  // |v| <= 32896: v * v < 2^31
-    }
-    hs[i] = h;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kNTy * kNTx; i += blockDim.x) {
-    const int r = i / kNTx, c = i - r * kNTx;
-    double s = 0.0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) s += hs[(r + a) * kNTx + c];
-    if (ty0 + r < He && tx0 + c < We)
-      norm[static_cast<size_t>(ty0 + r) * We + tx0 + c] = fma(s, 2048.0, static_cast<double>((tx0 + c + R) & 3));
-  }
-}
 
 template <bool BATCH>
 __global__ __launch_bounds__(256) void bm_norm_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
-  __shared__ int zt[(kNTy + 7) * (kNTx + 7)];
-  __shared__ double hs[(kNTy + 7) * kNTx];
+  __shared__ __align__(16) unsigned char smem[NormSmem::bytes];
+  int* zt = reinterpret_cast<int*>(smem);
+  double* hs = reinterpret_cast<double*>(smem + NormSmem::zt_bytes);
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
     norm_body(use_pilot ? r.pilot : r.noisy, r.norm, r.H, r.W, R, item, zt, hs);
   });

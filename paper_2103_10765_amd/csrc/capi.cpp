@@ -361,16 +361,25 @@ int choose_shape(const gbm3d_ctx* ctx, const gbm3d_params& p, long tiles) {
   return shape;
 }
 
+// The correlation kernel's norm table: r.norm when set, else the context's.
+int bind_norm(gbm3d_ctx* ctx, ImgRec& r) {
+  if (!r.norm) {
+    CHECK(ensure(ctx, ctx->norm, gbm3d::norm_bytes(r.H, r.W), "norm table"));
+    r.norm = static_cast<double*>(ctx->norm.p);
+  }
+  return GBM3D_OK;
+}
+
 // Block matching of one image (r.noisy, or r.pilot with use_pilot) into r.idx.
-// The correlation kernel's norm table is r.norm when set, else the context's.
-int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const BmChoice& c, int use_pilot, hipStream_t st) {
+// norm_ready: the correlation kernel's norm table is already in r.norm (formed
+// by the stack launch before it).
+int run_match(gbm3d_ctx* ctx, ImgRec& r, int R, int K, const BmChoice& c, int use_pilot, hipStream_t st,
+              bool norm_ready = false) {
   if (c.method == GBM3D_BM_CORR) {
-    if (!r.norm) {
-      CHECK(ensure(ctx, ctx->norm, gbm3d::norm_bytes(r.H, r.W), "norm table"));
-      r.norm = static_cast<double*>(ctx->norm.p);
-    }
-    HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(r, nullptr, R, use_pilot, 0, st); }),
-            "norm table launch");
+    CHECK(bind_norm(ctx, r));
+    if (!norm_ready)
+      HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(r, nullptr, R, use_pilot, 0, st); }),
+              "norm table launch");
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] {
               return gbm3d::launch_bm_corr(r, nullptr, R, K, c.split, use_pilot, 0, st);
             }),
@@ -426,12 +435,23 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
   r.partials = w.partials;
   r.norm = w.norm;
   r.eps = tv_eps(p, sigma);
-  CHECK(run_match(ctx, r, R, p.k_ht, p, 0, st));
-  if (recompute)
+  const BmChoice c = choose_bm(ctx, p, gbm3d::corr_tiles(H, W), p.k_ht);
+  if (recompute) {
+    CHECK(run_match(ctx, r, R, p.k_ht, c, 0, st));
     HIP_TRY(ctx, gbm3d::launch_clear_weights(r, st), "weight clearing launch");
-  else
+  } else if (c.method == GBM3D_BM_CORR) {
+    // the stack and the matcher's norm table in one launch, then the matching
+    CHECK(bind_norm(ctx, r));
+    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] {
+              return gbm3d::launch_stack_norm(r, 0, 0, 0, R, 0, st);
+            }),
+            "stack launch");
+    CHECK(run_match(ctx, r, R, p.k_ht, c, 0, st, true));
+  } else {
+    CHECK(run_match(ctx, r, R, p.k_ht, c, 0, st));
     HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(r, nullptr, 0, 0, 0, 0, st); }),
             "stack launch");
+  }
   HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
             return gbm3d::launch_group_ht(r, nullptr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, recompute,
                                           choose_shape(ctx, p, gbm3d::corr_tiles(H, W)), 0, st);
@@ -468,10 +488,21 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
   r.idx = w.idx;
   r.partials = w.partials;
   r.norm = w.norm;
-  CHECK(run_match(ctx, r, R, p.k_wiener, p, 1, st));
-  // the noisy and the pilot's DCT stacks in one launch
-  HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, -1, -1, 0, st); }),
-          "stack launch");
+  // the noisy and the pilot's DCT stacks in one launch, with the matcher's
+  // norm table of the pilot when the correlation kernel matches
+  const BmChoice c = choose_bm(ctx, p, gbm3d::corr_tiles(H, W), p.k_wiener);
+  if (c.method == GBM3D_BM_CORR) {
+    CHECK(bind_norm(ctx, r));
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] {
+              return gbm3d::launch_stack_norm(r, 1, -1, -1, R, 1, st);
+            }),
+            "stack launch");
+    CHECK(run_match(ctx, r, R, p.k_wiener, c, 1, st, true));
+  } else {
+    CHECK(run_match(ctx, r, R, p.k_wiener, c, 1, st));
+    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(r, nullptr, 1, -1, -1, 0, st); }),
+            "stack launch");
+  }
   HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
             return gbm3d::launch_group_wiener(r, nullptr, R, p.k_wiener, 0, st);
           }),
@@ -627,10 +658,17 @@ WorkList worklist(const gbm3d_ctx* ctx, const BatchPlan& plan, int n, int phase)
 // Grid cap of the batch launches: none (one workgroup per item).
 constexpr int kFullGrid = 1 << 30;
 
-// Batch matching phase: norm tables first when the correlation kernel runs.
-int launch_batch_match(gbm3d_ctx* ctx, const WorkList& nm, const WorkList& bm, int R, int K, int method, int split,
-                       int use_pilot, hipStream_t st) {
+// Batch matching of a stage, norm tables first when the correlation kernel
+// matches, then its stacks (kind 0: the bior1.5 stack of the noisy images;
+// 1: the DCT stacks of the noisy images and of the pilots).  Unlike a single
+// image, a batch keeps the norm tables in a launch of their own: carried by
+// the stack launch they made the 64-image batch slower (913 vs 940
+// Mpixel/s).
+int launch_batch_prep(gbm3d_ctx* ctx, const WorkList& sk, const WorkList& nm, const WorkList& bm, int R, int K,
+                      int method, int split, int kind, hipStream_t st) {
   const ImgRec none = blank_rec(0, 0, 0.0f);
+  const int use_pilot = kind;
+  const int sel = kind == 0 ? 0 : -1;
   if (method == GBM3D_BM_CORR) {
     HIP_TRY(ctx, timed(ctx, "bm_norm", st, [&] { return gbm3d::launch_bm_norm(none, &nm, R, use_pilot, kFullGrid, st); }),
             "batch norm tables");
@@ -642,6 +680,10 @@ int launch_batch_match(gbm3d_ctx* ctx, const WorkList& nm, const WorkList& bm, i
     HIP_TRY(ctx, timed(ctx, "bm", st, [&] { return gbm3d::launch_bm(none, &bm, R, K, split, use_pilot, kFullGrid, st); }),
             "batch block matching");
   }
+  HIP_TRY(ctx, timed(ctx, kind == 0 ? "stack_bior" : "stack_dct", st, [&] {
+            return gbm3d::launch_stack(none, &sk, kind, sel, sel, kFullGrid, st);
+          }),
+          "batch stacks");
   return GBM3D_OK;
 }
 
@@ -658,9 +700,7 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
     const WorkList nm = worklist(ctx, plan, n, kNorm1), bm = worklist(ctx, plan, n, kBm1);
     const WorkList sk = worklist(ctx, plan, n, kStack1);
     const WorkList gr = worklist(ctx, plan, n, kGroup1), rd = worklist(ctx, plan, n, kReduce1);
-    CHECK(launch_batch_match(ctx, nm, bm, R, p.k_ht, plan.bm_method1, plan.bm_split1, 0, st));
-    HIP_TRY(ctx, timed(ctx, "stack_bior", st, [&] { return gbm3d::launch_stack(none, &sk, 0, 0, 0, kFullGrid, st); }),
-            "batch stack");
+    CHECK(launch_batch_prep(ctx, sk, nm, bm, R, p.k_ht, plan.bm_method1, plan.bm_split1, 0, st));
     HIP_TRY(ctx, timed(ctx, "group_ht", st, [&] {
               return gbm3d::launch_group_ht(none, &gr, R, p.k_ht, p.ht_a, p.ht_b, p.ht_weight, p.keep_dc, 0,
                                             plan.ht_shape, kFullGrid,
@@ -675,9 +715,7 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
     const WorkList nm = worklist(ctx, plan, n, kNorm2), bm = worklist(ctx, plan, n, kBm2);
     const WorkList sk = worklist(ctx, plan, n, kStack2);
     const WorkList gr = worklist(ctx, plan, n, kGroup2), rd = worklist(ctx, plan, n, kReduce2);
-    CHECK(launch_batch_match(ctx, nm, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
-    HIP_TRY(ctx, timed(ctx, "stack_dct", st, [&] { return gbm3d::launch_stack(none, &sk, 1, -1, -1, kFullGrid, st); }),
-            "batch stack");
+    CHECK(launch_batch_prep(ctx, sk, nm, bm, R, p.k_wiener, plan.bm_method2, plan.bm_split2, 1, st));
     HIP_TRY(ctx, timed(ctx, "group_wiener", st, [&] {
               return gbm3d::launch_group_wiener(none, &gr, R, p.k_wiener, kFullGrid, st);
             }),

@@ -47,6 +47,11 @@ int corr_auto_split(long tiles);
 hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src_sel, int dst_sel, int grid_cap,
                         hipStream_t st);
 int stack_items_for(int H, int W);
+// launch_stack of one image and, in the same launch, the correlation
+// matcher's norm table (launch_bm_norm) of noisy (norm_src 0) or pilot (1)
+// into rec.norm.
+hipError_t launch_stack_norm(const ImgRec& one, int kind, int src_sel, int dst_sel, int R, int norm_src,
+                             hipStream_t st);
 
 // bytes of the aggregation buffer (64-bit fixed point) of the group kernels:
 // block-start weights of the image, then its numerator sums (R: unused, the

@@ -11,6 +11,7 @@
 // 16-byte stores (half-size staging keeps four workgroups per CU).
 #include "common.h"
 #include "kernels.h"
+#include "norm.h"
 
 namespace gbm3d {
 
@@ -140,6 +141,40 @@ __global__ __launch_bounds__(kStackThreads) void stack_kernel(ImgRec one, WorkLi
   });
 }
 
+// The stacks of a stage beside the correlation matcher's norm table of the
+// image it matches, in one launch over one image: grid rows y < gridDim.y - 1
+// are stack planes as in stack_kernel, the last row the norm items.  The two
+// passes share nothing but the launch: the short, latency-bound norm pass
+// runs in the gaps of the write-bound stack items instead of as a launch of
+// its own.
+struct StackSmem {
+  static constexpr int pix_bytes = (kPixRows * (kPixCols + 1) * 4 + 15) / 16 * 16;
+  static constexpr int bytes = pix_bytes + kRowsPerWg * kHalf * kStagePitch * 4;
+};
+
+template <int KIND>
+__global__ __launch_bounds__(kStackThreads) void stack_norm_kernel(ImgRec r, int src_sel, int dst_sel, int R,
+                                                                   int norm_src) {
+  constexpr int kBytes = StackSmem::bytes > NormSmem::bytes ? StackSmem::bytes : NormSmem::bytes;
+  __shared__ __align__(16) unsigned char smem[kBytes];
+  static_assert(kStackThreads == 256, "norm items are laid out for 256 threads");
+  const int item = static_cast<int>(blockIdx.x);
+  if (blockIdx.y == gridDim.y - 1) {
+    if (item >= norm_items(r.H, r.W)) return;
+    int* zt = reinterpret_cast<int*>(smem);
+    double* hs = reinterpret_cast<double*>(smem + NormSmem::zt_bytes);
+    norm_body(norm_src ? r.pilot : r.noisy, r.norm, r.H, r.W, R, item, zt, hs);
+    return;
+  }
+  if (item >= stack_items(r.H, r.W)) return;
+  auto pix = reinterpret_cast<float(*)[kPixCols + 1]>(smem);
+  auto stage = reinterpret_cast<float(*)[kHalf * kStagePitch]>(smem + StackSmem::pix_bytes);
+  const int src = src_sel < 0 ? static_cast<int>(blockIdx.y) : src_sel;
+  const int dst = dst_sel < 0 ? static_cast<int>(blockIdx.y) : dst_sel;
+  stack_body<KIND>(pix, stage, src ? r.pilot : r.noisy, dst ? r.stack_b : r.stack_a, dst ? nullptr : r.partials,
+                   r.H, r.W, item);
+}
+
 }  // namespace
 
 int stack_items_for(int H, int W) { return stack_items(H, W); }
@@ -162,6 +197,18 @@ hipError_t launch_stack(const ImgRec& one, const WorkList* wl, int kind, int src
     else
       hipLaunchKernelGGL((stack_kernel<1, true>), grid, dim3(kStackThreads), 0, st, one, *wl, src_sel, dst_sel);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_stack_norm(const ImgRec& one, int kind, int src_sel, int dst_sel, int R, int norm_src,
+                             hipStream_t st) {
+  if ((src_sel < 0) != (dst_sel < 0)) return hipErrorInvalidValue;
+  const unsigned rows = (src_sel < 0 ? 2u : 1u) + 1u;  // stack planes, then the norm items
+  const dim3 grid(static_cast<unsigned>(std::max(stack_items(one.H, one.W), norm_items(one.H, one.W))), rows);
+  if (kind == 0)
+    hipLaunchKernelGGL(stack_norm_kernel<0>, grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R, norm_src);
+  else
+    hipLaunchKernelGGL(stack_norm_kernel<1>, grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R, norm_src);
   return hipGetLastError();
 }
 
