@@ -17,7 +17,8 @@
 // gets its exact key 2048 (N(a) + N(b) - 512 (256 Phh + Phl + Plh) - 2 Pll) +
 // rank in float64 (all terms integers below 2^50) with no data-dependent
 // branch; keys below the lane's bound go to its candidate buffer.  Norms come
-// from a table written beforehand by bm_norm_kernel (float64, exact).
+// from a table written beforehand (norm.h; float64, exact) by bm_norm_kernel
+// or, for a single image, by the stack launch of the same stage.
 //
 // Every lane keeps the K-1 best keys of its reference among its quarter of
 // the candidates; the four quarters, and the SPLIT waves that share a tile,
