@@ -237,8 +237,9 @@ int gbm3d_global_match(gbm3d_ctx* ctx, const uint16_t* img, int H, int W,
  * device it runs on until the process ends.  The call makes no hipMalloc,
  * hipFree or other allocating call and records no timing events.  It
  * returns GBM3D_EINVAL, launching nothing, when the image needs more scratch
- * than that (with the default parameters 512 x 512 fits; the error text
- * gives the bytes needed).  Every call on a device shares that device's
+ * than that (with the default parameters square images up to 551 x 551
+ * fit, when basic_out and q_out are NULL; the error text gives the bytes
+ * needed).  Every call on a device shares that device's
  * array and leaves its contents behind (the kernels clear what must start
  * at zero), so calls that overlap on one device — on two streams, from two
  * contexts or two threads — race and give undefined results; serialise them.
