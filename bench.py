@@ -698,7 +698,7 @@ def main():
         return f"{'bm_corr_kernel' if t['method'] == 'corr' else 'bm_kernel'}<{K}, {4 // s}, {s}, false>"
     def stack_variant(K, kind):  # the stack launch carries the norm table when the correlation kernel matches
         t = tuned.get(f"K{K}")
-        return f"stack{'_norm' if t and t['method'] == 'corr' else ''}_kernel<{kind}, false>"
+        return f"stack_norm_kernel<{kind}>" if t and t["method"] == "corr" else f"stack_kernel<{kind}, false>"
     variants = {"bm": [bm_variant(p.k_ht), bm_variant(p.k_wiener)], "bm_norm": ["bm_norm_kernel<false>"] * 2,
                 "stack_bior": [stack_variant(p.k_ht, 0)], "stack_dct": [stack_variant(p.k_wiener, 1)],
                 "group_ht": [f"group_ht_kernel<{p.k_ht}, false, false, "

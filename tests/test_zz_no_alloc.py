@@ -105,3 +105,24 @@ def test_noalloc_rejects_images_beyond_the_scratch(torch, G):
         assert bool((out == -7.0).all()), "a rejected call wrote its output"
     finally:
         ctx.close()
+
+
+def test_noalloc_size_limit(torch, G):
+    """With the default parameters the largest square image whose buffers
+    (basic estimate and pilot included) fit the scratch is 551 x 551: it runs
+    and equals gbm3d_denoise; 552 x 552 is refused before any launch."""
+    ref_ctx = G.Context(0)
+    na_ctx = G.Context(0)
+    try:
+        _run_both(torch, G, ref_ctx, na_ctx, 551, 551, 25.0 / 255.0, 5, G.default_params())
+        H = W = 552
+        Zt = torch.zeros((H, W), dtype=torch.uint16, device="cuda")
+        out = torch.full((H, W), -7.0, dtype=torch.float32, device="cuda")
+        with pytest.raises(G.GBM3DError) as e:
+            na_ctx.denoise_noalloc(Zt, 0.1, out=out)
+        assert e.value.status == G.EINVAL
+        torch.cuda.synchronize()
+        assert bool((out == -7.0).all()), "a rejected call wrote its output"
+    finally:
+        ref_ctx.close()
+        na_ctx.close()
