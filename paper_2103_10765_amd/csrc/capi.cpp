@@ -421,7 +421,7 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
     // the recompute form transforms each matched block from its pixels: no stack
     if (!recompute) CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
     CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_ht * sizeof(int16_t), "idx"));
-    CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
+    CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W), "partials"));
     w.stack_a = static_cast<float*>(ctx->stack_a.p);
     w.idx = static_cast<int16_t*>(ctx->idx.p);
     w.partials = static_cast<unsigned long long*>(ctx->partials.p);
@@ -457,7 +457,7 @@ int run_basic(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, float sigma, 
                                           choose_shape(ctx, p, gbm3d::corr_tiles(H, W)), 0, st);
           }),
           "hard-threshold group launch");
-  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, R, 0, 0, st); }),
+  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, 0, 0, st); }),
           "aggregation launch");
   return GBM3D_OK;
 }
@@ -473,7 +473,7 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
     CHECK(ensure(ctx, ctx->stack_a, stack_bytes(H, W), "stack"));
     CHECK(ensure(ctx, ctx->stack_b, stack_bytes(H, W), "pilot stack"));
     CHECK(ensure(ctx, ctx->idx, n_refs(H, W) * p.k_wiener * sizeof(int16_t), "idx"));
-    CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W, R), "partials"));
+    CHECK(ensure(ctx, ctx->partials, gbm3d::partials_bytes(H, W), "partials"));
     w.stack_a = static_cast<float*>(ctx->stack_a.p);
     w.stack_b = static_cast<float*>(ctx->stack_b.p);
     w.idx = static_cast<int16_t*>(ctx->idx.p);
@@ -507,7 +507,7 @@ int run_wiener(gbm3d_ctx* ctx, const uint16_t* noisy, const uint16_t* pilot, int
             return gbm3d::launch_group_wiener(r, nullptr, R, p.k_wiener, 0, st);
           }),
           "Wiener group launch");
-  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, R, 1, 0, st); }),
+  HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(r, nullptr, 1, 0, st); }),
           "aggregation launch");
   return GBM3D_OK;
 }
@@ -566,7 +566,7 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
     total += align256(stack_bytes(H, W));                                   // stack_a
     if (!basic_only) total += align256(stack_bytes(H, W));                  // stack_b
     total += align256(n_refs(H, W) * kmax * sizeof(int16_t));               // idx
-    total += align256(gbm3d::partials_bytes(H, W, R));                      // partials
+    total += align256(gbm3d::partials_bytes(H, W));                      // partials
     if (s1 && !basic_only) total += align256(static_cast<size_t>(H) * W * (sizeof(float) + sizeof(uint16_t)));
   }
   CHECK(ensure(ctx, ctx->batch_ws, total, "batch workspace"));
@@ -591,7 +591,7 @@ int plan_batch(gbm3d_ctx* ctx, const gbm3d_image* imgs, int n, const gbm3d_param
     r.idx = reinterpret_cast<int16_t*>(c);
     c += align256(n_refs(H, W) * kmax * sizeof(int16_t));
     r.partials = reinterpret_cast<unsigned long long*>(c);
-    c += align256(gbm3d::partials_bytes(H, W, R));
+    c += align256(gbm3d::partials_bytes(H, W));
     r.noisy = im.noisy;
     r.eps = tv_eps(p, im.sigma);
     if (basic_only) {
@@ -707,7 +707,7 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
                                             st);
             }),
             "batch hard-threshold groups");
-    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 0, kFullGrid, st); }),
+    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, 0, kFullGrid, st); }),
             "batch aggregation");
   }
   if (plan.any_stage2) {
@@ -720,7 +720,7 @@ int launch_batch(gbm3d_ctx* ctx, const BatchPlan& plan, int n, const gbm3d_param
               return gbm3d::launch_group_wiener(none, &gr, R, p.k_wiener, kFullGrid, st);
             }),
             "batch Wiener groups");
-    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, R, 1, kFullGrid, st); }),
+    HIP_TRY(ctx, timed(ctx, "reduce", st, [&] { return gbm3d::launch_reduce(none, &rd, 1, kFullGrid, st); }),
             "batch aggregation");
   }
   return GBM3D_OK;
@@ -1246,7 +1246,6 @@ int gbm3d_denoise_noalloc(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, f
   CHECK(check_ht(ctx, p));
   // slices of the scratch: the same buffers gbm3d_denoise takes from the
   // context's workspace
-  const int R = p.search / 2;
   const size_t hw = static_cast<size_t>(H) * W;
   size_t off = 0;
   auto take = [&off](size_t bytes) {
@@ -1258,7 +1257,7 @@ int gbm3d_denoise_noalloc(gbm3d_ctx* ctx, const uint16_t* noisy, int H, int W, f
   const size_t o_sa = take(stack_bytes(H, W));
   const size_t o_sb = take(stack_bytes(H, W));
   const size_t o_idx = take(n_refs(H, W) * std::max(p.k_ht, p.k_wiener) * sizeof(int16_t));
-  const size_t o_part = take(gbm3d::partials_bytes(H, W, R));
+  const size_t o_part = take(gbm3d::partials_bytes(H, W));
   const size_t o_basic = basic_out ? 0 : take(hw * sizeof(float));
   const size_t o_q = q_out ? 0 : take(hw * sizeof(uint16_t));
   if (off > static_cast<size_t>(GBM3D_NOALLOC_SCRATCH_BYTES))

@@ -630,10 +630,7 @@ __global__ void quantize_kernel(const float* __restrict__ in, uint16_t* __restri
 
 }  // namespace
 
-size_t partials_bytes(int H, int W, int R) {
-  (void)R;
-  return aggregation_entries(H, W) * sizeof(acc_t);
-}
+size_t partials_bytes(int H, int W) { return aggregation_entries(H, W) * sizeof(acc_t); }
 
 int group_items_for(int H, int W, int R) {
   const GroupArgs g = make_args(H, W, R);
@@ -715,7 +712,7 @@ hipError_t launch_group_wiener(const ImgRec& one, const WorkList* wl, int R, int
   }
 }
 
-hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int R, int final_stage, int grid_cap,
+hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int final_stage, int grid_cap,
                          hipStream_t st) {
   if (!wl) {
     hipLaunchKernelGGL((reduce_kernel<false>), dim3(reduce_items(one.H, one.W)), dim3(kReduceThreads), 0, st, one,

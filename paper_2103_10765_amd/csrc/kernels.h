@@ -54,9 +54,8 @@ hipError_t launch_stack_norm(const ImgRec& one, int kind, int src_sel, int dst_s
                              hipStream_t st);
 
 // bytes of the aggregation buffer (64-bit fixed point) of the group kernels:
-// block-start weights of the image, then its numerator sums (R: unused, the
-// size does not depend on the search window)
-size_t partials_bytes(int H, int W, int R);
+// block-start weights of the image, then its numerator sums
+size_t partials_bytes(int H, int W);
 int group_items_for(int H, int W, int R);
 
 // stage-1 groups: stack_a (bior) + idx -> partials (weights scaled by rec.eps);
@@ -77,7 +76,7 @@ hipError_t launch_group_wiener(const ImgRec& one, const WorkList* wl, int R, int
 
 // numerator sum / 8 x 8 box sum of the block-start weights into rec.basic
 // (+ its quantisation into rec.q when set) or, with final_stage, rec.out
-hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int R, int final_stage, int grid_cap,
+hipError_t launch_reduce(const ImgRec& one, const WorkList* wl, int final_stage, int grid_cap,
                          hipStream_t st);
 int reduce_items_for(int H, int W);
 
