@@ -382,12 +382,17 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       b1 = b2;
       b2 = order(j + 3 * SPLIT);
     };
+    // whole pairs of steps in the loop and an odd last step after it: every
+    // path into a step then comes from the step of the other register set,
+    // whose loads are the younger ones the wait may leave in flight
+    const int steps = jb < nblk ? (nblk - jb + SPLIT - 1) / SPLIT : 0;
+    int j = jb;
 #pragma unroll 1
-    for (int j = jb; j < nblk; j += 2 * SPLIT) {
+    for (int s2 = 0; s2 + 1 < steps; s2 += 2, j += 2 * SPLIT) {
       step(j, nv0, p0);
-      if (j + SPLIT >= nblk) break;
       step(j + SPLIT, nv1, p1);
     }
+    if (steps & 1) step(j, nv0, p0);
   }
   if (wave_any(cnt > 0)) flush();
 
