@@ -175,26 +175,46 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   // y0 < H and x0 < W: rows and columns wrap at most once when the image
   // is at least as tall as the region and as wide as a plane row
   const bool near = H >= rows && W >= kPitch;
-  for (int i = threadIdx.x; i < rows * (kPitch / 4); i += blockDim.x) {
-    const int r = i / (kPitch / 4), c = (i - r * (kPitch / 4)) * 4;
-    int y = y0 + r, xb = x0 + c;
-    if (near) {
-      y += y < 0 ? H : (y >= H ? -H : 0);
-      xb += xb < 0 ? W : (xb >= W ? -W : 0);
-    } else {
-      y = pmod(y, H);
-      xb = pmod(xb, W);
-    }
-    unsigned wh = 0, wl = 0;
+  // every thread's pixel loads are issued before the first is used: one
+  // memory round trip for the whole fill instead of one per item
+  constexpr int kFillThreads = 256;
+  constexpr int kFillIter = (kRows * (kPitch / 4) + kFillThreads - 1) / kFillThreads;
+  const int n_fill = rows * (kPitch / 4);
+  unsigned zv[kFillIter][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int x = xb + j < W ? xb + j : xb + j - W;  // W >= 8 > j
-      const unsigned z = img[static_cast<size_t>(y) * W + x];
-      wh |= ((z >> 8) ^ 0x80u) << (8 * j);
-      wl |= ((z & 0xFFu) ^ 0x80u) << (8 * j);
+  for (int it = 0; it < kFillIter; ++it) {
+    const int i = static_cast<int>(threadIdx.x) + it * kFillThreads;
+    if (i < n_fill) {
+      const int r = i / (kPitch / 4), c = (i - r * (kPitch / 4)) * 4;
+      int y = y0 + r, xb = x0 + c;
+      if (near) {
+        y += y < 0 ? H : (y >= H ? -H : 0);
+        xb += xb < 0 ? W : (xb >= W ? -W : 0);
+      } else {
+        y = pmod(y, H);
+        xb = pmod(xb, W);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int x = xb + j < W ? xb + j : xb + j - W;  // W >= 8 > j
+        zv[it][j] = img[static_cast<size_t>(y) * W + x];
+      }
     }
-    reinterpret_cast<unsigned*>(hp + r * kPitch)[c / 4] = wh;
-    reinterpret_cast<unsigned*>(lp + r * kPitch)[c / 4] = wl;
+  }
+#pragma unroll
+  for (int it = 0; it < kFillIter; ++it) {
+    const int i = static_cast<int>(threadIdx.x) + it * kFillThreads;
+    if (i < n_fill) {
+      const int r = i / (kPitch / 4), c = (i - r * (kPitch / 4)) * 4;
+      unsigned wh = 0, wl = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        wh |= ((zv[it][j] >> 8) ^ 0x80u) << (8 * j);
+        wl |= ((zv[it][j] & 0xFFu) ^ 0x80u) << (8 * j);
+      }
+      reinterpret_cast<unsigned*>(hp + r * kPitch)[c / 4] = wh;
+      reinterpret_cast<unsigned*>(lp + r * kPitch)[c / 4] = wl;
+    }
   }
   if constexpr (SPLIT > 1) {
     bound[threadIdx.x] = __double_as_longlong(kInf);
