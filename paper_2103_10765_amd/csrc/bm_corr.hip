@@ -175,6 +175,12 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   // y0 < H and x0 < W: rows and columns wrap at most once when the image
   // is at least as tall as the region and as wide as a plane row
   const bool near = H >= rows && W >= kPitch;
+  // the reference's norm-table entry, loaded ahead of the fill (from an
+  // in-bounds column also for a tile right of the last reference column,
+  // whose value is not used)
+  const int We = norm_pitch(W);
+  const int cr = kStep * (qt + v) + kNormPad;
+  const double nref = norm[static_cast<size_t>(kStep * (p0 + u) + kNormPad) * We + min(cr, We - 1)];
   // every thread's pixel loads are issued before the first is used: one
   // memory round trip for the whole fill instead of one per item
   constexpr int kFillThreads = 256;
@@ -225,13 +231,9 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   // this lane's reference (p0 + u, qt + v): operand rows 2g, 2g + 1, and norm
   i32x4 rh, rl;
   load_operand(hp, lp, R + 3 * u, R + 12 * t + 3 * v, g, rh, rl);
-  const int We = norm_pitch(W);
   // 2048 N of the reference: its table entry less the column term (a tile
   // right of the last reference column only takes part in the merges)
-  const int cr = kStep * (qt + v) + kNormPad;
-  const double nr2048 =
-      qt < nRx ? norm[static_cast<size_t>(kStep * (p0 + u) + kNormPad) * We + cr] - static_cast<double>((cr + R) & 3)
-               : 0.0;
+  const double nr2048 = qt < nRx ? nref - static_cast<double>((cr + R) & 3) : 0.0;
   // table entries of this lane's result candidates: block (br, bc) row g, columns 0..3
   const auto ncand = norm + static_cast<size_t>(y0 + g + kNormPad) * We + (x0 + 12 * t + kNormPad);
 
