@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void bm_norm_kernel(ImgRec one, WorkList wl, i
   int* zt = reinterpret_cast<int*>(smem);
   double* hs = reinterpret_cast<double*>(smem + NormSmem::zt_bytes);
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    norm_body(use_pilot ? r.pilot : r.noisy, r.norm, r.H, r.W, R, item, zt, hs);
+    norm_body<false>(use_pilot ? r.pilot : r.noisy, r.norm, r.H, r.W, R, item, zt, hs);
   });
 }
 

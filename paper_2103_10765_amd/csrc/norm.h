@@ -28,6 +28,9 @@ __host__ __device__ constexpr int norm_items(int H, int W) {
   return ((H + 2 * kNormPad + kNTy - 1) / kNTy) * ((W + 2 * kNormPad + kNTx - 1) / kNTx);
 }
 
+// LOADS_FIRST: every thread's pixel loads are issued before the first is
+// used (one memory round trip for the tile); otherwise one item at a time.
+template <bool LOADS_FIRST>
 __device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img_, double* __restrict__ norm_, int H, int W,
                                           int R, int item, int* zt, double* hs) {
   const auto img = to_global(img_);
@@ -39,17 +42,42 @@ __device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img_, dou
   // table rows and columns lie within one period of the image when it is at
   // least as large as the border plus a tile; else the general modulo
   const bool near = H >= kNormPad + kNTy + 7 && W >= kNormPad + kNTx + 7;
-  for (int i = threadIdx.x; i < ZR * ZC; i += blockDim.x) {
-    const int r = i / ZC, c = i - r * ZC;
-    int y = ty0 + r - kNormPad, x = tx0 + c - kNormPad;
-    if (near) {
-      y += y < 0 ? H : (y >= H ? -H : 0);
-      x += x < 0 ? W : (x >= W ? -W : 0);
-    } else {
-      y = pmod(y, H);
-      x = pmod(x, W);
+  if constexpr (LOADS_FIRST) {
+    constexpr int kZIter = (ZR * ZC + 255) / 256;  // launched with 256 threads
+    int zv[kZIter];
+#pragma unroll
+    for (int it = 0; it < kZIter; ++it) {
+      // (unconditional: threads past the tile's last pixel reload it)
+      const int i = min(static_cast<int>(threadIdx.x) + it * 256, ZR * ZC - 1);
+      const int r = i / ZC, c = i - r * ZC;
+      int y = ty0 + r - kNormPad, x = tx0 + c - kNormPad;
+      if (near) {
+        y += y < 0 ? H : (y >= H ? -H : 0);
+        x += x < 0 ? W : (x >= W ? -W : 0);
+      } else {
+        y = pmod(y, H);
+        x = pmod(x, W);
+      }
+      zv[it] = static_cast<int>(img[static_cast<size_t>(y) * W + x]);
     }
-    zt[i] = static_cast<int>(img[static_cast<size_t>(y) * W + x]) - kZShift;
+#pragma unroll
+    for (int it = 0; it < kZIter; ++it) {
+      const int i = static_cast<int>(threadIdx.x) + it * 256;
+      if (i < ZR * ZC) zt[i] = zv[it] - kZShift;
+    }
+  } else {
+    for (int i = threadIdx.x; i < ZR * ZC; i += blockDim.x) {
+      const int r = i / ZC, c = i - r * ZC;
+      int y = ty0 + r - kNormPad, x = tx0 + c - kNormPad;
+      if (near) {
+        y += y < 0 ? H : (y >= H ? -H : 0);
+        x += x < 0 ? W : (x >= W ? -W : 0);
+      } else {
+        y = pmod(y, H);
+        x = pmod(x, W);
+      }
+      zt[i] = static_cast<int>(img[static_cast<size_t>(y) * W + x]) - kZShift;
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < ZR * kNTx; i += blockDim.x) {

@@ -63,7 +63,9 @@ __host__ __device__ constexpr int stack_items(int H, int W) {
   return ((H + kRowsPerWg - 1) / kRowsPerWg) * ((W + kWave - 1) / kWave);
 }
 
-template <int KIND>
+// LOADS_FIRST: every thread's pixel loads are issued before the first is
+// used (one memory round trip for the tile); otherwise one item at a time.
+template <int KIND, bool LOADS_FIRST>
 __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*stage)[kHalf * kStagePitch],
                                            const uint16_t* __restrict__ img_, float* __restrict__ out_,
                                            unsigned long long* __restrict__ block_weights_, int H, int W, int item) {
@@ -74,10 +76,32 @@ __device__ __forceinline__ void stack_body(float (*pix)[kPixCols + 1], float (*s
   const int y0 = (item / xt) * kRowsPerWg;
   const int x0 = (item % xt) * kWave;
   const float scale = 1.0f / 65535.0f;
-  for (int i = threadIdx.x; i < kPixRows * kPixCols; i += blockDim.x) {
-    const int r = i / kPixCols, c = i - r * kPixCols;
-    const int y = (y0 + r) % H, x = (x0 + c) % W;
-    pix[r][c] = static_cast<float>(img[static_cast<size_t>(y) * W + x]) * scale;
+  constexpr int kPix = kPixRows * kPixCols;
+  if constexpr (LOADS_FIRST) {
+    constexpr int kPixIter = (kPix + kStackThreads - 1) / kStackThreads;
+    unsigned zv[kPixIter];
+#pragma unroll
+    for (int it = 0; it < kPixIter; ++it) {
+      // (unconditional: threads past the tile's last pixel reload it)
+      const int i = min(static_cast<int>(threadIdx.x) + it * kStackThreads, kPix - 1);
+      const int r = i / kPixCols, c = i - r * kPixCols;
+      const int y = (y0 + r) % H, x = (x0 + c) % W;
+      zv[it] = img[static_cast<size_t>(y) * W + x];
+    }
+#pragma unroll
+    for (int it = 0; it < kPixIter; ++it) {
+      const int i = static_cast<int>(threadIdx.x) + it * kStackThreads;
+      if (i < kPix) {
+        const int r = i / kPixCols, c = i - r * kPixCols;
+        pix[r][c] = static_cast<float>(zv[it]) * scale;
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
+      const int r = i / kPixCols, c = i - r * kPixCols;
+      const int y = (y0 + r) % H, x = (x0 + c) % W;
+      pix[r][c] = static_cast<float>(img[static_cast<size_t>(y) * W + x]) * scale;
+    }
   }
   __syncthreads();
 
@@ -136,8 +160,8 @@ __global__ __launch_bounds__(kStackThreads) void stack_kernel(ImgRec one, WorkLi
   const int src = src_sel < 0 ? static_cast<int>(blockIdx.y) : src_sel;
   const int dst = dst_sel < 0 ? static_cast<int>(blockIdx.y) : dst_sel;
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    stack_body<KIND>(pix, stage, src ? r.pilot : r.noisy, dst ? r.stack_b : r.stack_a, dst ? nullptr : r.partials,
-                     r.H, r.W, item);
+    stack_body<KIND, false>(pix, stage, src ? r.pilot : r.noisy, dst ? r.stack_b : r.stack_a,
+                            dst ? nullptr : r.partials, r.H, r.W, item);
   });
 }
 
@@ -147,12 +171,16 @@ __global__ __launch_bounds__(kStackThreads) void stack_kernel(ImgRec one, WorkLi
 // passes share nothing but the launch: the short, latency-bound norm pass
 // runs in the gaps of the write-bound stack items instead of as a launch of
 // its own.
+// Workgroups (all grid rows) up to which a stack launch counts as short:
+// 32 per CU of the 256.
+constexpr int kShortLaunchItems = 32 * 256;
+
 struct StackSmem {
   static constexpr int pix_bytes = (kPixRows * (kPixCols + 1) * 4 + 15) / 16 * 16;
   static constexpr int bytes = pix_bytes + kRowsPerWg * kHalf * kStagePitch * 4;
 };
 
-template <int KIND>
+template <int KIND, bool LOADS_FIRST>
 __global__ __launch_bounds__(kStackThreads) void stack_norm_kernel(ImgRec r, int src_sel, int dst_sel, int R,
                                                                    int norm_src) {
   constexpr int kBytes = StackSmem::bytes > NormSmem::bytes ? StackSmem::bytes : NormSmem::bytes;
@@ -163,7 +191,7 @@ __global__ __launch_bounds__(kStackThreads) void stack_norm_kernel(ImgRec r, int
     if (item >= norm_items(r.H, r.W)) return;
     int* zt = reinterpret_cast<int*>(smem);
     double* hs = reinterpret_cast<double*>(smem + NormSmem::zt_bytes);
-    norm_body(norm_src ? r.pilot : r.noisy, r.norm, r.H, r.W, R, item, zt, hs);
+    norm_body<LOADS_FIRST>(norm_src ? r.pilot : r.noisy, r.norm, r.H, r.W, R, item, zt, hs);
     return;
   }
   if (item >= stack_items(r.H, r.W)) return;
@@ -171,8 +199,8 @@ __global__ __launch_bounds__(kStackThreads) void stack_norm_kernel(ImgRec r, int
   auto stage = reinterpret_cast<float(*)[kHalf * kStagePitch]>(smem + StackSmem::pix_bytes);
   const int src = src_sel < 0 ? static_cast<int>(blockIdx.y) : src_sel;
   const int dst = dst_sel < 0 ? static_cast<int>(blockIdx.y) : dst_sel;
-  stack_body<KIND>(pix, stage, src ? r.pilot : r.noisy, dst ? r.stack_b : r.stack_a, dst ? nullptr : r.partials,
-                   r.H, r.W, item);
+  stack_body<KIND, LOADS_FIRST>(pix, stage, src ? r.pilot : r.noisy, dst ? r.stack_b : r.stack_a,
+                                dst ? nullptr : r.partials, r.H, r.W, item);
 }
 
 }  // namespace
@@ -204,11 +232,27 @@ hipError_t launch_stack_norm(const ImgRec& one, int kind, int src_sel, int dst_s
                              hipStream_t st) {
   if ((src_sel < 0) != (dst_sel < 0)) return hipErrorInvalidValue;
   const unsigned rows = (src_sel < 0 ? 2u : 1u) + 1u;  // stack planes, then the norm items
-  const dim3 grid(static_cast<unsigned>(std::max(stack_items(one.H, one.W), norm_items(one.H, one.W))), rows);
-  if (kind == 0)
-    hipLaunchKernelGGL(stack_norm_kernel<0>, grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R, norm_src);
-  else
-    hipLaunchKernelGGL(stack_norm_kernel<1>, grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R, norm_src);
+  const int items = std::max(stack_items(one.H, one.W), norm_items(one.H, one.W));
+  const dim3 grid(static_cast<unsigned>(items), rows);
+  // A launch of a few workgroups per CU is bound by each workgroup's
+  // latency: there the pixel loads go out all at once (measured: 512^2
+  // faster, 4096^2 slower, where the stack writes bound the launch)
+  const bool short_launch = items * static_cast<int>(rows) <= kShortLaunchItems;
+  if (kind == 0) {
+    if (short_launch)
+      hipLaunchKernelGGL((stack_norm_kernel<0, true>), grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R,
+                         norm_src);
+    else
+      hipLaunchKernelGGL((stack_norm_kernel<0, false>), grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R,
+                         norm_src);
+  } else {
+    if (short_launch)
+      hipLaunchKernelGGL((stack_norm_kernel<1, true>), grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R,
+                         norm_src);
+    else
+      hipLaunchKernelGGL((stack_norm_kernel<1, false>), grid, dim3(kStackThreads), 0, st, one, src_sel, dst_sel, R,
+                         norm_src);
+  }
   return hipGetLastError();
 }
 
