@@ -66,10 +66,11 @@ template <int K, bool HT, bool BATCH, bool WIDE = true>
 struct GroupCfg {
   static constexpr bool two_tiles = HT && K <= 16 && WIDE;
   static constexpr int chunk = two_tiles ? (K > 8 ? 8 : K) : (K > 16 ? 16 : K);
+  static constexpr int rank_bytes = kTPY * kTPX * K * 2;  // the tile's ranks (int16)
   static constexpr int waves =
       two_tiles ? 12
       : Foot::entries * static_cast<int>(sizeof(acc_t)) +
-                      16 * chunk * kBlockFloats * static_cast<int>(sizeof(float)) <=
+                      16 * chunk * kBlockFloats * static_cast<int>(sizeof(float)) + rank_bytes <=
                   kLdsBytes &&
               !(HT && K > 16)
           ? 16
@@ -79,7 +80,7 @@ struct GroupCfg {
   static constexpr int threads = waves * kWave;
   static constexpr int min_waves_per_simd = waves * tiles / 4;
   static_assert(tiles * (Foot::entries * static_cast<int>(sizeof(acc_t)) +
-                         waves * chunk * kBlockFloats * static_cast<int>(sizeof(float))) <=
+                         waves * chunk * kBlockFloats * static_cast<int>(sizeof(float)) + rank_bytes) <=
                     kLdsBytes,
                 "LDS of the tiles sharing a CU");
 };
@@ -235,13 +236,39 @@ __device__ __forceinline__ void flush_acc(const acc_t* acc, const GroupArgs& g, 
   __syncthreads();  // the accumulator is reused by the next item
 }
 
+// The tile's match ranks [reference t][K] into LDS (t = 8 * row + column of
+// the tile's 8 x 8 references; references past the image's last row or
+// column read a clamped in-bounds entry that no group uses), every thread's
+// loads issued before the first is stored: one memory round trip per tile
+// instead of one per group.  The caller's next barrier publishes them.
+template <int K, int THREADS>
+__device__ __forceinline__ void load_ranks(int16_t* ranks, const GroupArgs& g, const int16_t* idx_, int tyi,
+                                           int txi) {
+  const auto idx = to_global(idx_);
+  constexpr int n = kTPY * kTPX * K;
+  constexpr int iters = (n + THREADS - 1) / THREADS;
+  int v[iters];
+#pragma unroll
+  for (int it = 0; it < iters; ++it) {
+    const int e = min(static_cast<int>(threadIdx.x) + it * THREADS, n - 1);
+    const int t = e / K, k = e % K;
+    const int p = min(tyi * kTPY + t / kTPX, g.nRy - 1), q = min(txi * kTPX + t % kTPX, g.nRx - 1);
+    v[it] = idx[(static_cast<size_t>(p) * g.nRx + q) * K + k];
+  }
+#pragma unroll
+  for (int it = 0; it < iters; ++it) {
+    const int e = static_cast<int>(threadIdx.x) + it * THREADS;
+    if (e < n) ranks[e] = static_cast<int16_t>(v[it]);
+  }
+}
+
 // The groups a wave filters in a tile: reference t = wave + j * WAVES,
 // j < kGroups.
 template <int WAVES>
 struct GroupWalk {
   static constexpr int kGroups = (kTPY * kTPX + WAVES - 1) / WAVES;
   const GroupArgs& g;
-  const int16_t* __restrict__ idx;
+  const int16_t* ranks;  // the tile's match ranks in LDS [reference t][K]
   int tyi, txi, wave, lane, fy0, fx0;
 
   __device__ __forceinline__ bool ref_of(int j, int& p, int& q) const {
@@ -250,12 +277,12 @@ struct GroupWalk {
     q = txi * kTPX + t % kTPX;
     return j < kGroups && t < kTPY * kTPX && p < g.nRy && q < g.nRx;
   }
-  // rank of slot `lane` of group j (0 where there is none)
+  // rank of slot `lane` of group j, for lanes below K of a group that exists
+  // (gather reads nothing else)
   template <int K>
   __device__ __forceinline__ int rank(int j) const {
-    int p, q;
-    if (!ref_of(j, p, q) || lane >= K) return 0;
-    return to_global(idx)[(static_cast<size_t>(p) * g.nRx + q) * K + lane];
+    const int t = wave + j * WAVES;
+    return t < kTPY * kTPX ? ranks[t * K + (lane & (K - 1))] : 0;
   }
   // stack rows of group j from its ranks: v[k] = stack[pos_k * 64 + lane];
   // lane k < K returns slot k's pixel index and footprint offset
@@ -366,12 +393,13 @@ __device__ __forceinline__ void for_each_group(const GroupWalk<WAVES>& walk, con
 template <int K, bool BATCH, bool RECOMPUTE, bool WIDE>
 __device__ __forceinline__ void group_ht_body(acc_t* acc,
                                               float (*scratch)[GroupCfg<K, true, BATCH, WIDE>::chunk * kBlockFloats],
-                                              const ImgRec& r, int R, const HtParams& hp, int item) {
+                                              int16_t* ranks, const ImgRec& r, int R, const HtParams& hp, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
   const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = wave_id();
   const int n_acc = g.FY * g.FXP;
+  load_ranks<K, GroupCfg<K, true, BATCH, WIDE>::threads>(ranks, g, r.idx, tyi, txi);
   zero_acc(acc, n_acc);
   const int fy0 = kStep * tyi * kTPY - g.R;
   const int fx0 = kStep * txi * kTPX - g.R;
@@ -382,7 +410,7 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc,
   acc_t* bw = r.partials;  // block-start weights
 
   using Cfg = GroupCfg<K, true, BATCH, WIDE>;
-  const GroupWalk<Cfg::waves> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  const GroupWalk<Cfg::waves> walk{g, ranks, tyi, txi, wave, lane, fy0, fx0};
   const float* const stacks[1] = {r.stack_a};
   auto filter = [&](const float (&cur)[1][K], int fo_v, int pos_v) {
     float v[K];
@@ -462,12 +490,13 @@ __device__ __forceinline__ void group_ht_body(acc_t* acc,
 template <int K, bool BATCH>
 __device__ __forceinline__ void group_wiener_body(acc_t* acc,
                                                   float (*scratch)[GroupCfg<K, false, BATCH>::chunk * kBlockFloats],
-                                                  const ImgRec& r, int R, int item) {
+                                                  int16_t* ranks, const ImgRec& r, int R, int item) {
   const GroupArgs g = make_args(r.H, r.W, R);
   const int tyi = item / g.nTx, txi = item % g.nTx;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = wave_id();
   const int n_acc = g.FY * g.FXP;
+  load_ranks<K, GroupCfg<K, false, BATCH>::threads>(ranks, g, r.idx, tyi, txi);
   zero_acc(acc, n_acc);
   const int fy0 = kStep * tyi * kTPY - g.R;
   const int fx0 = kStep * txi * kTPX - g.R;
@@ -477,7 +506,7 @@ __device__ __forceinline__ void group_wiener_body(acc_t* acc,
   acc_t* bw = r.partials;  // block-start weights
 
   using Cfg = GroupCfg<K, false, BATCH>;
-  const GroupWalk<Cfg::waves> walk{g, r.idx, tyi, txi, wave, lane, fy0, fx0};
+  const GroupWalk<Cfg::waves> walk{g, ranks, tyi, txi, wave, lane, fy0, fx0};
   // the walk gathers the pilot's spectra; the noisy ones are loaded once the
   // gains are known, so the two groups are never in registers together
   const float* const stacks[1] = {r.stack_b};
@@ -537,8 +566,9 @@ __global__ __launch_bounds__((GroupCfg<K, true, BATCH, WIDE>::threads),
   using Cfg = GroupCfg<K, true, BATCH, WIDE>;
   __shared__ acc_t acc[Foot::entries];
   __shared__ float scratch[Cfg::waves][Cfg::chunk * kBlockFloats];
+  __shared__ int16_t ranks[kTPY * kTPX * K];
   for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    group_ht_body<K, BATCH, RECOMPUTE, WIDE>(acc, scratch, r, R, hp, item);
+    group_ht_body<K, BATCH, RECOMPUTE, WIDE>(acc, scratch, ranks, r, R, hp, item);
   });
 }
 
@@ -556,8 +586,10 @@ __global__ __launch_bounds__((GroupCfg<K, false, BATCH>::threads)) void group_wi
   using Cfg = GroupCfg<K, false, BATCH>;
   __shared__ acc_t acc[Foot::entries];
   __shared__ float scratch[Cfg::waves][Cfg::chunk * kBlockFloats];
-  for_each_item<BATCH>(one, wl,
-                       [&](const ImgRec& r, int item) { group_wiener_body<K, BATCH>(acc, scratch, r, R, item); });
+  __shared__ int16_t ranks[kTPY * kTPX * K];
+  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
+    group_wiener_body<K, BATCH>(acc, scratch, ranks, r, R, item);
+  });
 }
 
 // One work item = 256 pixels of one row: the numerator sum of each pixel over
