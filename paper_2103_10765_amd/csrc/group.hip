@@ -614,23 +614,37 @@ __device__ __forceinline__ void reduce_body(acc_t* colsum, const ImgRec& r, int 
   // (H, W >= 8, so a row index wraps at most once; so does a column index
   // when W covers a chunk and its 7-column margin)
   const bool wide = W >= kReduceThreads + 7;
-  for (int c = threadIdx.x; c < kReduceThreads + 7; c += blockDim.x) {
-    int xi = xs - 7 + c;
-    if (wide)
-      xi += xi < 0 ? W : (xi >= W ? -W : 0);
-    else
-      xi = pmod(xi, W);
-    acc_t v[8];
+  constexpr int kCols = kReduceThreads + 7;
+  auto column = [&](int c) {
+    const int xi = xs - 7 + c;
+    return wide ? xi + (xi < 0 ? W : (xi >= W ? -W : 0)) : pmod(xi, W);
+  };
+  auto rows_of = [&](int xi, acc_t (&v)[8]) {
 #pragma unroll
     for (int dy = 0; dy < 8; ++dy) {
       const int yy = y - dy < 0 ? y - dy + H : y - dy;
       v[dy] = bw[static_cast<size_t>(yy) * W + xi];
     }
+  };
+  auto sum8 = [](const acc_t (&v)[8]) {
     acc_t sum = 0;
 #pragma unroll
     for (int dy = 0; dy < 8; ++dy) sum += v[dy];
-    colsum[c] = sum;
+    return sum;
+  };
+  // column c = thread, and the last 7 columns in the first wave, whose two
+  // sets of loads go out together (one round trip for the block)
+  const int c0 = static_cast<int>(threadIdx.x);
+  acc_t v0[8];
+  rows_of(column(c0), v0);
+  if (threadIdx.x < kWave) {
+    const int c1 = min(c0 + kReduceThreads, kCols - 1);
+    acc_t v1[8];
+    rows_of(column(c1), v1);
+    if (c0 + kReduceThreads < kCols) colsum[c1] = sum8(v1);
   }
+  colsum[c0] = sum8(v0);
+  static_assert(kCols - kReduceThreads <= kWave, "the extra columns fit the first wave");
   __syncthreads();
   if (active) {
     acc_t den = 0;
