@@ -16,7 +16,8 @@
 // reference n and candidates (row g, columns 0..3) of the block.  Every pair
 // gets its exact key 2048 (N(a) + N(b) - 512 (256 Phh + Phl + Plh) - 2 Pll) +
 // rank in float64 (all terms integers below 2^50) with no data-dependent
-// branch; keys below the lane's bound go to its candidate buffer.  Norms come
+// branch, held less a constant of its reference (two FMAs on the table
+// entry); keys below the lane's bound go to its candidate buffer.  Norms come
 // from a table written beforehand (norm.h; float64, exact) by bm_norm_kernel
 // or, for a single image, by the stack launch of the same stage.
 //
@@ -231,9 +232,15 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
   // this lane's reference (p0 + u, qt + v): operand rows 2g, 2g + 1, and norm
   i32x4 rh, rl;
   load_operand(hp, lp, R + 3 * u, R + 12 * t + 3 * v, g, rh, rl);
-  // 2048 N of the reference: its table entry less the column term (a tile
-  // right of the last reference column only takes part in the merges)
-  const double nr2048 = qt < nRx ? nref - static_cast<double>((cr + R) & 3) : 0.0;
+  // Keys are held less this lane's reference constant A = 2048 N(a) - F(a)
+  // + R S + R, with F the position term of the norm table (its entry at the
+  // reference is 2048 N(a) + F(a)): a candidate's key is then its table entry
+  // less the correlation terms, and the four quarters and SPLIT waves that
+  // compare or merge keys share the reference, so A is added only to the
+  // final list (a tile right of the last reference column only takes part
+  // in the merges)
+  const int f_ref = (kStep * (p0 + u) + kNormPad) * S + cr;
+  const double key_a = qt < nRx ? nref - static_cast<double>(2 * f_ref - R * S - R) : 0.0;
   // table entries of this lane's result candidates: block (br, bc) row g, columns 0..3
   const auto ncand = norm + static_cast<size_t>(y0 + g + kNormPad) * We + (x0 + 12 * t + kNormPad);
 
@@ -241,7 +248,6 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 #pragma unroll
   for (int i = 0; i < L; ++i) list[i] = kInf;
   double thr = kInf;  // no key at or above it can enter the list
-  const double key_base = nr2048;
   int cnt = 0;
   double* mybuf = buf + wave * kBuf<K> * kWave + lane;
   const int r_center = R * S + R;
@@ -317,8 +323,9 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       const int ey = 4 * br + g - 3 * u;     // dy + R
       const int ex0 = 4 * bc - 3 * v;        // dx + R for i = 0
       const bool row_ok = static_cast<unsigned>(ey) <= static_cast<unsigned>(2 * R);
-      // key = 2048 (N(a) + N(b) - 512 s - 2 Pll) + rank, every term an integer below 2^50
-      const double kb = key_base + static_cast<double>(ey * S + ex0);
+      // key = 2048 (N(a) + N(b) - 512 s - 2 Pll) + rank, held less A: the
+      // table entry 2048 N(b) + F(b) less the correlation terms, every
+      // intermediate an integer below 2^50 in magnitude
       // the reference itself (dy = dx = 0) is candidate ic of this block in at most a few lanes
       const int ic = R - ex0;
       const bool center_here = ey == R && static_cast<unsigned>(ic) < 4u;
@@ -326,9 +333,8 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int s = hh[i] * 256 + cc[i];  // 256 Phh + Phl + Plh, |s| < 2^29
-          const double c = nv[i] + kb;  // 2048 N(b) + i from the table
           const double key =
-              fma(-1048576.0, static_cast<double>(s), fma(-4096.0, static_cast<double>(ll[i]), c));
+              fma(-1048576.0, static_cast<double>(s), fma(-4096.0, static_cast<double>(ll[i]), nv[i]));
           // (bitwise: no short-circuit branches)
           bool ok = row_ok & (static_cast<unsigned>(ex0 + i) <= static_cast<unsigned>(2 * R));
           if constexpr (decltype(check_center)::value) ok = ok & !(center_here & (i == ic));
@@ -454,7 +460,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
     out[0] = static_cast<int16_t>(r_center);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      out[1 + i] = key_rank(list[i]);
+      out[1 + i] = key_rank(list[i] + key_a);
     }
   }
 }

@@ -13,14 +13,15 @@ constexpr int kZShift = 32896;
 __device__ __forceinline__ int norm_pitch(int W) { return W + 2 * kNormPad; }
 
 // ---------------------------------------------------------------------------
-// Norm table: T[ey][ex] = 2048 N + ((ex + R) mod 4), N the sum over the
-// 8 x 8 block at image position ((ey - pad) mod H, (ex - pad) mod W) of
-// (Z - 32896)^2, for ey < H + 2 pad, ex < W + 2 pad (exact: 2048 N < 2^50).
-// The matching kernel's candidate blocks start at table columns
-// congruent to -R mod 4, so (ex + R) mod 4 is the candidate's column in its
-// block, the part of its rank that varies inside a block: the key's
-// candidate term is one load.  Items are 8 x 64 output tiles (small tiles:
-// many workgroups in flight for what is a short, latency-bound pass).
+// Norm table: T[ey][ex] = 2048 N + ey S + ex (S = 2R + 1), N the sum over
+// the 8 x 8 block at image position ((ey - pad) mod H, (ex - pad) mod W) of
+// (Z - 32896)^2, for ey < H + 2 pad, ex < W + 2 pad (exact: 2048 N < 2^47,
+// ey S + ex < 2^23).  A candidate's rank (dy + R) S + (dx + R) is the
+// difference of the position terms of candidate and reference plus a
+// constant, so the matching kernel takes the candidate's whole key term from
+// one load and leaves the reference's to a per-reference constant.  Items
+// are 8 x 64 output tiles (small tiles: many workgroups in flight for what
+// is a short, latency-bound pass).
 // ---------------------------------------------------------------------------
 constexpr int kNTy = 8, kNTx = 64;
 
@@ -37,6 +38,7 @@ __device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img_, dou
   const auto norm = to_global(norm_);
   const int He = H + 2 * kNormPad, We = norm_pitch(W);
   const int tiles_x = (We + kNTx - 1) / kNTx;
+  const int S = 2 * R + 1;
   const int ty0 = (item / tiles_x) * kNTy, tx0 = (item % tiles_x) * kNTx;
   constexpr int ZR = kNTy + 7, ZC = kNTx + 7;
   // table rows and columns lie within one period of the image when it is at
@@ -97,7 +99,7 @@ __device__ __forceinline__ void norm_body(const uint16_t* __restrict__ img_, dou
 #pragma unroll
     for (int a = 0; a < 8; ++a) s += hs[(r + a) * kNTx + c];
     if (ty0 + r < He && tx0 + c < We)
-      norm[static_cast<size_t>(ty0 + r) * We + tx0 + c] = fma(s, 2048.0, static_cast<double>((tx0 + c + R) & 3));
+      norm[static_cast<size_t>(ty0 + r) * We + tx0 + c] = fma(s, 2048.0, static_cast<double>((ty0 + r) * S + tx0 + c));
   }
 }
 
