@@ -26,8 +26,8 @@ int bm_items_for(int H, int W, int split);
 
 // Correlation-form matching (Theorem 1, int8 matrix cores): the same indices.
 // launch_bm_norm writes rec.norm (norm_bytes: the block norms of the noisy or
-// pilot image with a periodic border, times 2048, plus a column term that
-// depends on R) and must precede launch_bm_corr with the same R on the
+// pilot image with a periodic border, times 2048, plus a position term
+// row (2R + 1) + column) and must precede launch_bm_corr with the same R on the
 // stream.  split: waves sharing a 4x4 reference tile (1, 2, 4; 0 = by size).
 hipError_t launch_bm_norm(const ImgRec& one, const WorkList* wl, int R, int use_pilot, int grid_cap,
                           hipStream_t st);
