@@ -53,6 +53,13 @@ template <int K>
 constexpr int kFlushAt = kBuf<K> - 4;  // a block appends at most 4
 constexpr double kInf = __builtin_huge_val();
 
+// an address in LDS, 32 bits wide
+typedef __attribute__((address_space(3))) double lds_double;
+
+// Keeps p in its register as it stands (the compiler would otherwise rebuild
+// it from the buffer base and an offset at every use).
+__device__ __forceinline__ void pin(lds_double*& p) { asm("" : "+v"(p)); }
+
 static_assert(12 * 3 + 4 * kMaxNb + 12 <= kPitch, "plane rows too short");
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
@@ -248,8 +255,13 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
 #pragma unroll
   for (int i = 0; i < L; ++i) list[i] = kInf;
   double thr = kInf;  // no key at or above it can enter the list
-  int cnt = 0;
   double* mybuf = buf + wave * kBuf<K> * kWave + lane;
+  // this lane's next free buffer slot, an LDS address held in a register:
+  // an append is one add and a store, and the compiler branches over the
+  // appends that no lane makes
+  lds_double* const buf0 = (lds_double*)(mybuf);
+  lds_double* wp = buf0;
+  pin(wp);
   const int r_center = R * S + R;
 
   // the two bounds over the 4 SPLIT lists of this reference (a published
@@ -278,8 +290,9 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
     thr = fmin(b1, b2);
   };
   auto flush = [&]() {
-    merge_buffer<L, kBuf<K>>(list, mybuf, kWave, cnt);
-    cnt = 0;
+    merge_buffer<L, kBuf<K>>(list, mybuf, kWave, static_cast<int>(wp - buf0) / kWave);
+    wp = buf0;
+    pin(wp);
     publish();
   };
 
@@ -341,8 +354,9 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
           if constexpr (decltype(warm)::value) {
             keys[i] = ok ? key : kInf;
           } else if (ok & (key < thr)) {
-            mybuf[cnt * kWave] = key;
-            ++cnt;
+            *wp = key;
+            wp += kWave;
+            pin(wp);
           }
         }
       };
@@ -351,7 +365,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
       else
         pairs(std::false_type{});
       if constexpr (!decltype(warm)::value) {
-        if (wave_any(cnt > kFlushAt<K>)) flush();
+        if (wave_any(wp > buf0 + kFlushAt<K> * kWave)) flush();
       }
     };
     // Warm start: the first kWarm blocks of this part give each lane four
@@ -422,7 +436,7 @@ __device__ __forceinline__ void corr_body(unsigned char* smem, const uint16_t* _
     }
     if (steps & 1) step(j, nv0, p0);
   }
-  if (wave_any(cnt > 0)) flush();
+  if (wave_any(wp != buf0)) flush();
 
   // the four quarters of each reference, then the SPLIT waves of the tile
   merge_sorted<L>(list, [&](int j) { return shfl_xor_double(list[j], 16); });
