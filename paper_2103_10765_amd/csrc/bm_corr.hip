@@ -488,16 +488,28 @@ constexpr int kCorrWaves = K == 16 ? 4 : K == 32 ? 3 : 2;
 template <int K, int TPW, int SPLIT, bool BATCH>
 __global__ __launch_bounds__(256, kCorrWaves<K>) void bm_corr_kernel(ImgRec one, WorkList wl, int R, int use_pilot) {
   __shared__ __align__(16) unsigned char smem[CorrSmem<K, TPW, SPLIT>::bytes];
-  for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
-    corr_body<K, TPW, SPLIT>(smem, use_pilot ? r.pilot : r.noisy, r.norm, r.idx, r.H, r.W, R, item);
-  });
+  if constexpr (!BATCH) {
+    // Workgroups go to the eight XCDs in turn (g -> XCD g mod 8): XCD x takes
+    // the x-th eighth of the items, a band of reference rows, so each XCD's
+    // L2 fetches its band's planes and norm-table rows instead of the whole
+    // image.  The grid is 8 q; items past the last exit at once.
+    const int n = corr_items<TPW>(one.H, one.W), q = (n + 7) / 8;
+    const int g = static_cast<int>(blockIdx.x);
+    const int item = (g & 7) * q + (g >> 3);
+    if (item >= n) return;
+    corr_body<K, TPW, SPLIT>(smem, use_pilot ? one.pilot : one.noisy, one.norm, one.idx, one.H, one.W, R, item);
+  } else {
+    for_each_item<BATCH>(one, wl, [&](const ImgRec& r, int item) {
+      corr_body<K, TPW, SPLIT>(smem, use_pilot ? r.pilot : r.noisy, r.norm, r.idx, r.H, r.W, R, item);
+    });
+  }
 }
 
 template <int K, int TPW, int SPLIT>
 hipError_t launch_corr_shape(const ImgRec& one, const WorkList* wl, int R, int use_pilot, int grid_cap,
                              hipStream_t st) {
   if (!wl) {
-    hipLaunchKernelGGL((bm_corr_kernel<K, TPW, SPLIT, false>), dim3(corr_items<TPW>(one.H, one.W)), dim3(256), 0, st,
+    hipLaunchKernelGGL((bm_corr_kernel<K, TPW, SPLIT, false>), dim3(8 * ((corr_items<TPW>(one.H, one.W) + 7) / 8)), dim3(256), 0, st,
                        one, WorkList{}, R, use_pilot);
   } else {
     if (wl->total <= 0) return hipSuccess;
